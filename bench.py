@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Throughput of the segmentation stage on one MI355X.
+
+Workload: synthetic uint16 video 256 x 256 x 10,000 frames (741 fps, 30
+neurons, structured background, Poisson-Gaussian noise; seed 2000), resident
+in HBM before timing. One step = push the whole video through the streaming
+kernel, then finalize (events, region filter, aggregation, components,
+per-component NMF) until the footprints are on the host.
+
+Prints one JSON line (rank 0): frames/s over the timed steps, the roofline of
+the dominant kernel (the streaming summary kernel, timed with HIP events on
+the stream it runs on) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK = 8.0e12          # B/s
+FP64_PEAK = 78.6e12        # FLOP/s, vector FP64 (full-rate FMA)
+SEG_LEN = 50
+# algorithmic units of the streaming kernel (per pixel-frame)
+BYTES_PER_PXF = 2.0 + 8.0 / SEG_LEN        # uint16 input + T and S per segment
+FLOPS_PER_PXF = 2 * 2 * 25                 # separable 25-tap smoothing, 2 passes, FMA = 2
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_video(frames, seed):
+    from synth import preset, simulate
+    cfg = preset(2, frames=frames)
+    t = time.time()
+    video, truth = simulate(cfg, seed)
+    log(f"simulated {video.shape} in {time.time() - t:.1f}s")
+    return video, truth
+
+
+def cpu_baseline(video, sample_frames):
+    """The FP64 oracle (test infrastructure) on the first `sample_frames`
+    frames: full pipeline including the correlation image and NMF."""
+    import oracle
+    sample = video[:sample_frames]
+    t = time.time()
+    oracle.segment(sample)
+    dt = time.time() - t
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([d.get("num_threads", 1) for d in info] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    return dict(value=sample_frames / dt, unit="frames/s", cores=int(cores), kind="oracle",
+                sample=f"first {sample_frames} frames ({sample_frames // SEG_LEN} segments) of the "
+                       f"256x256 video, whole oracle pipeline, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=10000)
+    ap.add_argument("--seed", type=int, default=2000)
+    ap.add_argument("--cpu-sample", type=int, default=500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs the segmentation of a recording "
+              "on a single MI355X (multi-GPU time sharding is designed, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2403_16438_amd import Session, to_device_frames
+    from paper_2403_16438_amd import abi
+
+    video, truth = make_video(args.frames, args.seed)
+    T, H, W = video.shape
+    dev = torch.device("cuda:0")
+    vdev = to_device_frames(video, dev)
+    torch.cuda.synchronize()
+    log("video resident in HBM")
+
+    sess0 = Session(H, W, T, dev)
+    ws = sess0.workspace
+    sess0.close()
+
+    def step():
+        s = Session(H, W, T, dev, workspace=ws)
+        s.push(vdev)
+        s.finalize()
+        return s
+
+    for i in range(args.warmup):
+        step().close()
+        log(f"warmup {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s = step()
+        if i + 1 < args.steps:
+            s.close()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {elapsed:.3f}s")
+    n_fp = s.footprints()["masks"].shape[0]
+    s.close()
+
+    # dominant kernel: the streaming summary kernel, timed with events on the
+    # stream it is launched on (torch's current stream)
+    reps = max(3, args.steps)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts, tf = [], []
+    for _ in range(reps):
+        s = Session(H, W, T, dev, workspace=ws)
+        ev0.record()
+        s.push(vdev)
+        ev1.record()
+        ev1.synchronize()
+        ts.append(ev0.elapsed_time(ev1) * 1e-3)
+        t1 = time.perf_counter()
+        s.finalize()
+        tf.append(time.perf_counter() - t1)
+        s.close()
+    k_time = float(np.mean(ts))
+    pxf = float(T) * H * W
+    achieved_flops = FLOPS_PER_PXF * pxf / k_time
+    achieved_bytes = BYTES_PER_PXF * pxf / k_time
+
+    out = {
+        "metric": "segmented frames/s (256x256x10000 uint16, plain detector)",
+        "value": args.frames * args.steps / elapsed,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16 in, f64 smoothing, f32 summaries",
+        "data": "synthetic (seeded simulator: 30 neurons, Poisson-Gaussian noise)",
+        "config": {"workload": f"{H}x{W}x{T} uint16 video, 741 fps, seed {args.seed}, "
+                               "whole video pushed then finalized",
+                   "frames": T, "height": H, "width": W, "segments": T // SEG_LEN},
+        "roofline": {"bound": "alu", "achieved": achieved_flops / 1e12, "peak": FP64_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved_flops / FP64_PEAK, "traffic": None,
+                     "kernel": "k_block_stats", "kernel_ms": k_time * 1e3,
+                     "algorithmic_flops_per_pixel_frame": FLOPS_PER_PXF},
+        "roofline_hbm": {"achieved": achieved_bytes / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                         "frac": achieved_bytes / HBM_PEAK,
+                         "algorithmic_bytes_per_pixel_frame": BYTES_PER_PXF},
+        "streaming_frames_per_s": T / k_time,
+        "finalize_ms": 1e3 * float(np.mean(tf)),
+        "footprints": n_fp,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(video, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * seg.h - C ABI of the MI355X neuron-segmentation library (libseg.so).
+ *
+ * The library implements the segmentation stage of Bando et al., "Real-time
+ * Neuron Segmentation for Voltage Imaging" (BIBM 2023), Sec. III:
+ *   - the motion-corrected video V(x, t) (Sec. III-B) is cut into
+ *     non-overlapping segments of L = 50 frames;
+ *   - each segment is summarised by the temporal mean S_i (Eq. 1) and the
+ *     max-minus-median image T_i of the Gaussian-smoothed video (Eq. 2);
+ *   - the plain detector normalises T_i by a per-pixel noise scale, detects
+ *     spike events, filters event regions by area, solidity and eccentricity
+ *     and aggregates them over segments (Sec. III-D);
+ *   - each connected component of the aggregate mask is factorised as
+ *     P ~ F A (Eq. 3) into possibly overlapping footprints f_j with
+ *     per-segment activities a_j, whose binarised footprints are the ROI
+ *     masks (Sec. III-D).
+ *
+ * Conventions
+ *   - Every function returns an int status: SEG_OK (0) or a negative SEG_E_*.
+ *     No function throws, aborts or exits.
+ *   - Frames are uint16, row-major [n][height][width], width fastest.
+ *   - "dev" pointers are HIP device pointers; "host" pointers are ordinary
+ *     host memory. `stream` is a hipStream_t (NULL = the default stream).
+ *   - The caller owns the workspace (device memory of seg_workspace_bytes()
+ *     bytes) and every frame buffer. The library never allocates device
+ *     memory, and keeps no global mutable state: sessions are independent.
+ *   - A session is used by one thread at a time.
+ *   - A HIP error inside a session makes it fail permanently (sticky):
+ *     every later call on it returns SEG_E_DEVICE; other sessions are
+ *     unaffected.
+ */
+#ifndef SEG_H
+#define SEG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SEG_OK          0
+#define SEG_E_INVAL    -1  /* NULL pointer, bad configuration or argument     */
+#define SEG_E_SHAPE    -2  /* frame size or buffer size mismatch               */
+#define SEG_E_STATE    -3  /* call not allowed in the session's current state */
+#define SEG_E_CAPACITY -4  /* more frames than max_frames, workspace too small */
+#define SEG_E_DEVICE   -5  /* a HIP call failed (sticky for the session)       */
+#define SEG_E_NOMODEL  -6  /* surrogate detector selected but no model loaded */
+
+/* detectors */
+#define SEG_DET_PLAIN 0
+
+/* image kinds for seg_get_image (all [height][width]) */
+#define SEG_IMG_MEAN        0  /* float: mean of S_i over segments (Eq. 1)         */
+#define SEG_IMG_CORR        1  /* float: 8-neighbour correlation image             */
+#define SEG_IMG_NOISE       2  /* float: per-pixel noise scale sigma(x)            */
+#define SEG_IMG_EVENT_COUNT 3  /* int32: number of segments with an event          */
+#define SEG_IMG_MASK_COUNT  4  /* int32: number of segments whose kept regions
+                                  cover the pixel (n_b)                             */
+#define SEG_IMG_LABELS      5  /* int32: components of the aggregate mask, 0 = none,
+                                  numbered 1..n by minimum raster index            */
+
+/* per-segment map kinds for seg_get_segment_maps (each [K][height][width] float) */
+#define SEG_MAP_S 0            /* spatial summary, Eq. 1                            */
+#define SEG_MAP_T 1            /* temporal summary, Eq. 2                           */
+#define SEG_MAP_P 2            /* detection map p_i = max(0, T_i / sigma - theta)   */
+#define SEG_MAP_B 3            /* kept-region mask b_i as 0.0 / 1.0                 */
+
+typedef struct seg_config {
+  uint32_t height, width;   /* frame size in pixels, >= 1                          */
+  uint32_t seg_len;         /* L; this build supports 50 (Sec. III-B)              */
+  uint32_t max_frames;      /* capacity of one session; sizes the workspace        */
+  float    gauss_sigma;     /* sd of the smoothing Gaussian, 3 px (Sec. III-B)     */
+  uint32_t gauss_radius;    /* taps |k| <= radius, 1..12 (12 = 4 sigma)            */
+  float    event_z;         /* theta: event when T_i / sigma >= theta (5.0)        */
+  uint32_t min_event_segs;  /* c_min: b = [sum_i b_i >= c_min] (2; 1 = the OR)     */
+  uint32_t area_min, area_max;  /* region area bounds in pixels (16, 1600)         */
+  float    solidity_min;    /* area / convex-hull area of pixel squares (0.75)     */
+  float    ecc_max;         /* eccentricity of the pixel-centre covariance (0.95)  */
+  uint32_t nmf_max_rank;    /* SPA rank cap per component, 1..8 (6)                */
+  uint32_t nmf_sweeps;      /* HALS sweeps after the initial A update (200)        */
+  float    spa_delta;       /* SPA stops below delta x the first pick's norm (0.3) */
+  float    footprint_level; /* mask = footprint >= level x its peak (0.25)         */
+  float    sigma_floor;     /* no event where sigma < floor (1e-3)                 */
+  uint32_t detector;        /* SEG_DET_PLAIN                                      */
+} seg_config;
+
+typedef struct seg_session seg_session;   /* opaque */
+
+/* Fill *out with the default configuration for height x width frames and a
+ * capacity of max_frames. Errors: SEG_E_INVAL (NULL out or zero size). */
+int seg_default_config(uint32_t height, uint32_t width, uint32_t max_frames,
+                       seg_config* out);
+
+/* Bytes of device workspace a session with this configuration needs.
+ * Errors: SEG_E_INVAL (NULL or invalid configuration). */
+int seg_workspace_bytes(const seg_config* cfg, size_t* bytes);
+
+/* Create a session on the current HIP device using the caller's workspace
+ * (dev, at least seg_workspace_bytes bytes, 256-byte aligned). The workspace
+ * must stay allocated until seg_destroy. Errors: SEG_E_INVAL,
+ * SEG_E_CAPACITY (workspace too small). */
+int seg_create(const seg_config* cfg, void* dev_workspace, size_t bytes,
+               seg_session** out);
+
+/* Append n_frames frames (dev, [n_frames][height][width] uint16) to the
+ * session, stream-ordered and asynchronous: the caller must not overwrite
+ * the frames until `stream` has passed this call. Frames that do not yet
+ * complete a segment are copied into the workspace and carried to the next
+ * push, so any blocking of the video gives the same result. A trailing
+ * partial segment at finalize is ignored.
+ * Errors: SEG_E_INVAL, SEG_E_STATE (after finalize), SEG_E_CAPACITY
+ * (total frames > max_frames), SEG_E_DEVICE. */
+int seg_push_frames(seg_session* s, const uint16_t* dev_frames,
+                    uint32_t n_frames, void* stream);
+
+/* Run the footprint reconstruction (events, region filter, aggregation,
+ * components, per-component NMF) on everything pushed so far. Blocks until
+ * the results are on the host. Needs at least one complete segment.
+ * Errors: SEG_E_STATE (already finalized or no segment), SEG_E_DEVICE. */
+int seg_finalize(seg_session* s, void* stream);
+
+/* Number of complete segments K pushed so far. */
+int seg_num_segments(const seg_session* s, uint32_t* k);
+
+/* Footprints after seg_finalize, ordered by component then by the raster
+ * index of the footprint peak. *n_out receives the count N; at most
+ * `capacity` footprints are copied. Any output pointer may be NULL.
+ *   weights  host float [capacity][height][width]: f_j scaled to peak 1
+ *   masks    host uint8 [capacity][height][width]: f_j >= footprint_level
+ *   activity host float [capacity][K]: a_j, one value per segment
+ *   component host int32 [capacity]: the component label of each footprint
+ * Errors: SEG_E_STATE (not finalized). */
+int seg_get_footprints(seg_session* s, uint32_t capacity, uint32_t* n_out,
+                       float* weights, uint8_t* masks, float* activity,
+                       int32_t* component);
+
+/* Copy one SEG_IMG_* image ([height][width], float or int32) to host_out.
+ * Every kind needs a finalized session. Errors: SEG_E_INVAL, SEG_E_STATE. */
+int seg_get_image(seg_session* s, int kind, void* host_out);
+
+/* Copy `count` per-segment maps starting at segment `first` of kind SEG_MAP_*
+ * into dev_out ([count][height][width] float, device memory), ordered on
+ * `stream`. S and T are available after the push that completes a segment;
+ * P and B need a finalized session.
+ * Errors: SEG_E_INVAL (range), SEG_E_STATE, SEG_E_DEVICE. */
+int seg_get_segment_maps(seg_session* s, int kind, uint32_t first,
+                         uint32_t count, float* dev_out, void* stream);
+
+/* Load precomputed per-segment summaries instead of pushing frames, then
+ * finalize as usual. For resuming a recording and for checking the
+ * footprint reconstruction on its own. All pointers are host memory:
+ *   T, S, D  float [k][height][width]   Eq. 2, Eq. 1, noise-scale term D_i
+ *   U        float [k][height][width]   sum over the segment of V - R_i
+ *   P        float [5][k][height][width] sums over the segment of
+ *            (V(x) - R_i(x)) (V(y) - R_i(y)) for y = x, x + (0,1), x + (1,0),
+ *            x + (1,1), x + (1,-1), with R_i any per-pixel integer reference
+ * U and P may be NULL (the correlation image is then 0). The session must be
+ * fresh (nothing pushed). Errors: SEG_E_INVAL, SEG_E_STATE, SEG_E_CAPACITY. */
+int seg_load_summaries(seg_session* s, uint32_t k, const float* T,
+                       const float* S, const float* D, const float* U,
+                       const float* P);
+
+/* Release the session (not the caller's workspace). NULL is a no-op. */
+int seg_destroy(seg_session* s);
+
+/* Static description of a status code. */
+const char* seg_strerror(int code);
+
+/* The sticky error of a session (SEG_OK if none). */
+int seg_last_error(const seg_session* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEG_H */

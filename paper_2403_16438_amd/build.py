@@ -1,0 +1,41 @@
+"""Build libseg.so (HIP kernels + C ABI) for gfx950 in the package directory.
+
+    python -m paper_2403_16438_amd.build
+
+Every call compiles from source: the compare-exchange network header is
+regenerated, then hipcc compiles and links all sources into one shared library.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libseg.so")
+SOURCES = ["seg_api.cpp", "k_stream.hip", "k_finalize.hip", "k_nmf.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+
+
+def build(verbose: bool = False) -> str:
+    subprocess.run([sys.executable, os.path.join(CSRC, "gen_selnet.py"),
+                    os.path.join(CSRC, "selnet_gen.h")], check=True,
+                   stdout=None if verbose else subprocess.DEVNULL)
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC] + FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    errs = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
+                     if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + errs)
+    if verbose and errs.strip():
+        print(errs)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,450 @@
+// Footprint-reconstruction kernels before the NMF (Sec. III-D):
+//   pointwise   noise scale sigma(x), mean image (Eq. 1 averaged), pooled
+//               co-moments and the 8-neighbour correlation image
+//   events      z_i = T_i / sigma, e_i = [z_i >= theta], p_i = max(0, z_i - theta),
+//               event count per pixel (a per-pixel loop over segments: no atomics)
+//   regions     8-connected components of every e_i by union-find whose roots
+//               are the minimum pixel index of each component; roots are
+//               compacted into region ids; per region: area, first and second
+//               moments, bounding box (integer atomics, order independent);
+//               the keep decision tests area, eccentricity and solidity (convex
+//               hull of the pixel-square corners, exact integer shoelace)
+//   aggregate   b_i = kept regions, n_b = sum_i b_i, b = [n_b >= c_min],
+//               components of b numbered 1..n by minimum raster index
+#include "seg_internal.h"
+
+// The region decisions repeat the reference arithmetic operation by operation
+// in FP64; no multiply-add contraction anywhere in this file.
+#pragma clang fp contract(off)
+
+namespace seg {
+namespace {
+
+constexpr int BS = 256;        // threads per block
+constexpr int PER = 4;         // elements per thread in the compaction scans
+constexpr int CHUNK = BS * PER;
+
+// Parent reads during the merge go to L2 (relaxed agent-scope atomic loads):
+// other CUs lower parents concurrently and the L1 is not coherent.
+__device__ __forceinline__ int ld_par(int* par, int x) {
+  return __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int uf_find(int* par, int x) {
+  int p = ld_par(par, x);
+  while (p != x) {
+    x = p;
+    p = ld_par(par, x);
+  }
+  return x;
+}
+
+// Union by minimum index: the root of every tree is its smallest element, so
+// after all unions each component's root is its minimum index.
+__device__ void uf_unite(int* par, int a, int b) {
+  while (true) {
+    a = uf_find(par, a);
+    b = uf_find(par, b);
+    if (a == b) return;
+    const int hi = a > b ? a : b;
+    const int lo = a > b ? b : a;
+    const int old = atomicMin(&par[hi], lo);
+    if (old == hi) return;
+    a = old;
+    b = lo;
+  }
+}
+
+// ---------------------------------------------------------------- pointwise
+
+__global__ void k_moments(FinalizeArgs a, double* __restrict__ C) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.M) return;
+  const int yy = x / a.W, xx = x - yy * a.W;
+  const int dy[5] = {0, 0, 1, 1, 1};
+  const int dx[5] = {0, 1, 0, 1, -1};
+  for (int o = 0; o < 5; ++o) {
+    const int ny = yy + dy[o], nx = xx + dx[o];
+    double acc = 0.0;
+    if (a.have_moments && ny < a.H && nx >= 0 && nx < a.W) {
+      const int y = ny * a.W + nx;
+      for (int i = 0; i < a.K; ++i) {
+        const long long b = (long long)i * a.M;
+        acc += (double)a.P[o * a.plane + b + x] -
+               (double)a.U[b + x] * (double)a.U[b + y] / (double)kSegLen;
+      }
+    }
+    C[(long long)o * a.M + x] = acc;
+  }
+}
+
+__global__ void k_pointwise(FinalizeArgs a, const double* __restrict__ C) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.M) return;
+  double sd = 0.0, ss = 0.0;
+  for (int i = 0; i < a.K; ++i) {
+    sd += (double)a.D[(long long)i * a.M + x];
+    ss += (double)a.S[(long long)i * a.M + x];
+  }
+  a.sigma[x] = sqrt(2.0 * 3.14159265358979323846) * sd / (double)a.K;
+  a.mean[x] = (float)(ss / (double)a.K);
+  // correlation image: mean of rho over in-frame 8-neighbours
+  const int yy = x / a.W, xx = x - yy * a.W;
+  const int dy[4] = {0, 1, 1, 1};
+  const int dx[4] = {1, 0, 1, -1};
+  const double vx = C[x];
+  double acc = 0.0;
+  int cnt = 0;
+  for (int o = 0; o < 4; ++o) {
+    for (int sgn = 1; sgn >= -1; sgn -= 2) {
+      const int ny = yy + sgn * dy[o], nx = xx + sgn * dx[o];
+      if (ny < 0 || ny >= a.H || nx < 0 || nx >= a.W) continue;
+      const int y = ny * a.W + nx;
+      const double cov = sgn > 0 ? C[(long long)(o + 1) * a.M + x] : C[(long long)(o + 1) * a.M + y];
+      const double d = vx * C[y];
+      acc += d > 0.0 ? cov / sqrt(d) : 0.0;
+      ++cnt;
+    }
+  }
+  a.corr[x] = cnt ? (float)(acc / cnt) : 0.f;
+}
+
+// ------------------------------------------------------------------- events
+
+__global__ void k_events(FinalizeArgs a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.M) return;
+  const double s = a.sigma[x];
+  const bool ok = s >= a.sigma_floor;
+  int cnt = 0;
+  for (int i = 0; i < a.K; ++i) {
+    const long long g = (long long)i * a.M + x;
+    const double z = ok ? (double)a.T[g] / s : 0.0;
+    const bool e = z >= a.theta;
+    a.p[g] = (float)fmax(0.0, z - a.theta);
+    a.lab[g] = e ? (int)g : -1;
+    cnt += e;
+  }
+  a.count[x] = cnt;
+}
+
+// ------------------------------------------------- connected components
+
+// lab: [n_img][M] with -1 = background, else a parent index (global).
+__global__ void k_ccl_merge(int* __restrict__ lab, int H, int W, long long n) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  if (lab[g] < 0) return;
+  const long long M = (long long)H * W;
+  const int x = (int)(g % M);
+  const int yy = x / W, xx = x - yy * W;
+  // neighbours already visited in raster order: W, NW, N, NE
+  if (xx > 0 && lab[g - 1] >= 0) uf_unite(lab, (int)g, (int)(g - 1));
+  if (yy > 0) {
+    const long long up = g - W;
+    if (xx > 0 && lab[up - 1] >= 0) uf_unite(lab, (int)g, (int)(up - 1));
+    if (lab[up] >= 0) uf_unite(lab, (int)g, (int)up);
+    if (xx + 1 < W && lab[up + 1] >= 0) uf_unite(lab, (int)g, (int)(up + 1));
+  }
+}
+
+__global__ void k_ccl_flatten(int* __restrict__ lab, long long n) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  if (lab[g] < 0) return;
+  lab[g] = uf_find(lab, (int)g);
+}
+
+// ------------------------------------------------------ compaction of roots
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < BS; off <<= 1) {
+    const int add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  const int incl = sh[t];
+  *total = sh[BS - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void k_count_roots(const int* __restrict__ lab, long long n, int* __restrict__ sums) {
+  __shared__ int sh[BS];
+  const long long base = (long long)blockIdx.x * CHUNK + (long long)threadIdx.x * PER;
+  int c = 0;
+  for (int k = 0; k < PER; ++k) {
+    const long long g = base + k;
+    if (g < n && lab[g] == (int)g) ++c;
+  }
+  int total;
+  block_exclusive_scan(c, sh, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// exclusive scan of nb block sums by one block; grand total to *total
+__global__ void k_scan_sums(int* __restrict__ sums, int nb, int* __restrict__ total) {
+  __shared__ int sh[BS];
+  int carry = 0;
+  for (int base = 0; base < nb; base += BS) {
+    const int i = base + threadIdx.x;
+    const int v = i < nb ? sums[i] : 0;
+    int tot;
+    const int ex = block_exclusive_scan(v, sh, &tot);
+    if (i < nb) sums[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+// id[g] = rank of root g among all roots (only written at roots)
+__global__ void k_assign_ids(const int* __restrict__ lab, long long n, const int* __restrict__ sums,
+                             int* __restrict__ id) {
+  __shared__ int sh[BS];
+  const long long base = (long long)blockIdx.x * CHUNK + (long long)threadIdx.x * PER;
+  int flags[PER];
+  int c = 0;
+  for (int k = 0; k < PER; ++k) {
+    const long long g = base + k;
+    flags[k] = (g < n && lab[g] == (int)g);
+    c += flags[k];
+  }
+  int total;
+  int r = block_exclusive_scan(c, sh, &total) + sums[blockIdx.x];
+  for (int k = 0; k < PER; ++k)
+    if (flags[k]) id[base + k] = r++;
+}
+
+// ------------------------------------------------------------ region stats
+
+__global__ void k_region_zero(FinalizeArgs a, int* __restrict__ root) {
+  const int nreg = a.counters[1];
+  for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < nreg;
+       r += (long long)gridDim.x * blockDim.x) {
+    a.reg_area[r] = 0;
+    a.reg_sx[r] = 0;
+    a.reg_sy[r] = 0;
+    a.reg_sxx[r] = 0;
+    a.reg_syy[r] = 0;
+    a.reg_sxy[r] = 0;
+    a.reg_box[4 * r + 0] = 0x7fffffff;
+    a.reg_box[4 * r + 1] = -1;
+    a.reg_box[4 * r + 2] = 0x7fffffff;
+    a.reg_box[4 * r + 3] = -1;
+    a.reg_keep[r] = 0;
+    root[r] = -1;
+  }
+}
+
+__global__ void k_region_accum(FinalizeArgs a, long long n, int* __restrict__ root) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int l = a.lab[g];
+  if (l < 0) return;
+  const int r = a.rid[l];
+  const int x = (int)(g % a.M);
+  const unsigned yy = (unsigned)(x / a.W), xx = (unsigned)(x - (int)yy * a.W);
+  atomicAdd(&a.reg_area[r], 1u);
+  atomicAdd(&a.reg_sx[r], xx);
+  atomicAdd(&a.reg_sy[r], yy);
+  atomicAdd(&a.reg_sxx[r], (unsigned long long)xx * xx);
+  atomicAdd(&a.reg_syy[r], (unsigned long long)yy * yy);
+  atomicAdd(&a.reg_sxy[r], (unsigned long long)xx * yy);
+  atomicMin(&a.reg_box[4 * r + 0], (int)xx);
+  atomicMax(&a.reg_box[4 * r + 1], (int)xx);
+  atomicMin(&a.reg_box[4 * r + 2], (int)yy);
+  atomicMax(&a.reg_box[4 * r + 3], (int)yy);
+  if (l == (int)g) root[r] = l;
+}
+
+constexpr int HULL_ROWS = kMaxDim;
+
+__device__ __forceinline__ long long cross3(int ou, int ov, int au, int av, int bu, int bv) {
+  return (long long)(au - ou) * (bv - ov) - (long long)(av - ov) * (bu - ou);
+}
+
+// One 64-thread block per region (grid-stride). Keep decision per Sec. III-D:
+// area bounds, eccentricity of the pixel-centre covariance, solidity against
+// the convex hull of the pixel-square corners.
+__global__ __launch_bounds__(64) void k_region_decide(FinalizeArgs a, const int* __restrict__ root) {
+  __shared__ int xl[HULL_ROWS], xr[HULL_ROWS];
+  __shared__ int sl[2 * HULL_ROWS + 2], sr[2 * HULL_ROWS + 2];  // packed (u << 16) | v
+  __shared__ int decide;
+  const int nreg = a.counters[1];
+  const int lane = threadIdx.x;
+  for (int r = blockIdx.x; r < nreg; r += gridDim.x) {
+    const long long n = a.reg_area[r];
+    if (lane == 0) {
+      int d = 0;
+      if (n >= a.area_min && n <= a.area_max) {
+        const long long sx = a.reg_sx[r], sy = a.reg_sy[r];
+        const long long A_ = n * (long long)a.reg_sxx[r] - sx * sx;
+        const long long B_ = n * (long long)a.reg_syy[r] - sy * sy;
+        const long long C_ = n * (long long)a.reg_sxy[r] - sx * sy;
+        const double p = (double)(A_ + B_);
+        const double dab = (double)(A_ - B_);
+        const double dc = (double)C_;
+        const double t1 = dab * dab;
+        const double t2 = 4.0 * dc;
+        const double t3 = t2 * dc;
+        const double s = sqrt(t1 + t3);
+        const double ratio = (p + s > 0.0) ? (p - s) / (p + s) : 1.0;
+        d = ratio >= a.ecc_thr ? 1 : 0;
+      }
+      decide = d;
+    }
+    __syncthreads();
+    if (!decide) {
+      __syncthreads();
+      continue;
+    }
+    // per-row extremes of the region inside its bounding box
+    const int x0 = a.reg_box[4 * r + 0], x1 = a.reg_box[4 * r + 1];
+    const int y0 = a.reg_box[4 * r + 2], y1 = a.reg_box[4 * r + 3];
+    const int rt = root[r];
+    const long long img = (long long)(rt / a.M) * a.M;
+    for (int y = y0; y <= y1; ++y) {
+      int mn = 0x7fffffff, mx = -1;
+      for (int x = x0 + lane; x <= x1; x += 64) {
+        if (a.lab[img + (long long)y * a.W + x] == rt) {
+          mn = min(mn, x);
+          mx = max(mx, x);
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        mn = min(mn, __shfl_xor(mn, off));
+        mx = max(mx, __shfl_xor(mx, off));
+      }
+      if (lane == 0) {
+        xl[y - y0] = mn;
+        xr[y - y0] = mx + 1;
+      }
+    }
+    __syncthreads();
+    if (lane == 0) {
+      const int rows = y1 - y0 + 1;
+      // lower chain over the left corner points, upper chain over the right
+      // ones, both in (u = y, v = x) coordinates sorted by (u, v)
+      int nl = 0, nu = 0;
+      auto push_l = [&](int u, int v) {
+        while (nl >= 2 && cross3(sl[nl - 2] >> 16, sl[nl - 2] & 0xffff, sl[nl - 1] >> 16,
+                                 sl[nl - 1] & 0xffff, u, v) <= 0)
+          --nl;
+        sl[nl++] = (u << 16) | v;
+      };
+      push_l(y0, xl[0]);
+      for (int k = 1; k < rows; ++k) {
+        const int lo = min(xl[k - 1], xl[k]), hi = max(xl[k - 1], xl[k]);
+        push_l(y0 + k, lo);
+        push_l(y0 + k, hi);
+      }
+      push_l(y1 + 1, xl[rows - 1]);
+      // upper chain: traverse the right points in reverse (u, v) order
+      auto push_u = [&](int u, int v) {
+        while (nu >= 2 && cross3(sr[nu - 2] >> 16, sr[nu - 2] & 0xffff, sr[nu - 1] >> 16,
+                                 sr[nu - 1] & 0xffff, u, v) <= 0)
+          --nu;
+        sr[nu++] = (u << 16) | v;
+      };
+      push_u(y1 + 1, xr[rows - 1]);
+      for (int k = rows - 1; k >= 1; --k) {
+        const int lo = min(xr[k - 1], xr[k]), hi = max(xr[k - 1], xr[k]);
+        push_u(y0 + k, hi);
+        push_u(y0 + k, lo);
+      }
+      push_u(y0, xr[0]);
+      long long a2 = 0;
+      const int nt = nl + nu;
+      for (int k = 0; k < nt; ++k) {
+        const int k2 = k + 1 == nt ? 0 : k + 1;
+        const int pk = k < nl ? sl[k] : sr[k - nl];
+        const int pm = k2 < nl ? sl[k2] : sr[k2 - nl];
+        const int ku = pk >> 16, kv = pk & 0xffff, mu = pm >> 16, mv = pm & 0xffff;
+        a2 += (long long)ku * mv - (long long)mu * kv;
+      }
+      if (a2 < 0) a2 = -a2;
+      const double sol = a2 ? 2.0 * (double)n / (double)a2 : 1.0;
+      a.reg_keep[r] = sol >= a.solidity_min ? 1 : 0;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------- aggregation
+
+__global__ void k_kept(FinalizeArgs a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.M) return;
+  int nb = 0;
+  for (int i = 0; i < a.K; ++i) {
+    const long long g = (long long)i * a.M + x;
+    const int l = a.lab[g];
+    const int b = l >= 0 ? a.reg_keep[a.rid[l]] : 0;
+    a.bmask[g] = (uint8_t)b;
+    nb += b;
+  }
+  a.nb[x] = nb;
+  a.blab[x] = nb >= a.min_event_segs ? x : -1;
+}
+
+__global__ void k_component_labels(FinalizeArgs a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.M) return;
+  const int l = a.blab[x];
+  a.comp[x] = l >= 0 ? a.rid[l] + 1 : 0;
+}
+
+__global__ void k_u8_to_f32(const uint8_t* __restrict__ in, float* __restrict__ out, long long n) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) out[g] = (float)in[g];
+}
+
+inline unsigned blocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t compact_roots(const int* lab, long long n, int* sums, int scan_cap, int* total,
+                         int* id, hipStream_t st) {
+  const long long nb = (n + CHUNK - 1) / CHUNK;
+  if (nb > scan_cap) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_count_roots, dim3((unsigned)nb), dim3(BS), 0, st, lab, n, sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(BS), 0, st, sums, (int)nb, total);
+  hipLaunchKernelGGL(k_assign_ids, dim3((unsigned)nb), dim3(BS), 0, st, lab, n, sums, id);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_finalize_maps(const FinalizeArgs& a, hipStream_t st) {
+  double* C = a.C;
+  int* root = a.root;
+  const long long KM = (long long)a.K * a.M;
+  hipLaunchKernelGGL(k_moments, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a, C);
+  hipLaunchKernelGGL(k_pointwise, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a, (const double*)C);
+  hipLaunchKernelGGL(k_events, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a);
+  hipLaunchKernelGGL(k_ccl_merge, dim3(blocks(KM, BS)), dim3(BS), 0, st, a.lab, a.H, a.W, KM);
+  hipLaunchKernelGGL(k_ccl_flatten, dim3(blocks(KM, BS)), dim3(BS), 0, st, a.lab, KM);
+  hipError_t e = compact_roots(a.lab, KM, a.scan, a.scan_cap, &a.counters[1], a.rid, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_region_zero, dim3(1024), dim3(BS), 0, st, a, root);
+  hipLaunchKernelGGL(k_region_accum, dim3(blocks(KM, BS)), dim3(BS), 0, st, a, KM, root);
+  hipLaunchKernelGGL(k_region_decide, dim3(4096), dim3(64), 0, st, a, (const int*)root);
+  hipLaunchKernelGGL(k_kept, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a);
+  hipLaunchKernelGGL(k_ccl_merge, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a.blab, a.H, a.W, (long long)a.M);
+  hipLaunchKernelGGL(k_ccl_flatten, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a.blab, (long long)a.M);
+  // component ids reuse the rid array (the per-segment ids are no longer needed)
+  e = compact_roots(a.blab, a.M, a.scan, a.scan_cap, &a.counters[0], a.rid, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_component_labels, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_u8_to_f32(const uint8_t* in, float* out, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_u8_to_f32, dim3(blocks(n, BS)), dim3(BS), 0, st, in, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace seg

@@ -1,0 +1,292 @@
+// Streaming segment-summary kernel: one pass over the uint16 video computes,
+// per 50-frame segment and pixel,
+//   S_i  temporal mean (Eq. 1),
+//   T_i  max minus median over time of the Gaussian-smoothed video (Eq. 2),
+//   D_i  mean of max(0, median - smoothed value) (noise-scale term),
+//   U_i, P_i  sums of reference-subtracted values and of their products with
+//        the right, lower, lower-right and lower-left neighbours (pooled
+//        co-moments of the correlation image).
+//
+// Work decomposition: one workgroup of 256 threads per (64 x 16 pixel tile,
+// segment). Per frame the tile plus a 12-pixel halo (88 x 40) is staged in
+// LDS as d = V - R, where R is a per-pixel integer reference (the median of
+// the segment's first three frames). Subtracting R leaves T, D and the
+// centred co-moments unchanged but keeps the smoothed values small, so the
+// per-pixel window can be held in FP32 without losing the precision the
+// event threshold needs. The separable smoothing accumulates in FP64
+// (full-rate FMA on gfx950): a vertical pass over 88 columns into LDS, then
+// a horizontal pass straight into each thread's window registers. Every
+// thread owns 4 adjacent pixels of one tile row and keeps their 50 smoothed
+// values in VGPRs (40) and a per-thread LDS slot (the chunk being filled);
+// after the segment a compare-exchange network gives the
+// median, the maximum and the 25 smallest values.
+#include "seg_internal.h"
+#include "selnet_gen.h"
+
+namespace seg {
+namespace {
+
+constexpr int L = kSegLen;
+constexpr int RAD = kMaxRadius;
+constexpr int NTAP = 2 * RAD + 1;
+constexpr int TW = 64, TH = 16;
+constexpr int DW = TW + 2 * RAD;     // 88 staged columns
+constexpr int DH = TH + 2 * RAD;     // 40 staged rows
+constexpr int NT = 256;
+constexpr int NPX = 4;               // pixels per thread
+constexpr int CH = 10;               // frames per unrolled chunk
+constexpr int NCH = L / CH;          // 5 chunks per segment
+constexpr int ROWS_PER_WAVE = DH / 4;
+constexpr int XTRA = DW - 64;        // 24 columns loaded by a second lane pass
+constexpr int NV0 = NT;              // first-round vertical tasks
+constexpr int NVT = DW * (TH / 4);   // 352 vertical tasks (column, 4 rows)
+static_assert(L % CH == 0, "chunking");
+static_assert(DH % 4 == 0, "rows per wave");
+static_assert(NVT - NV0 == 4 * XTRA, "second-round vertical tasks: 24 per wave");
+
+struct KParams {
+  const uint16_t* src0;
+  const uint16_t* src1;
+  long long n0;
+  int H, W;
+  int seg0, nseg;
+  float *T, *S, *D, *U, *P;
+  long long plane;
+  double w[NTAP];
+};
+
+__device__ __forceinline__ int reflect(int j, int n) {
+  const int m = 2 * n;
+  j %= m;
+  if (j < 0) j += m;
+  return j >= n ? m - 1 - j : j;
+}
+
+__device__ __forceinline__ int med3i(int a, int b, int c) {
+  return max(min(a, b), min(max(a, b), c));
+}
+
+// Vertical pass for one (column, 4-row) task: U rows 4q..4q+3 of column c.
+__device__ __forceinline__ void vtask(int q, const float* __restrict__ Dl,
+                                      float* __restrict__ Ul, const KParams& p) {
+  const int c = q % DW;
+  const int quad = q / DW;
+  const float* col = Dl + quad * 4 * DW + c;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+  for (int j = 0; j < NTAP + 3; ++j) {
+    const double x = (double)col[j * DW];
+    if (j < NTAP) a0 = fma(p.w[j], x, a0);
+    if (j >= 1 && j < NTAP + 1) a1 = fma(p.w[j - 1], x, a1);
+    if (j >= 2 && j < NTAP + 2) a2 = fma(p.w[j - 2], x, a2);
+    if (j >= 3) a3 = fma(p.w[j - 3], x, a3);
+  }
+  float* o = Ul + quad * 4 * DW + c;
+  o[0] = (float)a0;
+  o[DW] = (float)a1;
+  o[2 * DW] = (float)a2;
+  o[3 * DW] = (float)a3;
+}
+
+__global__ __launch_bounds__(NT, 2) void k_block_stats(KParams p) {
+  __shared__ float Dl[DH * DW];
+  __shared__ float Rl[DH * DW];
+  __shared__ float Ul[TH * DW];
+  __shared__ float4 Wl[CH * NT];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int tiles_x = (p.W + TW - 1) / TW;
+  const int tiles_y = (p.H + TH - 1) / TH;
+  const int ntile = tiles_x * tiles_y;
+  const int nblk = ntile * p.nseg;
+  // Blocks are dealt round-robin over the 8 XCDs; give every XCD a
+  // contiguous range of (segment, tile) pairs so that neighbouring tiles of a
+  // segment share their halo rows in one L2.
+  const int per = (nblk + 7) / 8;
+  const int logical = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (logical >= nblk) return;
+  const int sl = logical / ntile;
+  const int tile = logical - sl * ntile;
+  const int ty0 = (tile / tiles_x) * TH;
+  const int tx0 = (tile % tiles_x) * TW;
+  const long long M = (long long)p.H * p.W;
+
+  // ---- staging geometry: wave wv loads rows wv, wv+4, ...; lane = column
+  const int cx0 = reflect(tx0 - RAD + lane, p.W);
+  const int cx1 = reflect(tx0 - RAD + 64 + (lane < XTRA ? lane : 0), p.W);
+  int rowoff[ROWS_PER_WAVE];
+#pragma unroll
+  for (int k = 0; k < ROWS_PER_WAVE; ++k)
+    rowoff[k] = __builtin_amdgcn_readfirstlane(reflect(ty0 - RAD + wv + 4 * k, p.H) * p.W);
+
+  const long long fbase = (long long)sl * L;
+  auto frame = [&](int t) -> const uint16_t* {
+    const long long f = fbase + t;
+    return f < p.n0 ? p.src0 + f * M : p.src1 + (f - p.n0) * M;
+  };
+
+  // ---- per-pixel reference: median of the segment's first three frames
+  {
+    const uint16_t* f0 = frame(0);
+    const uint16_t* f1 = frame(1);
+    const uint16_t* f2 = frame(2);
+#pragma unroll
+    for (int k = 0; k < ROWS_PER_WAVE; ++k) {
+      const int r = wv + 4 * k;
+      const int o = rowoff[k];
+      Rl[r * DW + lane] = (float)med3i(f0[o + cx0], f1[o + cx0], f2[o + cx0]);
+      if (lane < XTRA)
+        Rl[r * DW + 64 + lane] = (float)med3i(f0[o + cx1], f1[o + cx1], f2[o + cx1]);
+    }
+  }
+  __syncthreads();
+
+  // ---- thread-owned pixels: tile row hy, columns hx0 .. hx0+3
+  const int hy = tid >> 4;
+  const int hx0 = (tid & 15) * NPX;
+  const float* own = Dl + (hy + RAD) * DW + hx0 + RAD;
+
+  // 40 of the 50 window values live in VGPRs (chunks 0..3); the chunk being
+  // filled lives in a per-thread LDS slot, so the frame loop needs no
+  // compile-time frame index. Completed chunks rotate into the registers.
+  float win[NCH - 1][CH][NPX];
+  float Uacc[NPX], Pacc[5][NPX];
+#pragma unroll
+  for (int i = 0; i < NPX; ++i) {
+    Uacc[i] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Pacc[k][i] = 0.f;
+  }
+
+#pragma unroll 1
+  for (int c = 0; c < NCH; ++c) {
+#pragma unroll 1
+    for (int f = 0; f < CH; ++f) {
+      const uint16_t* fr = frame(c * CH + f);
+      // (a) stage d = V - R for the tile and its halo
+#pragma unroll
+      for (int k = 0; k < ROWS_PER_WAVE; ++k) {
+        const int r = wv + 4 * k;
+        const int o = rowoff[k];
+        Dl[r * DW + lane] = (float)fr[o + cx0] - Rl[r * DW + lane];
+        if (lane < XTRA) Dl[r * DW + 64 + lane] = (float)fr[o + cx1] - Rl[r * DW + 64 + lane];
+      }
+      __syncthreads();
+      // (b) co-moment sums of the raw (reference-subtracted) values
+      {
+        float a[NPX + 1], b[NPX + 2];
+#pragma unroll
+        for (int i = 0; i <= NPX; ++i) a[i] = own[i];
+#pragma unroll
+        for (int i = 0; i < NPX + 2; ++i) b[i] = own[DW - 1 + i];
+#pragma unroll
+        for (int i = 0; i < NPX; ++i) {
+          const float d = a[i];
+          Uacc[i] += d;
+          Pacc[0][i] = fmaf(d, d, Pacc[0][i]);
+          Pacc[1][i] = fmaf(d, a[i + 1], Pacc[1][i]);
+          Pacc[2][i] = fmaf(d, b[i + 1], Pacc[2][i]);
+          Pacc[3][i] = fmaf(d, b[i + 2], Pacc[3][i]);
+          Pacc[4][i] = fmaf(d, b[i], Pacc[4][i]);
+        }
+      }
+      // (c) vertical pass into Ul
+      vtask(tid, Dl, Ul, p);
+      if (lane < XTRA) vtask(NV0 + wv * XTRA + lane, Dl, Ul, p);
+      __syncthreads();
+      // (d) horizontal pass into this thread's LDS chunk slot
+      {
+        const float* row = Ul + hy * DW + hx0;
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+#pragma unroll
+        for (int j = 0; j < NTAP + 3; ++j) {
+          const double x = (double)row[j];
+          if (j < NTAP) b0 = fma(p.w[j], x, b0);
+          if (j >= 1 && j < NTAP + 1) b1 = fma(p.w[j - 1], x, b1);
+          if (j >= 2 && j < NTAP + 2) b2 = fma(p.w[j - 2], x, b2);
+          if (j >= 3) b3 = fma(p.w[j - 3], x, b3);
+        }
+        Wl[f * NT + tid] = make_float4((float)b0, (float)b1, (float)b2, (float)b3);
+      }
+    }
+    if (c < NCH - 1) {
+#pragma unroll
+      for (int s = 0; s < NCH - 2; ++s)
+#pragma unroll
+        for (int f = 0; f < CH; ++f)
+#pragma unroll
+          for (int i = 0; i < NPX; ++i) win[s][f][i] = win[s + 1][f][i];
+#pragma unroll
+      for (int f = 0; f < CH; ++f) {
+        const float4 q = Wl[f * NT + tid];
+        win[NCH - 2][f][0] = q.x;
+        win[NCH - 2][f][1] = q.y;
+        win[NCH - 2][f][2] = q.z;
+        win[NCH - 2][f][3] = q.w;
+      }
+    }
+  }
+
+  // ---- per-pixel selection and outputs
+  const int gy = ty0 + hy;
+  const float* rref = Rl + (hy + RAD) * DW + hx0 + RAD;
+  const long long obase = (long long)(p.seg0 + sl) * M + (long long)gy * p.W;
+#pragma unroll
+  for (int i = 0; i < NPX; ++i) {
+    float v[L];
+#pragma unroll
+    for (int s = 0; s < NCH - 1; ++s)
+#pragma unroll
+      for (int f = 0; f < CH; ++f) v[s * CH + f] = win[s][f][i];
+#pragma unroll
+    for (int f = 0; f < CH; ++f) {
+      const float4 q = Wl[f * NT + tid];
+      v[(NCH - 1) * CH + f] = i == 0 ? q.x : i == 1 ? q.y : i == 2 ? q.z : q.w;
+    }
+    SELNET50(v);
+    const double med = 0.5 * ((double)v[SELNET50_LO] + (double)v[SELNET50_HI]);
+    double lo = 0.0;
+#pragma unroll
+    for (int k = 0; k <= SELNET50_LO; ++k) lo += (double)v[k];
+    const double dsum = (double)(L / 2) * med - lo;
+    const int gx = tx0 + hx0 + i;
+    if (gy < p.H && gx < p.W) {
+      const long long o = obase + gx;
+      p.T[o] = (float)((double)v[SELNET50_MAX] - med);
+      p.D[o] = (float)(dsum / (double)L);
+      p.S[o] = (float)(((double)L * (double)rref[i] + (double)Uacc[i]) / (double)L);
+      p.U[o] = Uacc[i];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) p.P[k * p.plane + o] = Pacc[k][i];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_block_stats(const StreamLaunch& a, hipStream_t st) {
+  KParams p;
+  p.src0 = a.src0;
+  p.src1 = a.src1;
+  p.n0 = a.n0;
+  p.H = a.H;
+  p.W = a.W;
+  p.seg0 = a.seg0;
+  p.nseg = a.nseg;
+  p.T = a.T;
+  p.S = a.S;
+  p.D = a.D;
+  p.U = a.U;
+  p.P = a.P;
+  p.plane = a.plane;
+  for (int k = 0; k < NTAP; ++k) p.w[k] = a.w[k];
+  const int tiles = ((a.W + TW - 1) / TW) * ((a.H + TH - 1) / TH);
+  const long long nblk = (long long)tiles * a.nseg;
+  const long long per = (nblk + 7) / 8;
+  hipLaunchKernelGGL(k_block_stats, dim3((unsigned)(per * 8)), dim3(NT), 0, st, p);
+  return hipGetLastError();
+}
+
+}  // namespace seg

@@ -1,0 +1,528 @@
+// Host side of the C ABI declared in include/seg.h: configuration checks,
+// workspace layout, the frame-to-segment bookkeeping of the streaming push,
+// and the orchestration of the finalize kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "seg_internal.h"
+
+using seg::Layout;
+using seg::State;
+
+namespace seg {
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+int check_config(const seg_config* c) {
+  if (!c) return SEG_E_INVAL;
+  if (c->height < 1 || c->width < 1 || c->height > (uint32_t)kMaxDim || c->width > (uint32_t)kMaxDim)
+    return SEG_E_INVAL;
+  if (c->seg_len != (uint32_t)kSegLen) return SEG_E_INVAL;
+  if (c->max_frames < (uint32_t)kSegLen || c->max_frames / kSegLen > (uint32_t)kMaxSegments)
+    return SEG_E_INVAL;
+  const long long M = (long long)c->height * c->width;
+  if ((long long)(c->max_frames / kSegLen) * M >= (1LL << 31)) return SEG_E_INVAL;
+  if (!(c->gauss_sigma > 0.f) || c->gauss_radius < 1 || c->gauss_radius > (uint32_t)kMaxRadius)
+    return SEG_E_INVAL;
+  if (!(c->event_z >= 0.f) || c->min_event_segs < 1) return SEG_E_INVAL;
+  if (c->area_min > c->area_max || c->area_max > 65536) return SEG_E_INVAL;
+  if (!(c->solidity_min >= 0.f && c->solidity_min <= 1.f)) return SEG_E_INVAL;
+  if (!(c->ecc_max >= 0.f && c->ecc_max <= 1.f)) return SEG_E_INVAL;
+  if (c->nmf_max_rank < 1 || c->nmf_max_rank > (uint32_t)kMaxRank) return SEG_E_INVAL;
+  if (!(c->spa_delta >= 0.f) || !(c->footprint_level > 0.f && c->footprint_level <= 1.f))
+    return SEG_E_INVAL;
+  if (!(c->sigma_floor >= 0.f)) return SEG_E_INVAL;
+  if (c->detector != SEG_DET_PLAIN) return SEG_E_INVAL;
+  return SEG_OK;
+}
+
+}  // namespace
+
+Layout make_layout(const seg_config& c) {
+  Layout l{};
+  const size_t M = (size_t)c.height * c.width;
+  const size_t K = c.max_frames / kSegLen;
+  const size_t half = (size_t)((c.height + 1) / 2) * ((c.width + 1) / 2);
+  l.Rcap = K * half;
+  l.Ccap = half;
+  l.scan_cap = (K * M + 1023) / 1024 + 1;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  l.tail = take((size_t)(kSegLen - 1) * M * 2);
+  l.T = take(K * M * 4);
+  l.S = take(K * M * 4);
+  l.D = take(K * M * 4);
+  l.U = take(K * M * 4);
+  l.P = take(5 * K * M * 4);
+  l.sigma = take(M * 8);
+  l.corr = take(M * 4);
+  l.mean = take(M * 4);
+  l.count = take(M * 4);
+  l.p = take(K * M * 4);
+  l.lab = take(K * M * 4);
+  l.rid = take(K * M * 4);
+  l.bmask = take(K * M);
+  l.reg_area = take(l.Rcap * 4);
+  l.reg_sx = take(l.Rcap * 4);
+  l.reg_sy = take(l.Rcap * 4);
+  l.reg_sxx = take(l.Rcap * 8);
+  l.reg_syy = take(l.Rcap * 8);
+  l.reg_sxy = take(l.Rcap * 8);
+  l.reg_box = take(l.Rcap * 16);
+  l.reg_keep = take(l.Rcap);
+  l.reg_root = take(l.Rcap * 4);
+  l.nb = take(M * 4);
+  l.blab = take(M * 4);
+  l.comp = take(M * 4);
+  l.scan = take(l.scan_cap * 4);
+  l.counters = take(16 * 4);
+  l.pix = take(M * 4);
+  l.coff = take((M + 1) * 4);
+  l.nmf_P = take(M * K * 8);
+  l.nmf_PT = take(M * K * 8);
+  l.nmf_R = take(M * K * 8);
+  l.nmf_F = take(M * kMaxRank * 8);
+  l.nmf_G = take(M * kMaxRank * 8);
+  l.nmf_A = take(l.Ccap * kMaxRank * K * 8);
+  l.nmf_W = take(l.Ccap * (kMaxRank + 2) * K * 8);
+  l.nmf_N = take(l.Ccap * 4);
+  l.cmom = take(5 * M * 8);
+  l.total = o;
+  return l;
+}
+
+}  // namespace seg
+
+namespace {
+
+template <class T>
+T* at(seg_session* s, size_t off) {
+  return reinterpret_cast<T*>(s->ws + off);
+}
+
+int fail(seg_session* s, hipError_t e) {
+  if (e == hipSuccess) return SEG_OK;
+  s->error = SEG_E_DEVICE;
+  s->state = State::Failed;
+  return SEG_E_DEVICE;
+}
+
+int enter(seg_session* s) {
+  if (!s) return SEG_E_INVAL;
+  if (s->state == State::Failed) return SEG_E_DEVICE;
+  if (hipSetDevice(s->device) != hipSuccess) return fail(s, hipErrorInvalidDevice);
+  return SEG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int seg_default_config(uint32_t height, uint32_t width, uint32_t max_frames, seg_config* out) {
+  if (!out || height == 0 || width == 0) return SEG_E_INVAL;
+  seg_config c{};
+  c.height = height;
+  c.width = width;
+  c.seg_len = seg::kSegLen;
+  c.max_frames = max_frames;
+  c.gauss_sigma = 3.0f;
+  c.gauss_radius = 12;
+  c.event_z = 5.0f;
+  c.min_event_segs = 2;
+  c.area_min = 16;
+  c.area_max = 1600;
+  c.solidity_min = 0.75f;
+  c.ecc_max = 0.95f;
+  c.nmf_max_rank = 6;
+  c.nmf_sweeps = 200;
+  c.spa_delta = 0.3f;
+  c.footprint_level = 0.25f;
+  c.sigma_floor = 1e-3f;
+  c.detector = SEG_DET_PLAIN;
+  *out = c;
+  return SEG_OK;
+}
+
+int seg_workspace_bytes(const seg_config* cfg, size_t* bytes) {
+  if (!bytes) return SEG_E_INVAL;
+  const int e = seg::check_config(cfg);
+  if (e) return e;
+  *bytes = seg::make_layout(*cfg).total;
+  return SEG_OK;
+}
+
+int seg_create(const seg_config* cfg, void* dev_workspace, size_t bytes, seg_session** out) {
+  if (!out || !dev_workspace) return SEG_E_INVAL;
+  *out = nullptr;
+  const int e = seg::check_config(cfg);
+  if (e) return e;
+  if (reinterpret_cast<uintptr_t>(dev_workspace) & 255) return SEG_E_INVAL;
+  Layout lay = seg::make_layout(*cfg);
+  if (bytes < lay.total) return SEG_E_CAPACITY;
+  seg_session* s = new (std::nothrow) seg_session();
+  if (!s) return SEG_E_INVAL;
+  s->cfg = *cfg;
+  s->lay = lay;
+  s->ws = static_cast<char*>(dev_workspace);
+  s->ws_bytes = bytes;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return SEG_E_DEVICE;
+  }
+  s->M = cfg->height * cfg->width;
+  s->Kmax = cfg->max_frames / seg::kSegLen;
+  s->frames = 0;
+  s->K = 0;
+  s->tail_n = 0;
+  s->state = State::Open;
+  s->error = SEG_OK;
+  s->n_comp = 0;
+  // smoothing taps: exp(-k^2 / (2 sigma^2)) normalised over |k| <= radius
+  const int r = (int)cfg->gauss_radius;
+  const double sg = (double)cfg->gauss_sigma;
+  double sum = 0.0;
+  for (int k = -r; k <= r; ++k) sum += std::exp(-(double)(k * k) / (2.0 * sg * sg));
+  for (int k = -seg::kMaxRadius; k <= seg::kMaxRadius; ++k)
+    s->w[k + seg::kMaxRadius] =
+        (k >= -r && k <= r) ? std::exp(-(double)(k * k) / (2.0 * sg * sg)) / sum : 0.0;
+  *out = s;
+  return SEG_OK;
+}
+
+int seg_push_frames(seg_session* s, const uint16_t* dev_frames, uint32_t n, void* stream) {
+  int e = enter(s);
+  if (e) return e;
+  if (s->state != State::Open) return SEG_E_STATE;
+  if (n == 0) return SEG_OK;
+  if (!dev_frames) return SEG_E_INVAL;
+  if (s->frames + n > s->cfg.max_frames) return SEG_E_CAPACITY;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long M = s->M;
+  const uint32_t total = s->tail_n + n;
+  const uint32_t nseg = total / seg::kSegLen;
+  const uint32_t rem = total - nseg * seg::kSegLen;
+  uint16_t* tail = at<uint16_t>(s, s->lay.tail);
+  if (nseg > 0) {
+    seg::StreamLaunch a{};
+    a.src0 = tail;
+    a.src1 = dev_frames;
+    a.n0 = s->tail_n;
+    a.H = (int)s->cfg.height;
+    a.W = (int)s->cfg.width;
+    a.seg0 = (int)s->K;
+    a.nseg = (int)nseg;
+    a.T = at<float>(s, s->lay.T);
+    a.S = at<float>(s, s->lay.S);
+    a.D = at<float>(s, s->lay.D);
+    a.U = at<float>(s, s->lay.U);
+    a.P = at<float>(s, s->lay.P);
+    a.plane = (long long)s->Kmax * M;
+    a.w = s->w;
+    if ((e = fail(s, seg::launch_block_stats(a, st)))) return e;
+    if (rem) {
+      const uint16_t* from = dev_frames + (size_t)(n - rem) * M;
+      if ((e = fail(s, hipMemcpyAsync(tail, from, (size_t)rem * M * 2, hipMemcpyDeviceToDevice, st))))
+        return e;
+    }
+  } else {
+    if ((e = fail(s, hipMemcpyAsync(tail + (size_t)s->tail_n * M, dev_frames, (size_t)n * M * 2,
+                                    hipMemcpyDeviceToDevice, st))))
+      return e;
+  }
+  s->K += nseg;
+  s->tail_n = rem;
+  s->frames += n;
+  return SEG_OK;
+}
+
+int seg_load_summaries(seg_session* s, uint32_t k, const float* T, const float* S, const float* D,
+                       const float* U, const float* P) {
+  int e = enter(s);
+  if (e) return e;
+  if (s->state != State::Open || s->frames != 0 || s->K != 0) return SEG_E_STATE;
+  if (!T || !S || !D || k == 0) return SEG_E_INVAL;
+  if (k > s->Kmax) return SEG_E_CAPACITY;
+  const size_t n = (size_t)k * s->M * 4;
+  if ((e = fail(s, hipMemcpy(at<float>(s, s->lay.T), T, n, hipMemcpyHostToDevice)))) return e;
+  if ((e = fail(s, hipMemcpy(at<float>(s, s->lay.S), S, n, hipMemcpyHostToDevice)))) return e;
+  if ((e = fail(s, hipMemcpy(at<float>(s, s->lay.D), D, n, hipMemcpyHostToDevice)))) return e;
+  const bool mom = U && P;
+  if (mom) {
+    if ((e = fail(s, hipMemcpy(at<float>(s, s->lay.U), U, n, hipMemcpyHostToDevice)))) return e;
+    for (int o = 0; o < 5; ++o) {
+      float* dst = at<float>(s, s->lay.P) + (size_t)o * s->Kmax * s->M;
+      if ((e = fail(s, hipMemcpy(dst, P + (size_t)o * k * s->M, n, hipMemcpyHostToDevice)))) return e;
+    }
+  } else {
+    // no co-moments: zero sums give a zero correlation image
+    if ((e = fail(s, hipMemset(at<float>(s, s->lay.U), 0, n)))) return e;
+    for (int o = 0; o < 5; ++o)
+      if ((e = fail(s, hipMemset(at<float>(s, s->lay.P) + (size_t)o * s->Kmax * s->M, 0, n)))) return e;
+  }
+  s->K = k;
+  s->frames = (uint64_t)k * seg::kSegLen;
+  return SEG_OK;
+}
+
+int seg_num_segments(const seg_session* s, uint32_t* k) {
+  if (!s || !k) return SEG_E_INVAL;
+  *k = s->K;
+  return SEG_OK;
+}
+
+int seg_finalize(seg_session* s, void* stream) {
+  int e = enter(s);
+  if (e) return e;
+  if (s->state != State::Open || s->K == 0) return SEG_E_STATE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout& l = s->lay;
+  const seg_config& c = s->cfg;
+  seg::FinalizeArgs a{};
+  a.H = (int)c.height;
+  a.W = (int)c.width;
+  a.M = (int)s->M;
+  a.K = (int)s->K;
+  a.Kmax = (int)s->Kmax;
+  a.T = at<float>(s, l.T);
+  a.S = at<float>(s, l.S);
+  a.D = at<float>(s, l.D);
+  a.U = at<float>(s, l.U);
+  a.P = at<float>(s, l.P);
+  a.plane = (long long)s->Kmax * s->M;
+  a.sigma = at<double>(s, l.sigma);
+  a.corr = at<float>(s, l.corr);
+  a.mean = at<float>(s, l.mean);
+  a.count = at<int>(s, l.count);
+  a.p = at<float>(s, l.p);
+  a.lab = at<int>(s, l.lab);
+  a.rid = at<int>(s, l.rid);
+  a.bmask = at<uint8_t>(s, l.bmask);
+  a.reg_area = at<uint32_t>(s, l.reg_area);
+  a.reg_sx = at<uint32_t>(s, l.reg_sx);
+  a.reg_sy = at<uint32_t>(s, l.reg_sy);
+  a.reg_sxx = at<unsigned long long>(s, l.reg_sxx);
+  a.reg_syy = at<unsigned long long>(s, l.reg_syy);
+  a.reg_sxy = at<unsigned long long>(s, l.reg_sxy);
+  a.reg_box = at<int>(s, l.reg_box);
+  a.reg_keep = at<uint8_t>(s, l.reg_keep);
+  a.nb = at<int>(s, l.nb);
+  a.blab = at<int>(s, l.blab);
+  a.comp = at<int>(s, l.comp);
+  a.scan = at<int>(s, l.scan);
+  a.counters = at<int>(s, l.counters);
+  a.Rcap = (long long)l.Rcap;
+  a.scan_cap = (int)l.scan_cap;
+  a.C = at<double>(s, l.cmom);
+  a.root = at<int>(s, l.reg_root);
+  a.theta = (double)c.event_z;
+  a.sigma_floor = (double)c.sigma_floor;
+  a.solidity_min = (double)c.solidity_min;
+  a.ecc_thr = 1.0 - (double)c.ecc_max * (double)c.ecc_max;
+  a.area_min = (int)c.area_min;
+  a.area_max = (int)c.area_max;
+  a.min_event_segs = (int)c.min_event_segs;
+  a.have_moments = true;
+  if ((e = fail(s, seg::launch_finalize_maps(a, st)))) return e;
+  int ncomp = 0;
+  if ((e = fail(s, hipMemcpyAsync(&ncomp, a.counters, sizeof(int), hipMemcpyDeviceToHost, st)))) return e;
+  std::vector<int> comp(s->M);
+  if ((e = fail(s, hipMemcpyAsync(comp.data(), a.comp, (size_t)s->M * 4, hipMemcpyDeviceToHost, st))))
+    return e;
+  if ((e = fail(s, hipStreamSynchronize(st)))) return e;
+  // pixel lists per component in raster order (CSR)
+  std::vector<int> coff(ncomp + 1, 0), pix;
+  for (uint32_t x = 0; x < s->M; ++x)
+    if (comp[x] > 0) ++coff[comp[x]];
+  for (int k = 0; k < ncomp; ++k) coff[k + 1] += coff[k];
+  pix.resize(coff[ncomp]);
+  {
+    std::vector<int> fill(coff.begin(), coff.end() - 1);
+    for (uint32_t x = 0; x < s->M; ++x)
+      if (comp[x] > 0) pix[fill[comp[x] - 1]++] = (int)x;
+  }
+  s->n_comp = (uint32_t)ncomp;
+  s->fps.clear();
+  if (ncomp > 0) {
+    int* dpix = at<int>(s, l.pix);
+    int* dcoff = at<int>(s, l.coff);
+    if ((e = fail(s, hipMemcpyAsync(dpix, pix.data(), pix.size() * 4, hipMemcpyHostToDevice, st)))) return e;
+    if ((e = fail(s, hipMemcpyAsync(dcoff, coff.data(), coff.size() * 4, hipMemcpyHostToDevice, st))))
+      return e;
+    seg::NmfArgs na{};
+    na.M = (int)s->M;
+    na.K = (int)s->K;
+    na.Kmax = (int)s->Kmax;
+    na.ncomp = ncomp;
+    na.p = a.p;
+    na.pix = dpix;
+    na.coff = dcoff;
+    na.P = at<double>(s, l.nmf_P);
+    na.PT = at<double>(s, l.nmf_PT);
+    na.R = at<double>(s, l.nmf_R);
+    na.F = at<double>(s, l.nmf_F);
+    na.A = at<double>(s, l.nmf_A);
+    na.G = at<double>(s, l.nmf_G);
+    na.Wk = at<double>(s, l.nmf_W);
+    na.N = at<int>(s, l.nmf_N);
+    na.max_rank = (int)c.nmf_max_rank;
+    na.sweeps = (int)c.nmf_sweeps;
+    na.delta = (double)c.spa_delta;
+    if ((e = fail(s, seg::launch_nmf(na, st)))) return e;
+    const size_t npx = pix.size();
+    std::vector<int> N(ncomp);
+    std::vector<double> F(npx * seg::kMaxRank), A((size_t)ncomp * seg::kMaxRank * s->Kmax);
+    if ((e = fail(s, hipMemcpyAsync(N.data(), na.N, ncomp * 4, hipMemcpyDeviceToHost, st)))) return e;
+    if ((e = fail(s, hipMemcpyAsync(F.data(), na.F, F.size() * 8, hipMemcpyDeviceToHost, st)))) return e;
+    if ((e = fail(s, hipMemcpyAsync(A.data(), na.A, A.size() * 8, hipMemcpyDeviceToHost, st)))) return e;
+    if ((e = fail(s, hipStreamSynchronize(st)))) return e;
+    const double level = (double)c.footprint_level;
+    for (int k = 0; k < ncomp; ++k) {
+      const int off = coff[k], Mc = coff[k + 1] - coff[k];
+      std::vector<seg::Footprint> items;
+      for (int n = 0; n < N[k]; ++n) {
+        double mx = 0.0;
+        int arg = 0;
+        for (int m = 0; m < Mc; ++m) {
+          const double v = F[(size_t)(off + m) * seg::kMaxRank + n];
+          if (v > mx) {
+            mx = v;
+            arg = m;
+          }
+        }
+        if (mx <= 0.0) continue;
+        uint32_t area = 0;
+        for (int m = 0; m < Mc; ++m) area += F[(size_t)(off + m) * seg::kMaxRank + n] >= level;
+        if (area < c.area_min) continue;
+        seg::Footprint fp;
+        fp.component = k + 1;
+        fp.peak = pix[off + arg];
+        fp.weights.assign(s->M, 0.f);
+        fp.mask.assign(s->M, 0);
+        for (int m = 0; m < Mc; ++m) {
+          const double v = F[(size_t)(off + m) * seg::kMaxRank + n];
+          fp.weights[pix[off + m]] = (float)v;
+          fp.mask[pix[off + m]] = v >= level;
+        }
+        fp.activity.resize(s->K);
+        for (uint32_t i = 0; i < s->K; ++i)
+          fp.activity[i] = (float)A[((size_t)k * seg::kMaxRank + n) * s->Kmax + i];
+        items.push_back(std::move(fp));
+      }
+      std::stable_sort(items.begin(), items.end(),
+                       [](const seg::Footprint& x, const seg::Footprint& y) { return x.peak < y.peak; });
+      for (auto& it : items) s->fps.push_back(std::move(it));
+    }
+  }
+  s->state = State::Finalized;
+  return SEG_OK;
+}
+
+int seg_get_footprints(seg_session* s, uint32_t capacity, uint32_t* n_out, float* weights, uint8_t* masks,
+                       float* activity, int32_t* component) {
+  if (!s) return SEG_E_INVAL;
+  if (s->state == State::Failed) return SEG_E_DEVICE;
+  if (s->state != State::Finalized) return SEG_E_STATE;
+  if (n_out) *n_out = (uint32_t)s->fps.size();
+  const uint32_t n = std::min<uint32_t>(capacity, (uint32_t)s->fps.size());
+  for (uint32_t j = 0; j < n; ++j) {
+    const seg::Footprint& f = s->fps[j];
+    if (weights) std::memcpy(weights + (size_t)j * s->M, f.weights.data(), (size_t)s->M * 4);
+    if (masks) std::memcpy(masks + (size_t)j * s->M, f.mask.data(), s->M);
+    if (activity) std::memcpy(activity + (size_t)j * s->K, f.activity.data(), (size_t)s->K * 4);
+    if (component) component[j] = f.component;
+  }
+  return SEG_OK;
+}
+
+int seg_get_image(seg_session* s, int kind, void* host_out) {
+  int e = enter(s);
+  if (e) return e;
+  if (!host_out) return SEG_E_INVAL;
+  if (s->state != State::Finalized) return SEG_E_STATE;
+  const Layout& l = s->lay;
+  const size_t M = s->M;
+  switch (kind) {
+    case SEG_IMG_MEAN:
+      return fail(s, hipMemcpy(host_out, s->ws + l.mean, M * 4, hipMemcpyDeviceToHost));
+    case SEG_IMG_CORR:
+      return fail(s, hipMemcpy(host_out, s->ws + l.corr, M * 4, hipMemcpyDeviceToHost));
+    case SEG_IMG_NOISE: {
+      std::vector<double> tmp(M);
+      if ((e = fail(s, hipMemcpy(tmp.data(), s->ws + l.sigma, M * 8, hipMemcpyDeviceToHost)))) return e;
+      float* o = static_cast<float*>(host_out);
+      for (size_t x = 0; x < M; ++x) o[x] = (float)tmp[x];
+      return SEG_OK;
+    }
+    case SEG_IMG_EVENT_COUNT:
+      return fail(s, hipMemcpy(host_out, s->ws + l.count, M * 4, hipMemcpyDeviceToHost));
+    case SEG_IMG_MASK_COUNT:
+      return fail(s, hipMemcpy(host_out, s->ws + l.nb, M * 4, hipMemcpyDeviceToHost));
+    case SEG_IMG_LABELS:
+      return fail(s, hipMemcpy(host_out, s->ws + l.comp, M * 4, hipMemcpyDeviceToHost));
+    default:
+      return SEG_E_INVAL;
+  }
+}
+
+int seg_get_segment_maps(seg_session* s, int kind, uint32_t first, uint32_t count, float* dev_out,
+                         void* stream) {
+  int e = enter(s);
+  if (e) return e;
+  if (!dev_out) return SEG_E_INVAL;
+  if ((uint64_t)first + count > s->K) return SEG_E_INVAL;
+  const Layout& l = s->lay;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t M = s->M;
+  size_t base;
+  switch (kind) {
+    case SEG_MAP_S: base = l.S; break;
+    case SEG_MAP_T: base = l.T; break;
+    case SEG_MAP_P:
+      if (s->state != State::Finalized) return SEG_E_STATE;
+      base = l.p;
+      break;
+    case SEG_MAP_B:
+      if (s->state != State::Finalized) return SEG_E_STATE;
+      return fail(s, seg::launch_u8_to_f32(at<uint8_t>(s, l.bmask) + (size_t)first * M, dev_out,
+                                           (long long)count * M, st));
+    default:
+      return SEG_E_INVAL;
+  }
+  return fail(s, hipMemcpyAsync(dev_out, s->ws + base + (size_t)first * M * 4, (size_t)count * M * 4,
+                                hipMemcpyDeviceToDevice, st));
+}
+
+int seg_destroy(seg_session* s) {
+  delete s;
+  return SEG_OK;
+}
+
+const char* seg_strerror(int code) {
+  switch (code) {
+    case SEG_OK: return "ok";
+    case SEG_E_INVAL: return "invalid argument or configuration";
+    case SEG_E_SHAPE: return "shape mismatch";
+    case SEG_E_STATE: return "call not allowed in the session's state";
+    case SEG_E_CAPACITY: return "capacity exceeded";
+    case SEG_E_DEVICE: return "HIP device error";
+    case SEG_E_NOMODEL: return "no model loaded";
+    default: return "unknown status";
+  }
+}
+
+int seg_last_error(const seg_session* s) {
+  if (!s) return SEG_E_INVAL;
+  return s->error;
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// Internal declarations shared by the host library and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "seg.h"
+
+namespace seg {
+
+constexpr int kSegLen = 50;       // L, Sec. III-B
+constexpr int kMaxRadius = 12;    // smoothing taps |k| <= 12
+constexpr int kMaxRank = 8;       // NMF rank cap per component
+constexpr int kMaxDim = 2048;     // frame height / width limit
+constexpr int kMaxSegments = 4096;
+
+// Offsets (bytes) of every array inside the caller's workspace.
+struct Layout {
+  size_t tail;      // u16 [L-1][M]   frames carried to the next push
+  size_t T, S, D, U;  // f32 [Kmax][M] per-segment summaries
+  size_t P;         // f32 [5][Kmax][M] per-segment co-moment sums
+  size_t sigma;     // f64 [M]
+  size_t corr;      // f32 [M]
+  size_t mean;      // f32 [M]
+  size_t count;     // i32 [M] events per pixel
+  size_t p;         // f32 [Kmax][M] detection maps
+  size_t lab;       // i32 [Kmax][M] per-segment event labels (union-find)
+  size_t rid;       // i32 [Kmax][M] region id at each root pixel
+  size_t bmask;     // u8  [Kmax][M] kept-region masks b_i
+  size_t reg_area;  // u32 [Rcap]
+  size_t reg_sx, reg_sy;          // u32 [Rcap]
+  size_t reg_sxx, reg_syy, reg_sxy;  // u64 [Rcap]
+  size_t reg_box;   // i32 [Rcap][4] xmin, xmax, ymin, ymax
+  size_t reg_keep;  // u8  [Rcap]
+  size_t nb;        // i32 [M]
+  size_t blab;      // i32 [M] union-find labels of the aggregate mask
+  size_t comp;      // i32 [M] canonical component labels
+  size_t scan;      // i32 [scan_cap] block sums for compaction scans
+  size_t counters;  // i32 [16]
+  size_t pix;       // i32 [M] component pixel lists (raster order)
+  size_t coff;      // i32 [M + 1] component offsets
+  size_t nmf_P;     // f64 [M][Kmax] gathered P_c (pixel-major)
+  size_t nmf_PT;    // f64 [Kmax][M] gathered P_c (segment-major)
+  size_t nmf_R;     // f64 [M][Kmax] SPA residual
+  size_t nmf_F;     // f64 [M][kMaxRank]
+  size_t nmf_A;     // f64 [Ccap][kMaxRank][Kmax]
+  size_t nmf_N;     // i32 [Ccap] rank per component
+  size_t nmf_G;     // f64 [M][kMaxRank] P A^T and SPA direction
+  size_t nmf_W;     // f64 [Ccap][kMaxRank + 2][Kmax] F^T P, column norms, projections
+  size_t cmom;      // f64 [5][M] pooled co-moments
+  size_t reg_root;  // i32 [Rcap]
+  size_t total;
+  size_t Rcap;      // region capacity
+  size_t Ccap;      // component capacity
+  size_t scan_cap;
+};
+
+Layout make_layout(const seg_config& c);
+
+struct Footprint {
+  int component;
+  int peak;
+  std::vector<float> weights;  // [M]
+  std::vector<uint8_t> mask;   // [M]
+  std::vector<float> activity; // [K]
+};
+
+enum class State { Open, Finalized, Failed };
+
+}  // namespace seg
+
+struct seg_session {
+  seg_config cfg;
+  seg::Layout lay;
+  char* ws;            // device workspace base
+  size_t ws_bytes;
+  int device;
+  uint32_t M;
+  uint32_t Kmax;
+  uint64_t frames;     // frames accepted so far
+  uint32_t K;          // complete segments
+  uint32_t tail_n;     // frames held in the tail buffer
+  seg::State state;
+  int error;           // sticky error
+  double w[2 * seg::kMaxRadius + 1];
+  // results (host copies after finalize)
+  uint32_t n_comp;
+  std::vector<seg::Footprint> fps;
+};
+
+namespace seg {
+
+// ---- kernel launchers (defined in the .hip files) ----
+
+struct StreamLaunch {
+  const uint16_t* src0;  // first n0 frames come from here (the tail buffer)
+  const uint16_t* src1;  // then from here (the caller's frames)
+  long long n0;
+  int H, W;
+  int seg0;       // index of the first segment written
+  int nseg;       // segments in this launch
+  float *T, *S, *D, *U, *P;
+  long long plane;  // Kmax * M, stride between the five P planes
+  const double* w;  // 2 * kMaxRadius + 1 taps (zero beyond the radius)
+};
+hipError_t launch_block_stats(const StreamLaunch& a, hipStream_t st);
+
+struct FinalizeArgs {
+  int H, W, M, K, Kmax;
+  const float *T, *S, *D, *U, *P;
+  long long plane;
+  double* sigma;
+  float* corr;
+  float* mean;
+  int* count;
+  float* p;
+  int* lab;
+  int* rid;
+  uint8_t* bmask;
+  uint32_t *reg_area, *reg_sx, *reg_sy;
+  unsigned long long *reg_sxx, *reg_syy, *reg_sxy;
+  int* reg_box;
+  uint8_t* reg_keep;
+  int* nb;
+  int* blab;
+  int* comp;
+  int* scan;
+  int* counters;
+  long long Rcap;
+  int scan_cap;
+  double* C;       // f64 [5][M] pooled co-moments
+  int* root;       // i32 [Rcap] root pixel of each region
+  double theta, sigma_floor, solidity_min, ecc_thr;
+  int area_min, area_max, min_event_segs;
+  bool have_moments;
+};
+// pointwise images, events, per-segment regions, kept masks, aggregate,
+// canonical components; writes the component count to counters[0]
+hipError_t launch_finalize_maps(const FinalizeArgs& a, hipStream_t st);
+hipError_t launch_u8_to_f32(const uint8_t* in, float* out, long long n, hipStream_t st);
+
+struct NmfArgs {
+  int M, K, Kmax, ncomp;
+  const float* p;
+  const int* pix;
+  const int* coff;
+  double *P, *PT, *R, *F, *A, *G, *Wk;
+  int* N;
+  int max_rank, sweeps;
+  double delta;
+};
+hipError_t launch_nmf(const NmfArgs& a, hipStream_t st);
+
+}  // namespace seg

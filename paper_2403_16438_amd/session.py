@@ -1,0 +1,111 @@
+"""Session: a recording being segmented on one GPU.
+
+PyTorch provides the device memory (the workspace and frame buffers) and the
+stream; every step of the segmentation runs in libseg.so through `abi`.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import abi
+
+
+def to_device_frames(video: np.ndarray, device="cuda") -> torch.Tensor:
+    """uint16 [n, H, W] host array -> contiguous device tensor holding the
+    same bytes (int16 view: torch has no full uint16 support)."""
+    v = np.ascontiguousarray(video, dtype=np.uint16)
+    return torch.from_numpy(v.view(np.int16)).to(device)
+
+
+class Session:
+    def __init__(self, height: int, width: int, max_frames: int, device=None,
+                 workspace: torch.Tensor | None = None, **overrides):
+        self.device = torch.device(device or "cuda")
+        if self.device.type != "cuda":
+            raise ValueError("Session needs a GPU device")
+        self.cfg = abi.seg_default_config(height, width, max_frames)
+        for k, v in overrides.items():
+            if not hasattr(self.cfg, k):
+                raise KeyError(k)
+            setattr(self.cfg, k, v)
+        self.nbytes = abi.seg_workspace_bytes(self.cfg)
+        with torch.cuda.device(self.device):
+            if workspace is not None and workspace.numel() >= self.nbytes + 256:
+                self.workspace = workspace
+            else:
+                self.workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) & ~255
+            self.handle = abi.seg_create(self.cfg, aligned, self.nbytes)
+        self.H, self.W = height, width
+
+    # -- streaming
+    def push(self, frames: torch.Tensor, stream: torch.cuda.Stream | None = None) -> None:
+        if frames.device != self.device or not frames.is_contiguous():
+            raise ValueError("frames must be a contiguous tensor on the session's device")
+        if frames.dtype not in (torch.int16, torch.uint16) or tuple(frames.shape[1:]) != (self.H, self.W):
+            raise ValueError("frames must be 16-bit [n, H, W]")
+        st = (stream or torch.cuda.current_stream(self.device)).cuda_stream
+        abi.seg_push_frames(self.handle, frames.data_ptr(), frames.shape[0], st)
+
+    def finalize(self, stream: torch.cuda.Stream | None = None) -> None:
+        st = (stream or torch.cuda.current_stream(self.device)).cuda_stream
+        abi.seg_finalize(self.handle, st)
+
+    @property
+    def num_segments(self) -> int:
+        return abi.seg_num_segments(self.handle)
+
+    # -- results
+    def footprints(self) -> dict:
+        n = abi.seg_get_footprints(self.handle, 0, None, None, None, None)
+        K = self.num_segments
+        w = np.zeros((n, self.H, self.W), np.float32)
+        m = np.zeros((n, self.H, self.W), np.uint8)
+        a = np.zeros((n, K), np.float32)
+        c = np.zeros(n, np.int32)
+        abi.seg_get_footprints(self.handle, n, w, m, a, c)
+        return dict(weights=w, masks=m.astype(bool), activity=a, component=c)
+
+    def image(self, kind: int) -> np.ndarray:
+        dt = np.float32 if kind in (abi.SEG_IMG_MEAN, abi.SEG_IMG_CORR, abi.SEG_IMG_NOISE) else np.int32
+        out = np.zeros((self.H, self.W), dt)
+        abi.seg_get_image(self.handle, kind, out)
+        return out
+
+    def segment_maps(self, kind: int, first: int = 0, count: int | None = None) -> torch.Tensor:
+        count = self.num_segments - first if count is None else count
+        out = torch.empty((count, self.H, self.W), dtype=torch.float32, device=self.device)
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        abi.seg_get_segment_maps(self.handle, kind, first, count, out.data_ptr(), st)
+        return out
+
+    def load_summaries(self, T, S, D, U=None, P=None) -> None:
+        f = lambda a: None if a is None else np.ascontiguousarray(a, np.float32)
+        T = f(T)
+        abi.seg_load_summaries(self.handle, T.shape[0], T, f(S), f(D), f(U), f(P))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            abi.seg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def segment_video(video: np.ndarray, block: int | None = None, **overrides) -> Session:
+    """Push a host uint16 video [T, H, W] (in blocks of `block` frames) and
+    finalize. Returns the finalized session."""
+    T, H, W = video.shape
+    s = Session(H, W, max(T, 50), **overrides)
+    block = block or T
+    for t0 in range(0, T, block):
+        s.push(to_device_frames(video[t0:t0 + block], s.device))
+    s.finalize()
+    torch.cuda.synchronize(s.device)
+    return s

@@ -2,8 +2,15 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-if ROOT not in sys.path:
-    sys.path.insert(0, ROOT)
+HERE = os.path.dirname(os.path.abspath(__file__))
+for p in (ROOT, HERE):
+    if p not in sys.path:
+        sys.path.insert(0, p)
+
+# Tests load the library that is built; they build it only when none exists.
+if not os.path.exists(os.path.join(ROOT, "paper_2403_16438_amd", "libseg.so")):
+    from paper_2403_16438_amd.build import build
+    build()
 
 
 def pytest_configure(config):
