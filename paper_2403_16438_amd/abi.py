@@ -50,6 +50,10 @@ class SegError(RuntimeError):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime (same soname as /opt/rocm's). Loading
+    # torch first makes libseg.so bind to that runtime, so the process holds a
+    # single HIP runtime and torch's device memory and streams are valid here.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2403_16438_amd.build`")

@@ -1,47 +1,111 @@
-// Per-component NMF P_c ~ F A (Eq. 3, Sec. III-D), FP64, one workgroup per
-// component of the aggregate mask.
-//   gather  P_c[m][i] = p_i(x_m) for the component's pixels x_m (raster order)
-//   SPA     successive projection on the nonzero columns: pick the column of
-//           largest residual norm (lowest index on ties), stop below delta x
-//           the first pick's norm or at the rank cap, project the residual
-//           onto the complement of the picked direction
+// Per-component NMF P_c ~ F A (Eq. 3, Sec. III-D), FP64 arithmetic, one
+// workgroup of 512 threads per component of the aggregate mask.
+//   gather  P_c[m][i] = p_i(x_m) for the component's pixels x_m (raster
+//           order), stored twice in FP32 (exact: the maps are FP32): pixel-
+//           major for column sweeps and segment-major for pixel sweeps
+//   SPA     successive projection on the nonzero columns (FP64 residual):
+//           pick the column of largest residual norm (lowest index on ties),
+//           stop below delta x the first pick's norm or at the rank cap,
+//           project the residual onto the complement of the picked direction
 //   init    F = picked columns scaled to max 1, A = 0, one HALS update of A
 //   HALS    `sweeps` times: rows of A in order, then columns of F in order,
-//           each clipped at 0; a row/column with zero Gram diagonal is kept
+//           each clipped at 0; a row/column with zero Gram diagonal is kept.
+//           The A update is independent per column and the F update per
+//           pixel, so a thread owns a column (a pixel), keeps it in
+//           registers through the sequential row (column) updates, and only
+//           the N x N Gram matrices F^T F and A A^T need block reductions.
 //   scale   each f_n to max 1, a_n inversely
-// Reductions run in a fixed order per thread, so results are deterministic.
+// Every reduction has a fixed order, so results are bit-reproducible.
 #include "seg_internal.h"
 
 namespace seg {
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 512;
+constexpr int NW = NT / 64;
 constexpr int R8 = kMaxRank;
+constexpr int NPAIR = R8 * (R8 + 1) / 2;
 
-__device__ void block_argmax(double v, int idx, double* sv, int* si, double* best, int* bidx) {
-  const int t = threadIdx.x;
-  sv[t] = v;
-  si[t] = idx;
-  __syncthreads();
-  for (int off = NT / 2; off > 0; off >>= 1) {
-    if (t < off) {
-      const double a = sv[t], b = sv[t + off];
-      const int ia = si[t], ib = si[t + off];
-      if (b > a || (b == a && ib < ia)) {
-        sv[t] = b;
-        si[t] = ib;
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Block-wide sums of the N(N+1)/2 pair values each thread holds in s[];
+// result symmetric in gram[n1 * R8 + n2]. Fixed reduction order.
+__device__ void block_gram(double (&s)[NPAIR], int N, double* red, double* gram) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int k = 0;
+#pragma unroll
+  for (int n1 = 0; n1 < R8; ++n1)
+#pragma unroll
+    for (int n2 = n1; n2 < R8; ++n2, ++k) {
+      if (n2 < N) {
+        const double v = wave_sum(s[k]);
+        if (lane == 0) red[w * NPAIR + k] = v;
       }
     }
-    __syncthreads();
+  __syncthreads();
+  if (threadIdx.x < NPAIR) {
+    const int kk = threadIdx.x;
+    int n1 = 0, rem = kk;
+    while (rem >= R8 - n1) {
+      rem -= R8 - n1;
+      ++n1;
+    }
+    const int n2 = n1 + rem;
+    if (n2 < N) {
+      double v = 0.0;
+      for (int ww = 0; ww < NW; ++ww) v += red[ww * NPAIR + kk];
+      gram[n1 * R8 + n2] = v;
+      gram[n2 * R8 + n1] = v;
+    }
   }
-  *best = sv[0];
-  *bidx = si[0];
+  __syncthreads();
+}
+
+__device__ double block_max(double v, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double m = red[0];
+  for (int ww = 1; ww < NW; ++ww) m = fmax(m, red[ww]);
+  __syncthreads();
+  return m;
+}
+
+// argmax with lowest index on ties
+__device__ void block_argmax(double v, int idx, double* red, int* redi, double* best, int* bidx) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off);
+    const int oi = __shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+  if (lane == 0) {
+    red[w] = v;
+    redi[w] = idx;
+  }
+  __syncthreads();
+  double b = red[0];
+  int bi = redi[0];
+  for (int ww = 1; ww < NW; ++ww)
+    if (red[ww] > b || (red[ww] == b && redi[ww] < bi)) {
+      b = red[ww];
+      bi = redi[ww];
+    }
+  *best = b;
+  *bidx = bi;
   __syncthreads();
 }
 
 __global__ __launch_bounds__(NT) void k_nmf(NmfArgs a) {
-  __shared__ double sv[NT];
-  __shared__ int si[NT];
+  __shared__ double red[NW * NPAIR];
+  __shared__ int redi[NW];
   __shared__ double gram[R8 * R8];
   __shared__ int picks[R8];
   const int c = blockIdx.x;
@@ -49,46 +113,52 @@ __global__ __launch_bounds__(NT) void k_nmf(NmfArgs a) {
   const int off = a.coff[c];
   const int Mc = a.coff[c + 1] - off;
   const int K = a.K;
-  double* P = a.P + (long long)off * K;     // [Mc][K]
-  double* PT = a.PT + (long long)off * K;   // [K][Mc]
-  double* R = a.R + (long long)off * K;     // [Mc][K]
-  double* F = a.F + (long long)off * R8;    // [Mc][R8]
-  double* G = a.G + (long long)off * R8;    // [Mc][R8]
-  double* A = a.A + (long long)c * R8 * a.Kmax;          // [R8][K]
-  double* FtP = a.Wk + (long long)c * (R8 + 2) * a.Kmax; // [R8][K]
-  double* nrm = FtP + (long long)R8 * a.Kmax;           // [K]
-  double* prj = nrm + a.Kmax;                            // [K]
+  float* P = reinterpret_cast<float*>(a.P) + (long long)off * K;    // [Mc][K]
+  float* PT = reinterpret_cast<float*>(a.PT) + (long long)off * K;  // [K][Mc]
+  double* R = a.R + (long long)off * K;                              // [Mc][K]
+  double* F = a.F + (long long)off * R8;                             // [Mc][R8]
+  double* U = a.G + (long long)off * R8;                             // SPA direction
+  double* A = a.A + (long long)c * R8 * a.Kmax;                      // [R8][Kmax]
+  double* nz = a.Wk + (long long)c * (R8 + 2) * a.Kmax;              // [K] flags
+  double* prj = nz + a.Kmax;                                         // [K]
 
-  // gather
   for (long long e = t; e < (long long)Mc * K; e += NT) {
     const int m = (int)(e / K), i = (int)(e - (long long)m * K);
-    const double v = (double)a.p[(long long)i * a.M + a.pix[off + m]];
+    const float v = a.p[(long long)i * a.M + a.pix[off + m]];
     P[e] = v;
-    R[e] = v;
     PT[(long long)i * Mc + m] = v;
+    R[e] = (double)v;
   }
   __syncthreads();
 
-  // SPA on the nonzero columns
-  int N = 0;
-  double ref = 0.0;
+  // ---------------------------------------------------------------- SPA
   for (int i = t; i < K; i += NT) {
-    double s = 0.0;
-    for (int m = 0; m < Mc; ++m) s += fabs(P[(long long)m * K + i]);
-    prj[i] = s > 0.0 ? 1.0 : 0.0;   // nonzero-column flag until the first projection
+    float s = 0.f;
+    for (int m = 0; m < Mc; ++m) s = fmaxf(s, P[(long long)m * K + i]);
+    nz[i] = s > 0.f ? 1.0 : 0.0;
   }
   __syncthreads();
+  int N = 0;
+  double ref = 0.0;
   while (N < a.max_rank) {
     double bv = -1.0;
     int bi = 0x7fffffff;
     for (int i = t; i < K; i += NT) {
-      double s = 0.0;
-      for (int m = 0; m < Mc; ++m) {
-        const double r = R[(long long)m * K + i];
-        s += r * r;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int m = 0;
+      for (; m + 4 <= Mc; m += 4) {
+        const double r0 = R[(long long)m * K + i], r1 = R[(long long)(m + 1) * K + i];
+        const double r2 = R[(long long)(m + 2) * K + i], r3 = R[(long long)(m + 3) * K + i];
+        s0 += r0 * r0;
+        s1 += r1 * r1;
+        s2 += r2 * r2;
+        s3 += r3 * r3;
       }
-      const double nv = prj[i] > 0.0 ? sqrt(s) : -1.0;
-      nrm[i] = nv;
+      for (; m < Mc; ++m) {
+        const double r = R[(long long)m * K + i];
+        s0 += r * r;
+      }
+      const double nv = nz[i] > 0.0 ? sqrt((s0 + s1) + (s2 + s3)) : -1.0;
       if (nv > bv) {
         bv = nv;
         bi = i;
@@ -96,125 +166,155 @@ __global__ __launch_bounds__(NT) void k_nmf(NmfArgs a) {
     }
     double best;
     int j;
-    block_argmax(bv, bi, sv, si, &best, &j);
+    block_argmax(bv, bi, red, redi, &best, &j);
     if (best <= 0.0) break;
     if (N == 0) ref = best;
     else if (best < a.delta * ref) break;
     if (t == 0) picks[N] = j;
     ++N;
-    // u = R[:, j] / ||R[:, j]||, coefficients v_i = u . R[:, i], R -= u v^T
-    for (int m = t; m < Mc; m += NT) G[(long long)m * R8] = R[(long long)m * K + j] / best;
+    for (int m = t; m < Mc; m += NT) U[(long long)m * R8] = R[(long long)m * K + j] / best;
     __syncthreads();
     for (int i = t; i < K; i += NT) {
-      double s = 0.0;
-      for (int m = 0; m < Mc; ++m) s += G[(long long)m * R8] * R[(long long)m * K + i];
-      nrm[i] = s;
+      double s0 = 0.0, s1 = 0.0;
+      int m = 0;
+      for (; m + 2 <= Mc; m += 2) {
+        s0 += U[(long long)m * R8] * R[(long long)m * K + i];
+        s1 += U[(long long)(m + 1) * R8] * R[(long long)(m + 1) * K + i];
+      }
+      if (m < Mc) s0 += U[(long long)m * R8] * R[(long long)m * K + i];
+      prj[i] = s0 + s1;
     }
     __syncthreads();
     for (long long e = t; e < (long long)Mc * K; e += NT) {
       const int m = (int)(e / K), i = (int)(e - (long long)m * K);
-      R[e] -= G[(long long)m * R8] * nrm[i];
+      R[e] -= U[(long long)m * R8] * prj[i];
     }
     __syncthreads();
   }
   __syncthreads();
 
-  // initial footprints: picked raw columns scaled to max 1
+  // ------------------------------------------------- initial footprints
   for (int n = 0; n < N; ++n) {
+    const int col = picks[n];
     double mx = 0.0;
-    for (int m = t; m < Mc; m += NT) {
-      const double v = P[(long long)m * K + picks[n]];
-      F[(long long)m * R8 + n] = v;
-      mx = fmax(mx, v);
-    }
-    double best;
-    int dummy;
-    block_argmax(mx, 0, sv, si, &best, &dummy);
-    for (int m = t; m < Mc; m += NT) F[(long long)m * R8 + n] /= best;
+    for (int m = t; m < Mc; m += NT) mx = fmax(mx, (double)P[(long long)m * K + col]);
+    const double best = block_max(mx, red);
+    for (int m = t; m < Mc; m += NT) F[(long long)m * R8 + n] = (double)P[(long long)m * K + col] / best;
   }
-  for (int n = 0; n < N; ++n)
-    for (int i = t; i < K; i += NT) A[(long long)n * a.Kmax + i] = 0.0;
+  for (int i = t; i < K; i += NT)
+    for (int n = 0; n < R8; ++n) A[(long long)n * a.Kmax + i] = 0.0;
   __syncthreads();
 
   for (int sweep = -1; sweep < a.sweeps; ++sweep) {
-    // ---- A update: FtP = F^T P, FtF = F^T F
+    // ---- A update. Gram F^T F:
+    {
+      double s[NPAIR];
+#pragma unroll
+      for (int k = 0; k < NPAIR; ++k) s[k] = 0.0;
+      for (int m = t; m < Mc; m += NT) {
+        double f[R8];
+#pragma unroll
+        for (int n = 0; n < R8; ++n) f[n] = n < N ? F[(long long)m * R8 + n] : 0.0;
+        int k = 0;
+#pragma unroll
+        for (int n1 = 0; n1 < R8; ++n1)
+#pragma unroll
+          for (int n2 = n1; n2 < R8; ++n2, ++k) s[k] += f[n1] * f[n2];
+      }
+      block_gram(s, N, red, gram);
+    }
+    // per column i: F^T P[:, i], then the rows of A in order
     for (int i = t; i < K; i += NT) {
-      double s[R8];
+      double fp[R8];
 #pragma unroll
-      for (int n = 0; n < R8; ++n) s[n] = 0.0;
+      for (int n = 0; n < R8; ++n) fp[n] = 0.0;
+#pragma unroll 4
       for (int m = 0; m < Mc; ++m) {
-        const double pv = P[(long long)m * K + i];
+        const double pv = (double)P[(long long)m * K + i];
+        const double* fm = F + (long long)m * R8;
 #pragma unroll
         for (int n = 0; n < R8; ++n)
-          if (n < N) s[n] += F[(long long)m * R8 + n] * pv;
+          if (n < N) fp[n] += fm[n] * pv;
+      }
+      double av[R8];
+#pragma unroll
+      for (int n = 0; n < R8; ++n) av[n] = n < N ? A[(long long)n * a.Kmax + i] : 0.0;
+#pragma unroll
+      for (int n = 0; n < R8; ++n) {
+        if (n < N) {
+          const double d = gram[n * R8 + n];
+          if (d > 0.0) {
+            double s = 0.0;
+#pragma unroll
+            for (int n2 = 0; n2 < R8; ++n2)
+              if (n2 < N) s += gram[n * R8 + n2] * av[n2];
+            av[n] = fmax(0.0, av[n] + (fp[n] - s) / d);
+          }
+        }
       }
 #pragma unroll
       for (int n = 0; n < R8; ++n)
-        if (n < N) FtP[(long long)n * a.Kmax + i] = s[n];
-    }
-    if (t < N * N) {
-      const int n1 = t / N, n2 = t % N;
-      double s = 0.0;
-      for (int m = 0; m < Mc; ++m) s += F[(long long)m * R8 + n1] * F[(long long)m * R8 + n2];
-      gram[n1 * R8 + n2] = s;
+        if (n < N) A[(long long)n * a.Kmax + i] = av[n];
     }
     __syncthreads();
-    for (int n = 0; n < N; ++n) {
-      const double d = gram[n * R8 + n];
-      if (d > 0.0) {
-        for (int i = t; i < K; i += NT) {
-          double s = 0.0;
-          for (int n2 = 0; n2 < N; ++n2) s += gram[n * R8 + n2] * A[(long long)n2 * a.Kmax + i];
-          const long long ai = (long long)n * a.Kmax + i;
-          A[ai] = fmax(0.0, A[ai] + (FtP[ai] - s) / d);
-        }
-      }
-      __syncthreads();
-    }
     if (sweep < 0) continue;
-    // ---- F update: PAt = P A^T, AAt = A A^T
-    for (int m = t; m < Mc; m += NT) {
-      double s[R8];
+    // ---- F update. Gram A A^T:
+    {
+      double s[NPAIR];
 #pragma unroll
-      for (int n = 0; n < R8; ++n) s[n] = 0.0;
+      for (int k = 0; k < NPAIR; ++k) s[k] = 0.0;
+      for (int i = t; i < K; i += NT) {
+        double av[R8];
+#pragma unroll
+        for (int n = 0; n < R8; ++n) av[n] = n < N ? A[(long long)n * a.Kmax + i] : 0.0;
+        int k = 0;
+#pragma unroll
+        for (int n1 = 0; n1 < R8; ++n1)
+#pragma unroll
+          for (int n2 = n1; n2 < R8; ++n2, ++k) s[k] += av[n1] * av[n2];
+      }
+      block_gram(s, N, red, gram);
+    }
+    // per pixel m: P[m, :] A^T, then the columns of F in order
+    for (int m = t; m < Mc; m += NT) {
+      double g[R8];
+#pragma unroll
+      for (int n = 0; n < R8; ++n) g[n] = 0.0;
+#pragma unroll 4
       for (int i = 0; i < K; ++i) {
-        const double pv = PT[(long long)i * Mc + m];
+        const double pv = (double)PT[(long long)i * Mc + m];
 #pragma unroll
         for (int n = 0; n < R8; ++n)
-          if (n < N) s[n] += pv * A[(long long)n * a.Kmax + i];
+          if (n < N) g[n] += pv * A[(long long)n * a.Kmax + i];
+      }
+      double f[R8];
+#pragma unroll
+      for (int n = 0; n < R8; ++n) f[n] = n < N ? F[(long long)m * R8 + n] : 0.0;
+#pragma unroll
+      for (int n = 0; n < R8; ++n) {
+        if (n < N) {
+          const double d = gram[n * R8 + n];
+          if (d > 0.0) {
+            double s = 0.0;
+#pragma unroll
+            for (int n2 = 0; n2 < R8; ++n2)
+              if (n2 < N) s += f[n2] * gram[n2 * R8 + n];
+            f[n] = fmax(0.0, f[n] + (g[n] - s) / d);
+          }
+        }
       }
 #pragma unroll
       for (int n = 0; n < R8; ++n)
-        if (n < N) G[(long long)m * R8 + n] = s[n];
-    }
-    if (t < N * N) {
-      const int n1 = t / N, n2 = t % N;
-      double s = 0.0;
-      for (int i = 0; i < K; ++i) s += A[(long long)n1 * a.Kmax + i] * A[(long long)n2 * a.Kmax + i];
-      gram[n1 * R8 + n2] = s;
+        if (n < N) F[(long long)m * R8 + n] = f[n];
     }
     __syncthreads();
-    for (int n = 0; n < N; ++n) {
-      const double d = gram[n * R8 + n];
-      if (d > 0.0) {
-        for (int m = t; m < Mc; m += NT) {
-          double s = 0.0;
-          for (int n2 = 0; n2 < N; ++n2) s += F[(long long)m * R8 + n2] * gram[n2 * R8 + n];
-          const long long fi = (long long)m * R8 + n;
-          F[fi] = fmax(0.0, F[fi] + (G[fi] - s) / d);
-        }
-      }
-      __syncthreads();
-    }
   }
 
-  // scale footprints to peak 1
+  // ---------------------------------------------- scale to peak 1
   for (int n = 0; n < N; ++n) {
     double mx = 0.0;
     for (int m = t; m < Mc; m += NT) mx = fmax(mx, F[(long long)m * R8 + n]);
-    double best;
-    int dummy;
-    block_argmax(mx, 0, sv, si, &best, &dummy);
+    const double best = block_max(mx, red);
     if (best > 0.0) {
       for (int m = t; m < Mc; m += NT) F[(long long)m * R8 + n] /= best;
       for (int i = t; i < K; i += NT) A[(long long)n * a.Kmax + i] *= best;

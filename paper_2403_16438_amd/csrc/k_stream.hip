@@ -38,11 +38,8 @@ constexpr int CH = 10;               // frames per unrolled chunk
 constexpr int NCH = L / CH;          // 5 chunks per segment
 constexpr int ROWS_PER_WAVE = DH / 4;
 constexpr int XTRA = DW - 64;        // 24 columns loaded by a second lane pass
-constexpr int NV0 = NT;              // first-round vertical tasks
-constexpr int NVT = DW * (TH / 4);   // 352 vertical tasks (column, 4 rows)
 static_assert(L % CH == 0, "chunking");
 static_assert(DH % 4 == 0, "rows per wave");
-static_assert(NVT - NV0 == 4 * XTRA, "second-round vertical tasks: 24 per wave");
 
 struct KParams {
   const uint16_t* src0;
@@ -66,28 +63,82 @@ __device__ __forceinline__ int med3i(int a, int b, int c) {
   return max(min(a, b), min(max(a, b), c));
 }
 
-// Vertical pass for one (column, 4-row) task: U rows 4q..4q+3 of column c.
-__device__ __forceinline__ void vtask(int q, const float* __restrict__ Dl,
-                                      float* __restrict__ Ul, const KParams& p) {
-  const int c = q % DW;
-  const int quad = q / DW;
-  const float* col = Dl + quad * 4 * DW + c;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll
-  for (int j = 0; j < NTAP + 3; ++j) {
-    const double x = (double)col[j * DW];
-    if (j < NTAP) a0 = fma(p.w[j], x, a0);
-    if (j >= 1 && j < NTAP + 1) a1 = fma(p.w[j - 1], x, a1);
-    if (j >= 2 && j < NTAP + 2) a2 = fma(p.w[j - 2], x, a2);
-    if (j >= 3) a3 = fma(p.w[j - 3], x, a3);
-  }
-  float* o = Ul + quad * 4 * DW + c;
-  o[0] = (float)a0;
-  o[DW] = (float)a1;
-  o[2 * DW] = (float)a2;
-  o[3 * DW] = (float)a3;
+// LDS-only workgroup barrier: waits for this wave's LDS traffic, not for its
+// outstanding global loads, so the next frame's prefetch stays in flight.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Vertical pass for one (column, 8-row) task: U rows 8h..8h+7 of column c,
+// streaming the 32 staged rows once.
+constexpr int VROWS = 8;
+constexpr int NVT8 = DW * (TH / VROWS);   // 176 tasks, one round
+static_assert(NVT8 <= NT, "one vertical round");
+
+__device__ __forceinline__ void vtask8(int q, const float* __restrict__ Dl,
+                                       float* __restrict__ Ul, const KParams& p) {
+  const int c = q % DW;
+  const int h = q / DW;
+  const float* col = Dl + h * VROWS * DW + c;
+  double acc[VROWS];
+#pragma unroll
+  for (int o = 0; o < VROWS; ++o) acc[o] = 0.0;
+#pragma unroll
+  for (int j = 0; j < NTAP + VROWS - 1; ++j) {
+    const double x = (double)col[j * DW];
+#pragma unroll
+    for (int o = 0; o < VROWS; ++o)
+      if (j - o >= 0 && j - o < NTAP) acc[o] = fma(p.w[j - o], x, acc[o]);
+  }
+  float* out = Ul + h * VROWS * DW + c;
+#pragma unroll
+  for (int o = 0; o < VROWS; ++o) out[o * DW] = (float)acc[o];
+}
+
+// Quad loader: the staged region (40 rows x 88 columns) as 880 groups of 4
+// consecutive columns. With W % 4 == 0 and W >= 16, every group maps to 4
+// contiguous source columns, ascending, or descending where the group lies in
+// the reflected border, so one 8-byte load fetches it.
+constexpr int QPR = DW / 4;          // 22 groups per row
+constexpr int NQ = DH * QPR;         // 880
+constexpr int KQ = (NQ + NT - 1) / NT;  // 4 groups per thread at most
+
+struct QuadPlan {
+  int off[KQ];    // element offset of the group's lowest source column
+  int dst[KQ];    // first LDS index of the group
+  int rev;        // bit k: group k is reversed
+  int nk;         // groups this thread owns
+};
+
+__device__ __forceinline__ QuadPlan quad_plan(int tid, int ty0, int tx0, int H, int W) {
+  QuadPlan qp;
+  qp.rev = 0;
+  qp.nk = 0;
+#pragma unroll
+  for (int k = 0; k < KQ; ++k) {
+    const int q = tid + k * NT;
+    const int qq = q < NQ ? q : 0;
+    const int r = qq / QPR, c4 = qq - r * QPR;
+    const int srow = reflect(ty0 - RAD + r, H);
+    const int a = tx0 - RAD + 4 * c4;
+    const int c0 = reflect(a, W), c3 = reflect(a + 3, W);
+    qp.off[k] = srow * W + (c3 < c0 ? c3 : c0);
+    qp.dst[k] = r * DW + 4 * c4;
+    if (c3 < c0) qp.rev |= 1 << k;
+    if (q < NQ) qp.nk = k + 1;
+  }
+  return qp;
+}
+
+__device__ __forceinline__ void unpack4(uint2 v, bool rev, int (&x)[4]) {
+  const int a = (int)(v.x & 0xffffu), b = (int)(v.x >> 16), c = (int)(v.y & 0xffffu), d = (int)(v.y >> 16);
+  x[0] = rev ? d : a;
+  x[1] = rev ? c : b;
+  x[2] = rev ? b : c;
+  x[3] = rev ? a : d;
+}
+
+template <bool QUAD>
 __global__ __launch_bounds__(NT, 2) void k_block_stats(KParams p) {
   __shared__ float Dl[DH * DW];
   __shared__ float Rl[DH * DW];
@@ -113,32 +164,55 @@ __global__ __launch_bounds__(NT, 2) void k_block_stats(KParams p) {
   const int tx0 = (tile % tiles_x) * TW;
   const long long M = (long long)p.H * p.W;
 
-  // ---- staging geometry: wave wv loads rows wv, wv+4, ...; lane = column
-  const int cx0 = reflect(tx0 - RAD + lane, p.W);
-  const int cx1 = reflect(tx0 - RAD + 64 + (lane < XTRA ? lane : 0), p.W);
-  int rowoff[ROWS_PER_WAVE];
-#pragma unroll
-  for (int k = 0; k < ROWS_PER_WAVE; ++k)
-    rowoff[k] = __builtin_amdgcn_readfirstlane(reflect(ty0 - RAD + wv + 4 * k, p.H) * p.W);
-
   const long long fbase = (long long)sl * L;
   auto frame = [&](int t) -> const uint16_t* {
     const long long f = fbase + t;
     return f < p.n0 ? p.src0 + f * M : p.src1 + (f - p.n0) * M;
   };
 
+  // ---- staging geometry
+  QuadPlan qp;
+  int cx0 = 0, cx1 = 0;
+  int rowoff[ROWS_PER_WAVE];
+  if constexpr (QUAD) {
+    qp = quad_plan(tid, ty0, tx0, p.H, p.W);
+  } else {
+    // wave wv loads rows wv, wv+4, ...; lane = column
+    cx0 = reflect(tx0 - RAD + lane, p.W);
+    cx1 = reflect(tx0 - RAD + 64 + (lane < XTRA ? lane : 0), p.W);
+#pragma unroll
+    for (int k = 0; k < ROWS_PER_WAVE; ++k)
+      rowoff[k] = __builtin_amdgcn_readfirstlane(reflect(ty0 - RAD + wv + 4 * k, p.H) * p.W);
+  }
+
   // ---- per-pixel reference: median of the segment's first three frames
   {
     const uint16_t* f0 = frame(0);
     const uint16_t* f1 = frame(1);
     const uint16_t* f2 = frame(2);
+    if constexpr (QUAD) {
 #pragma unroll
-    for (int k = 0; k < ROWS_PER_WAVE; ++k) {
-      const int r = wv + 4 * k;
-      const int o = rowoff[k];
-      Rl[r * DW + lane] = (float)med3i(f0[o + cx0], f1[o + cx0], f2[o + cx0]);
-      if (lane < XTRA)
-        Rl[r * DW + 64 + lane] = (float)med3i(f0[o + cx1], f1[o + cx1], f2[o + cx1]);
+      for (int k = 0; k < KQ; ++k) {
+        if (k < qp.nk) {
+          int a[4], b[4], c[4];
+          const bool rv = (qp.rev >> k) & 1;
+          unpack4(*reinterpret_cast<const uint2*>(f0 + qp.off[k]), rv, a);
+          unpack4(*reinterpret_cast<const uint2*>(f1 + qp.off[k]), rv, b);
+          unpack4(*reinterpret_cast<const uint2*>(f2 + qp.off[k]), rv, c);
+          *reinterpret_cast<float4*>(Rl + qp.dst[k]) =
+              make_float4((float)med3i(a[0], b[0], c[0]), (float)med3i(a[1], b[1], c[1]),
+                          (float)med3i(a[2], b[2], c[2]), (float)med3i(a[3], b[3], c[3]));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < ROWS_PER_WAVE; ++k) {
+        const int r = wv + 4 * k;
+        const int o = rowoff[k];
+        Rl[r * DW + lane] = (float)med3i(f0[o + cx0], f1[o + cx0], f2[o + cx0]);
+        if (lane < XTRA)
+          Rl[r * DW + 64 + lane] = (float)med3i(f0[o + cx1], f1[o + cx1], f2[o + cx1]);
+      }
     }
   }
   __syncthreads();
@@ -160,20 +234,49 @@ __global__ __launch_bounds__(NT, 2) void k_block_stats(KParams p) {
     for (int k = 0; k < 5; ++k) Pacc[k][i] = 0.f;
   }
 
+  uint2 pf[KQ];   // next frame's raw groups (quad path)
+  if constexpr (QUAD) {
+    const uint16_t* fr = frame(0);
+#pragma unroll
+    for (int k = 0; k < KQ; ++k)
+      if (k < qp.nk) pf[k] = *reinterpret_cast<const uint2*>(fr + qp.off[k]);
+  }
+
 #pragma unroll 1
   for (int c = 0; c < NCH; ++c) {
 #pragma unroll 1
     for (int f = 0; f < CH; ++f) {
-      const uint16_t* fr = frame(c * CH + f);
+      const int t = c * CH + f;
       // (a) stage d = V - R for the tile and its halo
+      if constexpr (QUAD) {
 #pragma unroll
-      for (int k = 0; k < ROWS_PER_WAVE; ++k) {
-        const int r = wv + 4 * k;
-        const int o = rowoff[k];
-        Dl[r * DW + lane] = (float)fr[o + cx0] - Rl[r * DW + lane];
-        if (lane < XTRA) Dl[r * DW + 64 + lane] = (float)fr[o + cx1] - Rl[r * DW + 64 + lane];
+        for (int k = 0; k < KQ; ++k) {
+          if (k < qp.nk) {
+            int x[4];
+            unpack4(pf[k], (qp.rev >> k) & 1, x);
+            const float4 r = *reinterpret_cast<const float4*>(Rl + qp.dst[k]);
+            *reinterpret_cast<float4*>(Dl + qp.dst[k]) =
+                make_float4((float)x[0] - r.x, (float)x[1] - r.y, (float)x[2] - r.z, (float)x[3] - r.w);
+          }
+        }
+        // prefetch frame t + 1 while this frame is processed
+        if (t + 1 < L) {
+          const uint16_t* fr = frame(t + 1);
+#pragma unroll
+          for (int k = 0; k < KQ; ++k)
+            if (k < qp.nk) pf[k] = *reinterpret_cast<const uint2*>(fr + qp.off[k]);
+        }
+      } else {
+        const uint16_t* fr = frame(t);
+#pragma unroll
+        for (int k = 0; k < ROWS_PER_WAVE; ++k) {
+          const int r = wv + 4 * k;
+          const int o = rowoff[k];
+          Dl[r * DW + lane] = (float)fr[o + cx0] - Rl[r * DW + lane];
+          if (lane < XTRA) Dl[r * DW + 64 + lane] = (float)fr[o + cx1] - Rl[r * DW + 64 + lane];
+        }
       }
-      __syncthreads();
+      lds_barrier();
       // (b) co-moment sums of the raw (reference-subtracted) values
       {
         float a[NPX + 1], b[NPX + 2];
@@ -193,9 +296,8 @@ __global__ __launch_bounds__(NT, 2) void k_block_stats(KParams p) {
         }
       }
       // (c) vertical pass into Ul
-      vtask(tid, Dl, Ul, p);
-      if (lane < XTRA) vtask(NV0 + wv * XTRA + lane, Dl, Ul, p);
-      __syncthreads();
+      if (tid < NVT8) vtask8(tid, Dl, Ul, p);
+      lds_barrier();
       // (d) horizontal pass into this thread's LDS chunk slot
       {
         const float* row = Ul + hy * DW + hx0;
@@ -285,7 +387,10 @@ hipError_t launch_block_stats(const StreamLaunch& a, hipStream_t st) {
   const int tiles = ((a.W + TW - 1) / TW) * ((a.H + TH - 1) / TH);
   const long long nblk = (long long)tiles * a.nseg;
   const long long per = (nblk + 7) / 8;
-  hipLaunchKernelGGL(k_block_stats, dim3((unsigned)(per * 8)), dim3(NT), 0, st, p);
+  if (a.W % 4 == 0 && a.W >= 16)
+    hipLaunchKernelGGL(k_block_stats<true>, dim3((unsigned)(per * 8)), dim3(NT), 0, st, p);
+  else
+    hipLaunchKernelGGL(k_block_stats<false>, dim3((unsigned)(per * 8)), dim3(NT), 0, st, p);
   return hipGetLastError();
 }
 

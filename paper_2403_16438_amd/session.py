@@ -21,9 +21,12 @@ def to_device_frames(video: np.ndarray, device="cuda") -> torch.Tensor:
 class Session:
     def __init__(self, height: int, width: int, max_frames: int, device=None,
                  workspace: torch.Tensor | None = None, **overrides):
-        self.device = torch.device(device or "cuda")
-        if self.device.type != "cuda":
+        dev = torch.device(device or "cuda")
+        if dev.type != "cuda":
             raise ValueError("Session needs a GPU device")
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
         self.cfg = abi.seg_default_config(height, width, max_frames)
         for k, v in overrides.items():
             if not hasattr(self.cfg, k):
