@@ -162,6 +162,37 @@ int seg_load_summaries(seg_session* s, uint32_t k, const float* T,
                        const float* S, const float* D, const float* U,
                        const float* P);
 
+/* ---- serving: several recordings in one launch (continuous batching) ----
+ *
+ * A batch object owns a slot table that describes, for every session of a
+ * push, where its frames and per-segment outputs are. The streaming kernel
+ * is captured once in a HIP graph whose launch reads that table from device
+ * memory, so each push rewrites the table (one host-to-device copy) and
+ * replays the graph. Every session's result is the same as when it is
+ * pushed alone: each (segment, tile) item runs the same code on the same data.
+ */
+typedef struct seg_batch seg_batch;   /* opaque */
+
+/* Device bytes of a batch table for up to max_slots sessions (<= 64). */
+int seg_batch_bytes(uint32_t max_slots, size_t* bytes);
+
+/* Create a batch object using the caller's device memory dev_table (at least
+ * seg_batch_bytes bytes, 256-byte aligned); it also allocates a pinned host
+ * copy of the table. Errors: SEG_E_INVAL, SEG_E_CAPACITY, SEG_E_DEVICE. */
+int seg_batch_create(uint32_t max_slots, void* dev_table, size_t bytes, seg_batch** out);
+
+/* Append n_frames[k] frames (dev_frames[k], device memory) to sessions[k] for
+ * k < count, as seg_push_frames would, with one graph launch on `stream` for
+ * all complete segments. Sessions must be distinct, open and on the batch's
+ * device. All checks happen before anything is launched: on error nothing is
+ * pushed. Errors: SEG_E_INVAL, SEG_E_STATE, SEG_E_CAPACITY, SEG_E_DEVICE. */
+int seg_push_batch(seg_batch* b, seg_session* const* sessions,
+                   const uint16_t* const* dev_frames, const uint32_t* n_frames,
+                   uint32_t count, void* stream);
+
+/* Release the batch object (not the caller's device table). */
+int seg_batch_destroy(seg_batch* b);
+
 /* Release the session (not the caller's workspace). NULL is a no-op. */
 int seg_destroy(seg_session* s);
 

@@ -72,6 +72,10 @@ def _load():
         "seg_get_segment_maps": (C.c_int, [P, C.c_int, u32, u32, P, P]),
         "seg_load_summaries": (C.c_int, [P, u32, P, P, P, P, P]),
         "seg_destroy": (C.c_int, [P]),
+        "seg_batch_bytes": (C.c_int, [u32, C.POINTER(C.c_size_t)]),
+        "seg_batch_create": (C.c_int, [u32, P, C.c_size_t, C.POINTER(P)]),
+        "seg_push_batch": (C.c_int, [P, C.POINTER(P), C.POINTER(P), C.POINTER(u32), u32, P]),
+        "seg_batch_destroy": (C.c_int, [P]),
         "seg_strerror": (C.c_char_p, [C.c_int]),
         "seg_last_error": (C.c_int, [P]),
     }
@@ -160,3 +164,28 @@ def seg_destroy(h) -> None:
 
 def seg_last_error(h) -> int:
     return lib.seg_last_error(h)
+
+
+def seg_batch_bytes(max_slots: int) -> int:
+    n = C.c_size_t()
+    check(lib.seg_batch_bytes(max_slots, C.byref(n)), "seg_batch_bytes")
+    return n.value
+
+
+def seg_batch_create(max_slots: int, dev_table: int, nbytes: int):
+    h = C.c_void_p()
+    check(lib.seg_batch_create(max_slots, C.c_void_p(dev_table), nbytes, C.byref(h)), "seg_batch_create")
+    return h
+
+
+def seg_push_batch(b, sessions, dev_frames, n_frames, stream: int) -> None:
+    k = len(sessions)
+    S = (C.c_void_p * k)(*[s.value for s in sessions])
+    F = (C.c_void_p * k)(*dev_frames)
+    N = (C.c_uint32 * k)(*n_frames)
+    check(lib.seg_push_batch(b, S, F, N, k, C.c_void_p(stream)), "seg_push_batch")
+
+
+def seg_batch_destroy(b) -> None:
+    lib.seg_batch_destroy(b)
+

@@ -1,5 +1,5 @@
 // Per-component NMF P_c ~ F A (Eq. 3, Sec. III-D), FP64 arithmetic, one
-// workgroup of 512 threads per component of the aggregate mask.
+// workgroup of 1024 threads per component of the aggregate mask.
 //   gather  P_c[m][i] = p_i(x_m) for the component's pixels x_m (raster
 //           order), stored twice in FP32 (exact: the maps are FP32): pixel-
 //           major for column sweeps and segment-major for pixel sweeps
@@ -14,14 +14,19 @@
 //           pixel, so a thread owns a column (a pixel), keeps it in
 //           registers through the sequential row (column) updates, and only
 //           the N x N Gram matrices F^T F and A A^T need block reductions.
+//           F and A live in LDS when they fit (dynamic size chosen by the
+//           host), and the column sums F^T P are split over Q pixel ranges
+//           reduced in a fixed order.
 //   scale   each f_n to max 1, a_n inversely
 // Every reduction has a fixed order, so results are bit-reproducible.
+#include <algorithm>
+
 #include "seg_internal.h"
 
 namespace seg {
 namespace {
 
-constexpr int NT = 512;
+constexpr int NT = 1024;
 constexpr int NW = NT / 64;
 constexpr int R8 = kMaxRank;
 constexpr int NPAIR = R8 * (R8 + 1) / 2;
@@ -103,7 +108,9 @@ __device__ void block_argmax(double v, int idx, double* red, int* redi, double* 
   __syncthreads();
 }
 
+template <bool LDS>
 __global__ __launch_bounds__(NT) void k_nmf(NmfArgs a) {
+  extern __shared__ double dyn[];
   __shared__ double red[NW * NPAIR];
   __shared__ int redi[NW];
   __shared__ double gram[R8 * R8];
@@ -113,14 +120,33 @@ __global__ __launch_bounds__(NT) void k_nmf(NmfArgs a) {
   const int off = a.coff[c];
   const int Mc = a.coff[c + 1] - off;
   const int K = a.K;
+  const int Q = a.Q;
   float* P = reinterpret_cast<float*>(a.P) + (long long)off * K;    // [Mc][K]
   float* PT = reinterpret_cast<float*>(a.PT) + (long long)off * K;  // [K][Mc]
   double* R = a.R + (long long)off * K;                              // [Mc][K]
-  double* F = a.F + (long long)off * R8;                             // [Mc][R8]
   double* U = a.G + (long long)off * R8;                             // SPA direction
-  double* A = a.A + (long long)c * R8 * a.Kmax;                      // [R8][Kmax]
-  double* nz = a.Wk + (long long)c * (R8 + 2) * a.Kmax;              // [K] flags
+  double* nz = a.Wk + (long long)c * 2 * a.Kmax;                     // [K] flags
   double* prj = nz + a.Kmax;                                         // [K]
+  // LDS carve-up: A [R8][K], partial column sums [Q][R8][K], F [Mc][R8];
+  // without room in LDS, A and F live in the output arrays and Q = 1 (each
+  // thread sums a whole column, no partial sums)
+  // (the placement is a template parameter so that LDS accesses compile to
+  // ds instructions rather than flat ones)
+  double* A;
+  double* part;
+  double* F;
+  int As;                                                            // row stride of A
+  if constexpr (LDS) {
+    A = dyn;
+    part = dyn + R8 * K;
+    F = dyn + (long long)R8 * K * (1 + Q);
+    As = K;
+  } else {
+    A = a.A + (long long)c * R8 * a.Kmax;
+    part = nullptr;
+    F = a.F + (long long)off * R8;
+    As = a.Kmax;
+  }
 
   for (long long e = t; e < (long long)Mc * K; e += NT) {
     const int m = (int)(e / K), i = (int)(e - (long long)m * K);
@@ -202,9 +228,10 @@ __global__ __launch_bounds__(NT) void k_nmf(NmfArgs a) {
     for (int m = t; m < Mc; m += NT) F[(long long)m * R8 + n] = (double)P[(long long)m * K + col] / best;
   }
   for (int i = t; i < K; i += NT)
-    for (int n = 0; n < R8; ++n) A[(long long)n * a.Kmax + i] = 0.0;
+    for (int n = 0; n < R8; ++n) A[(long long)n * As + i] = 0.0;
   __syncthreads();
 
+  const int mq = (Mc + Q - 1) / Q;   // pixels per partition of the column sums
   for (int sweep = -1; sweep < a.sweeps; ++sweep) {
     // ---- A update. Gram F^T F:
     {
@@ -223,22 +250,52 @@ __global__ __launch_bounds__(NT) void k_nmf(NmfArgs a) {
       }
       block_gram(s, N, red, gram);
     }
-    // per column i: F^T P[:, i], then the rows of A in order
-    for (int i = t; i < K; i += NT) {
-      double fp[R8];
+    // partial F^T P over pixel range q of column i (LDS placement); with
+    // Q = 1 the column sums stay in registers below
+    if constexpr (LDS) {
+      for (int e = t; e < Q * K; e += NT) {
+        const int q = e / K, i = e - q * K;
+        const int m0 = q * mq, m1 = min(Mc, m0 + mq);
+        double fp[R8];
 #pragma unroll
-      for (int n = 0; n < R8; ++n) fp[n] = 0.0;
-#pragma unroll 4
-      for (int m = 0; m < Mc; ++m) {
-        const double pv = (double)P[(long long)m * K + i];
-        const double* fm = F + (long long)m * R8;
+        for (int n = 0; n < R8; ++n) fp[n] = 0.0;
+#pragma unroll 8
+        for (int m = m0; m < m1; ++m) {
+          const double pv = (double)P[(long long)m * K + i];
+          const double* fm = F + (long long)m * R8;
+#pragma unroll
+          for (int n = 0; n < R8; ++n)
+            if (n < N) fp[n] += fm[n] * pv;
+        }
 #pragma unroll
         for (int n = 0; n < R8; ++n)
-          if (n < N) fp[n] += fm[n] * pv;
+          if (n < N) part[((long long)q * R8 + n) * K + i] = fp[n];
       }
-      double av[R8];
+      __syncthreads();
+    }
+    // per column: sum the partitions in order, then the rows of A in order
+    for (int i = t; i < K; i += NT) {
+      double fp[R8], av[R8];
 #pragma unroll
-      for (int n = 0; n < R8; ++n) av[n] = n < N ? A[(long long)n * a.Kmax + i] : 0.0;
+      for (int n = 0; n < R8; ++n) {
+        fp[n] = 0.0;
+        av[n] = n < N ? A[(long long)n * As + i] : 0.0;
+      }
+      if constexpr (LDS) {
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+          for (int n = 0; n < R8; ++n)
+            if (n < N) fp[n] += part[((long long)q * R8 + n) * K + i];
+      } else {
+#pragma unroll 8
+        for (int m = 0; m < Mc; ++m) {
+          const double pv = (double)P[(long long)m * K + i];
+          const double* fm = F + (long long)m * R8;
+#pragma unroll
+          for (int n = 0; n < R8; ++n)
+            if (n < N) fp[n] += fm[n] * pv;
+        }
+      }
 #pragma unroll
       for (int n = 0; n < R8; ++n) {
         if (n < N) {
@@ -254,7 +311,7 @@ __global__ __launch_bounds__(NT) void k_nmf(NmfArgs a) {
       }
 #pragma unroll
       for (int n = 0; n < R8; ++n)
-        if (n < N) A[(long long)n * a.Kmax + i] = av[n];
+        if (n < N) A[(long long)n * As + i] = av[n];
     }
     __syncthreads();
     if (sweep < 0) continue;
@@ -266,7 +323,7 @@ __global__ __launch_bounds__(NT) void k_nmf(NmfArgs a) {
       for (int i = t; i < K; i += NT) {
         double av[R8];
 #pragma unroll
-        for (int n = 0; n < R8; ++n) av[n] = n < N ? A[(long long)n * a.Kmax + i] : 0.0;
+        for (int n = 0; n < R8; ++n) av[n] = n < N ? A[(long long)n * As + i] : 0.0;
         int k = 0;
 #pragma unroll
         for (int n1 = 0; n1 < R8; ++n1)
@@ -275,50 +332,67 @@ __global__ __launch_bounds__(NT) void k_nmf(NmfArgs a) {
       }
       block_gram(s, N, red, gram);
     }
-    // per pixel m: P[m, :] A^T, then the columns of F in order
-    for (int m = t; m < Mc; m += NT) {
-      double g[R8];
-#pragma unroll
-      for (int n = 0; n < R8; ++n) g[n] = 0.0;
-#pragma unroll 4
-      for (int i = 0; i < K; ++i) {
-        const double pv = (double)PT[(long long)i * Mc + m];
-#pragma unroll
-        for (int n = 0; n < R8; ++n)
-          if (n < N) g[n] += pv * A[(long long)n * a.Kmax + i];
-      }
-      double f[R8];
-#pragma unroll
-      for (int n = 0; n < R8; ++n) f[n] = n < N ? F[(long long)m * R8 + n] : 0.0;
+    // per pixel m: P[m, :] A^T, then the columns of F in order; each thread
+    // carries two pixels (m and m + NT) to keep more loads in flight
+    for (int m0 = t; m0 < Mc; m0 += 2 * NT) {
+      const int m1 = m0 + NT;
+      const bool two = m1 < Mc;
+      double g0[R8], g1[R8];
 #pragma unroll
       for (int n = 0; n < R8; ++n) {
-        if (n < N) {
-          const double d = gram[n * R8 + n];
-          if (d > 0.0) {
-            double s = 0.0;
+        g0[n] = 0.0;
+        g1[n] = 0.0;
+      }
+#pragma unroll 4
+      for (int i = 0; i < K; ++i) {
+        const double pv0 = (double)PT[(long long)i * Mc + m0];
+        const double pv1 = two ? (double)PT[(long long)i * Mc + m1] : 0.0;
 #pragma unroll
-            for (int n2 = 0; n2 < R8; ++n2)
-              if (n2 < N) s += f[n2] * gram[n2 * R8 + n];
-            f[n] = fmax(0.0, f[n] + (g[n] - s) / d);
+        for (int n = 0; n < R8; ++n)
+          if (n < N) {
+            const double av = A[(long long)n * As + i];
+            g0[n] += pv0 * av;
+            g1[n] += pv1 * av;
           }
-        }
       }
 #pragma unroll
-      for (int n = 0; n < R8; ++n)
-        if (n < N) F[(long long)m * R8 + n] = f[n];
+      for (int h = 0; h < 2; ++h) {
+        const int m = h ? m1 : m0;
+        if (h && !two) break;
+        double f[R8];
+#pragma unroll
+        for (int n = 0; n < R8; ++n) f[n] = n < N ? F[(long long)m * R8 + n] : 0.0;
+#pragma unroll
+        for (int n = 0; n < R8; ++n) {
+          if (n < N) {
+            const double d = gram[n * R8 + n];
+            if (d > 0.0) {
+              double s = 0.0;
+#pragma unroll
+              for (int n2 = 0; n2 < R8; ++n2)
+                if (n2 < N) s += f[n2] * gram[n2 * R8 + n];
+              f[n] = fmax(0.0, f[n] + ((h ? g1[n] : g0[n]) - s) / d);
+            }
+          }
+        }
+#pragma unroll
+        for (int n = 0; n < R8; ++n)
+          if (n < N) F[(long long)m * R8 + n] = f[n];
+      }
     }
     __syncthreads();
   }
 
-  // ---------------------------------------------- scale to peak 1
+  // ---------------------------------------------- scale to peak 1, export
+  double* Ag = a.A + (long long)c * R8 * a.Kmax;
+  double* Fg = a.F + (long long)off * R8;
   for (int n = 0; n < N; ++n) {
     double mx = 0.0;
     for (int m = t; m < Mc; m += NT) mx = fmax(mx, F[(long long)m * R8 + n]);
     const double best = block_max(mx, red);
-    if (best > 0.0) {
-      for (int m = t; m < Mc; m += NT) F[(long long)m * R8 + n] /= best;
-      for (int i = t; i < K; i += NT) A[(long long)n * a.Kmax + i] *= best;
-    }
+    const double sc = best > 0.0 ? best : 1.0;
+    for (int m = t; m < Mc; m += NT) Fg[(long long)m * R8 + n] = F[(long long)m * R8 + n] / sc;
+    for (int i = t; i < K; i += NT) Ag[(long long)n * a.Kmax + i] = A[(long long)n * As + i] * sc;
     __syncthreads();
   }
   if (t == 0) a.N[c] = N;
@@ -326,9 +400,39 @@ __global__ __launch_bounds__(NT) void k_nmf(NmfArgs a) {
 
 }  // namespace
 
+void plan_nmf(NmfArgs& a, int max_mc) {
+  int dev = 0, max_lds = 65536;
+  if (hipGetDevice(&dev) == hipSuccess)
+    hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  const size_t budget = max_lds > 16384 ? (size_t)max_lds - 8192 : 0;  // static LDS ~5 KB
+  const size_t K = (size_t)a.K;
+  int Q = (int)std::max<size_t>(1, std::min<size_t>(16, NT / std::max<size_t>(1, K)));
+  auto aq = [&](int q) { return (size_t)R8 * K * 8 * (1 + q); };
+  while (Q > 1 && aq(Q) > budget) --Q;
+  a.lds_A = aq(Q) <= budget;
+  if (!a.lds_A) Q = 1;
+  a.Q = Q;
+  const size_t used = a.lds_A ? aq(Q) : 0;
+  const size_t fbytes = (size_t)max_mc * R8 * 8;
+  a.lds_F = a.lds_A && used + fbytes <= budget;
+  if (!a.lds_F) {  // global placement (A, partial sums and F), one pixel range
+    a.lds_A = false;
+    a.Q = 1;
+  }
+  a.lds_bytes = a.lds_F ? used + fbytes : 0;
+}
+
 hipError_t launch_nmf(const NmfArgs& a, hipStream_t st) {
   if (a.ncomp <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_nmf, dim3(a.ncomp), dim3(NT), 0, st, a);
+  if (a.lds_A && a.lds_F) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_nmf<true>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)a.lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_nmf<true>, dim3(a.ncomp), dim3(NT), a.lds_bytes, st, a);
+  } else {
+    hipLaunchKernelGGL(k_nmf<false>, dim3(a.ncomp), dim3(NT), 0, st, a);
+  }
   return hipGetLastError();
 }
 

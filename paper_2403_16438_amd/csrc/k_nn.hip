@@ -1,0 +1,440 @@
+// Kernels of the learned surrogate detector (the spiking-pixel identifier of
+// Sec. III-C: temporal convolutions feeding a 2-D U-Net). Activations are
+// FP32 in a [channel][batch][row][col] layout, so a convolution is one GEMM
+// whose output is already the next activation; matrix operands are rounded to
+// BF16 (round to nearest even) and multiplied on MFMA with FP32 accumulation.
+#include <cstdint>
+
+#include "nn_internal.h"
+
+namespace seg {
+namespace nn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <class T>
+__device__ __forceinline__ uint16_t ld_bf16(const T* p, long long i);
+template <>
+__device__ __forceinline__ uint16_t ld_bf16<uint16_t>(const uint16_t* p, long long i) {
+  return p[i];
+}
+template <>
+__device__ __forceinline__ uint16_t ld_bf16<float>(const float* p, long long i) {
+  return to_bf16(p[i]);
+}
+
+// ---------------------------------------------------------------- GEMM
+// C[m][n] (+)= sum_k A(m, k) B(k, n); A(m, k) = A[m*sam + k*sak],
+// B(k, n) = B[k*sbk + n*sbn]. Block: 256 threads, 64 x 64 tile, K step 32.
+// Split-K over gridDim.z writes partial tiles to C + z*M*ldc (summed later).
+constexpr int GT = 64, GK = 32;
+
+template <class TA, class TB>
+__global__ __launch_bounds__(256) void k_gemm(const TA* __restrict__ A, long long sam, long long sak,
+                                              const TB* __restrict__ B, long long sbk, long long sbn,
+                                              float* __restrict__ C, long long ldc, int M, int N, int K,
+                                              int kchunk, int accumulate) {
+  __shared__ uint16_t As[GT][GK + 8];   // [m][k]
+  __shared__ uint16_t Bs[GT][GK + 8];   // [n][k]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+  float* Cz = C + (long long)blockIdx.z * M * ldc;
+  f32x16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  for (int k0 = kbeg; k0 < kend; k0 += GK) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + 256 * j;
+      int m, k;
+      if (sak == 1) {
+        m = e / GK;
+        k = e % GK;
+      } else {
+        k = e / GT;
+        m = e % GT;
+      }
+      const int gm = m0 + m, gk = k0 + k;
+      As[m][k] = (gm < M && gk < kend) ? ld_bf16(A, gm * sam + gk * sak) : (uint16_t)0;
+      int n, kb;
+      if (sbn == 1) {
+        kb = e / GT;
+        n = e % GT;
+      } else {
+        n = e / GK;
+        kb = e % GK;
+      }
+      const int gn = n0 + n, gkb = k0 + kb;
+      Bs[n][kb] = (gn < N && gkb < kend) ? ld_bf16(B, gkb * sbk + gn * sbn) : (uint16_t)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 16) {
+      const int kk = ks + (lane >> 5) * 8;
+      bf16x8 a, b;
+      const uint16_t* ap = &As[wm * 32 + (lane & 31)][kk];
+      const uint16_t* bp = &Bs[wn * 32 + (lane & 31)][kk];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        a[q] = __builtin_bit_cast(__bf16, ap[q]);
+        b[q] = __builtin_bit_cast(__bf16, bp[q]);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int col = n0 + wn * 32 + (lane & 31);
+  if (col >= N) return;
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = m0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
+      if (row < M) {
+        float* c = Cz + (long long)row * ldc + col;
+        *c = accumulate ? *c + acc[4 * g + r] : acc[4 * g + r];
+      }
+    }
+}
+
+// sum the split-K partials in order: C[m][n] (+)= sum_z P[z][m][n]
+__global__ void k_splitk_reduce(const float* __restrict__ P, float* __restrict__ C, long long MN, int Z,
+                                int accumulate) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MN) return;
+  float s = 0.f;
+  for (int z = 0; z < Z; ++z) s += P[(long long)z * MN + i];
+  C[i] = accumulate ? C[i] + s : s;
+}
+
+// ------------------------------------------------------- 3x3 convolutions
+// col[(c*9 + ky*3 + kx)][b*HW + y*W + x] = X[c][b][y + ky - 1][x + kx - 1]
+__global__ void k_im2col3(const float* __restrict__ X, uint16_t* __restrict__ col, int C, int Bn, int H, int W) {
+  const long long N = (long long)Bn * H * W;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * C * 9) return;
+  const long long p = i % N;
+  const int r = (int)(i / N);
+  const int c = r / 9, kk = r % 9, ky = kk / 3, kx = kk % 3;
+  const int b = (int)(p / (H * W)), yx = (int)(p % (H * W)), y = yx / W, x = yx % W;
+  const int yy = y + ky - 1, xx = x + kx - 1;
+  const float v = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? X[((long long)c * Bn + b) * H * W + yy * W + xx] : 0.f;
+  col[i] = to_bf16(v);
+}
+
+// dX[c][b][y][x] (+)= sum_{ky,kx} dcol[c*9 + ky*3 + kx][b, y - ky + 1, x - kx + 1]
+__global__ void k_col2im3(const float* __restrict__ dcol, float* __restrict__ dX, int C, int Bn, int H, int W,
+                          int accumulate) {
+  const long long N = (long long)Bn * H * W;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * C) return;
+  const int c = (int)(i / N);
+  const long long p = i % N;
+  const int b = (int)(p / (H * W)), yx = (int)(p % (H * W)), y = yx / W, x = yx % W;
+  float s = 0.f;
+  for (int ky = 0; ky < 3; ++ky)
+    for (int kx = 0; kx < 3; ++kx) {
+      const int yy = y - ky + 1, xx = x - kx + 1;
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+        s += dcol[(long long)(c * 9 + ky * 3 + kx) * N + (long long)b * H * W + yy * W + xx];
+    }
+  dX[i] = accumulate ? dX[i] + s : s;
+}
+
+// -------------------------------------------------- temporal convolutions
+// input normalisation per segment and pixel: (V - mean) / sqrt(mean + 25);
+// out layout [t][b][p] (one channel), frames [b][t][p] with p over H*W
+__global__ void k_tnorm(const uint16_t* __restrict__ frames, float* __restrict__ out, int Bn, int L, long long HW) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)Bn * HW) return;
+  const int b = (int)(i / HW);
+  const long long p = i % HW;
+  const uint16_t* f = frames + (long long)b * L * HW + p;
+  float s = 0.f;
+  for (int t = 0; t < L; ++t) s += (float)f[(long long)t * HW];
+  const float mean = s / L;
+  const float inv = rsqrtf(mean + 25.f);
+  for (int t = 0; t < L; ++t) out[((long long)t * Bn + b) * HW + p] = ((float)f[(long long)t * HW] - mean) * inv;
+}
+
+// 1-D im2col: in [C][Tin][N], kernel KT, stride S, pad P ->
+// col[(c*KT + k)][(j*N + n)] = in[c][j*S + k - P][n], j < Tout
+__global__ void k_im2col1(const float* __restrict__ in, uint16_t* __restrict__ col, int C, int Tin, int Tout,
+                          int KT, int S, int P, long long N) {
+  const long long total = (long long)C * KT * Tout * N;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const long long cols = (long long)Tout * N;
+  const int r = (int)(i / cols);
+  const long long q = i % cols;
+  const int c = r / KT, k = r % KT;
+  const int j = (int)(q / N);
+  const long long n = q % N;
+  const int t = j * S + k - P;
+  col[i] = to_bf16((t >= 0 && t < Tin) ? in[((long long)c * Tin + t) * N + n] : 0.f);
+}
+
+// 1-D col2im: d_in[c][t][n] = sum over (j, k) with j*S + k - P = t of dcol[c*KT + k][j*N + n]
+__global__ void k_col2im1(const float* __restrict__ dcol, float* __restrict__ din, int C, int Tin, int Tout,
+                          int KT, int S, int P, long long N) {
+  const long long total = (long long)C * Tin * N;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int c = (int)(i / ((long long)Tin * N));
+  const long long q = i % ((long long)Tin * N);
+  const int t = (int)(q / N);
+  const long long n = q % N;
+  float s = 0.f;
+  for (int k = 0; k < KT; ++k) {
+    const int jt = t + P - k;
+    if (jt < 0 || jt % S) continue;
+    const int j = jt / S;
+    if (j >= Tout) continue;
+    s += dcol[(long long)(c * KT + k) * Tout * N + (long long)j * N + n];
+  }
+  din[i] = s;
+}
+
+// ------------------------------------------------------------ elementwise
+__global__ void k_bias_act(float* __restrict__ Y, const float* __restrict__ bias, int C, long long N, int relu) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)C * N) return;
+  float v = Y[i] + bias[i / N];
+  Y[i] = relu ? fmaxf(v, 0.f) : v;
+}
+
+// dY *= [Y > 0] (ReLU backward through the stored output)
+__global__ void k_relu_bwd(float* __restrict__ dY, const float* __restrict__ Y, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !(Y[i] > 0.f)) dY[i] = 0.f;
+}
+
+// db[c] (+)= sum_n dY[c][n], one block per channel, fixed order
+__global__ void k_bias_grad(const float* __restrict__ dY, float* __restrict__ db, long long N, int accumulate) {
+  __shared__ float sh[256];
+  const int c = blockIdx.x;
+  float s = 0.f;
+  for (long long n = threadIdx.x; n < N; n += 256) s += dY[(long long)c * N + n];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[c] = accumulate ? db[c] + sh[0] : sh[0];
+}
+
+// 2x2 max pool (H, W even): Y[c][b][i][j] = max over the 2x2 block; arg = 0..3
+__global__ void k_pool(const float* __restrict__ X, float* __restrict__ Y, uint8_t* __restrict__ arg, int CB,
+                       int H, int W) {
+  const int h = H / 2, w = W / 2;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)CB * h * w) return;
+  const long long cb = i / (h * w);
+  const int yx = (int)(i % (h * w)), y = yx / w, x = yx % w;
+  const float* s = X + cb * H * W + (2 * y) * W + 2 * x;
+  float best = s[0];
+  int a = 0;
+  if (s[1] > best) { best = s[1]; a = 1; }
+  if (s[W] > best) { best = s[W]; a = 2; }
+  if (s[W + 1] > best) { best = s[W + 1]; a = 3; }
+  Y[i] = best;
+  arg[i] = (uint8_t)a;
+}
+
+// dX (+)= dY routed to the argmax position
+__global__ void k_pool_bwd(const float* __restrict__ dY, const uint8_t* __restrict__ arg, float* __restrict__ dX,
+                           int CB, int H, int W, int accumulate) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)CB * H * W) return;
+  const long long cb = i / (H * W);
+  const int yx = (int)(i % (H * W)), y = yx / W, x = yx % W;
+  const int h = H / 2, w = W / 2;
+  const long long o = cb * h * w + (y / 2) * w + (x / 2);
+  const int a = (y & 1) * 2 + (x & 1);
+  const float v = arg[o] == a ? dY[o] : 0.f;
+  dX[i] = accumulate ? dX[i] + v : v;
+}
+
+// transposed 2x2 stride-2 convolution, scatter of Z[(co*4 + a*2 + b)][n*hw + i*w + j]
+// to Y[co][n][2i + a][2j + b] plus bias
+__global__ void k_up_scatter(const float* __restrict__ Z, const float* __restrict__ bias, float* __restrict__ Y,
+                             int Co, int Bn, int h, int w) {
+  const int H = 2 * h, W = 2 * w;
+  const long long tot = (long long)Co * Bn * H * W;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= tot) return;
+  const int co = (int)(i / ((long long)Bn * H * W));
+  const long long q = i % ((long long)Bn * H * W);
+  const int n = (int)(q / (H * W)), yx = (int)(q % (H * W)), y = yx / W, x = yx % W;
+  const int a = y & 1, bb = x & 1;
+  Y[i] = Z[(long long)(co * 4 + a * 2 + bb) * Bn * h * w + (long long)n * h * w + (y / 2) * w + x / 2] + bias[co];
+}
+
+// backward of the scatter: dZ[(co*4 + a*2 + b)][n*hw + i*w + j] = dY[co][n][2i + a][2j + b]
+__global__ void k_up_gather(const float* __restrict__ dY, float* __restrict__ dZ, int Co, int Bn, int h, int w) {
+  const long long tot = (long long)Co * 4 * Bn * h * w;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= tot) return;
+  const long long hw = (long long)h * w;
+  const int r = (int)(i / (Bn * hw));
+  const long long q = i % (Bn * hw);
+  const int co = r / 4, a = (r % 4) / 2, bb = r % 2;
+  const int n = (int)(q / hw), ij = (int)(q % hw), y = ij / w, x = ij % w;
+  dZ[i] = dY[(long long)co * Bn * 4 * hw + (long long)n * 4 * hw + (2 * y + a) * (2 * w) + 2 * x + bb];
+}
+
+__global__ void k_copy(const float* __restrict__ s, float* __restrict__ d, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+
+__global__ void k_add(float* __restrict__ d, const float* __restrict__ s, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] += s[i];
+}
+
+// sigmoid + binary cross-entropy on logits z with targets y:
+// loss_i = max(z, 0) - z y + log(1 + exp(-|z|)); dz = (sigmoid(z) - y) / n;
+// prob = sigmoid(z); per-block loss partials (summed in order on the host)
+__global__ void k_bce(const float* __restrict__ z, const float* __restrict__ y, float* __restrict__ dz,
+                      float* __restrict__ prob, float* __restrict__ part, long long n) {
+  __shared__ float sh[256];
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.f;
+  if (i < n) {
+    const float zi = z[i];
+    const float p = 1.f / (1.f + expf(-zi));
+    if (prob) prob[i] = p;
+    if (y) {
+      const float yi = y[i];
+      l = fmaxf(zi, 0.f) - zi * yi + log1pf(expf(-fabsf(zi)));
+      if (dz) dz[i] = (p - yi) / (float)n;
+    }
+  }
+  if (!part) return;
+  sh[threadIdx.x] = l;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// RMSProp on FP32 master weights, then refresh the BF16 copy
+__global__ void k_rmsprop(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ v,
+                          uint16_t* __restrict__ wb, long long n, float lr, float rho, float eps) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float vi = rho * v[i] + (1.f - rho) * gi * gi;
+  v[i] = vi;
+  const float wi = w[i] - lr * gi / (sqrtf(vi) + eps);
+  w[i] = wi;
+  wb[i] = to_bf16(wi);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ w, uint16_t* __restrict__ wb, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) wb[i] = to_bf16(w[i]);
+}
+
+inline dim3 grid1(long long n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t gemm(const GemmOp& g, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  const int splits = g.splits < 1 ? 1 : g.splits;
+  int kchunk = (g.K + splits - 1) / splits;
+  kchunk = (kchunk + GK - 1) / GK * GK;
+  const int z = (g.K + kchunk - 1) / kchunk;
+  dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT, z > 0 ? z : 1);
+  float* out = z > 1 ? g.scratch : g.C;
+  const int acc = z > 1 ? 0 : g.accumulate;
+  if (g.a_bf16 && g.b_bf16)
+    hipLaunchKernelGGL((k_gemm<uint16_t, uint16_t>), grid, dim3(256), 0, st, (const uint16_t*)g.A, g.sam, g.sak,
+                       (const uint16_t*)g.B, g.sbk, g.sbn, out, (long long)g.N, g.M, g.N, g.K, kchunk, acc);
+  else if (g.a_bf16)
+    hipLaunchKernelGGL((k_gemm<uint16_t, float>), grid, dim3(256), 0, st, (const uint16_t*)g.A, g.sam, g.sak,
+                       (const float*)g.B, g.sbk, g.sbn, out, (long long)g.N, g.M, g.N, g.K, kchunk, acc);
+  else if (g.b_bf16)
+    hipLaunchKernelGGL((k_gemm<float, uint16_t>), grid, dim3(256), 0, st, (const float*)g.A, g.sam, g.sak,
+                       (const uint16_t*)g.B, g.sbk, g.sbn, out, (long long)g.N, g.M, g.N, g.K, kchunk, acc);
+  else
+    hipLaunchKernelGGL((k_gemm<float, float>), grid, dim3(256), 0, st, (const float*)g.A, g.sam, g.sak,
+                       (const float*)g.B, g.sbk, g.sbn, out, (long long)g.N, g.M, g.N, g.K, kchunk, acc);
+  if (z > 1) {
+    const long long MN = (long long)g.M * g.N;
+    hipLaunchKernelGGL(k_splitk_reduce, grid1(MN), dim3(256), 0, st, g.scratch, g.C, MN, z, g.accumulate);
+  }
+  return hipGetLastError();
+}
+
+#define L1(kernel, n, ...) hipLaunchKernelGGL(kernel, grid1(n), dim3(256), 0, st, __VA_ARGS__)
+
+void im2col3(const float* X, uint16_t* col, int C, int Bn, int H, int W, hipStream_t st) {
+  L1(k_im2col3, (long long)C * 9 * Bn * H * W, X, col, C, Bn, H, W);
+}
+void col2im3(const float* dcol, float* dX, int C, int Bn, int H, int W, bool acc, hipStream_t st) {
+  L1(k_col2im3, (long long)C * Bn * H * W, dcol, dX, C, Bn, H, W, (int)acc);
+}
+void tnorm(const uint16_t* frames, float* out, int Bn, int L, long long HW, hipStream_t st) {
+  L1(k_tnorm, (long long)Bn * HW, frames, out, Bn, L, HW);
+}
+void im2col1(const float* in, uint16_t* col, int C, int Tin, int Tout, int KT, int S, int P, long long N,
+             hipStream_t st) {
+  L1(k_im2col1, (long long)C * KT * Tout * N, in, col, C, Tin, Tout, KT, S, P, N);
+}
+void col2im1(const float* dcol, float* din, int C, int Tin, int Tout, int KT, int S, int P, long long N,
+             hipStream_t st) {
+  L1(k_col2im1, (long long)C * Tin * N, dcol, din, C, Tin, Tout, KT, S, P, N);
+}
+void bias_act(float* Y, const float* b, int C, long long N, bool relu, hipStream_t st) {
+  L1(k_bias_act, (long long)C * N, Y, b, C, N, (int)relu);
+}
+void relu_bwd(float* dY, const float* Y, long long n, hipStream_t st) { L1(k_relu_bwd, n, dY, Y, n); }
+void bias_grad(const float* dY, float* db, int C, long long N, hipStream_t st) {
+  hipLaunchKernelGGL(k_bias_grad, dim3(C), dim3(256), 0, st, dY, db, N, 0);
+}
+void pool(const float* X, float* Y, uint8_t* arg, int CB, int H, int W, hipStream_t st) {
+  L1(k_pool, (long long)CB * (H / 2) * (W / 2), X, Y, arg, CB, H, W);
+}
+void pool_bwd(const float* dY, const uint8_t* arg, float* dX, int CB, int H, int W, bool acc, hipStream_t st) {
+  L1(k_pool_bwd, (long long)CB * H * W, dY, arg, dX, CB, H, W, (int)acc);
+}
+void up_scatter(const float* Z, const float* b, float* Y, int Co, int Bn, int h, int w, hipStream_t st) {
+  L1(k_up_scatter, (long long)Co * Bn * 4 * h * w, Z, b, Y, Co, Bn, h, w);
+}
+void up_gather(const float* dY, float* dZ, int Co, int Bn, int h, int w, hipStream_t st) {
+  L1(k_up_gather, (long long)Co * 4 * Bn * h * w, dY, dZ, Co, Bn, h, w);
+}
+void copy(const float* s, float* d, long long n, hipStream_t st) { L1(k_copy, n, s, d, n); }
+void add(float* d, const float* s, long long n, hipStream_t st) { L1(k_add, n, d, s, n); }
+void bce(const float* z, const float* y, float* dz, float* prob, float* part, long long n, hipStream_t st) {
+  L1(k_bce, n, z, y, dz, prob, part, n);
+}
+void rmsprop(float* w, const float* g, float* v, uint16_t* wb, long long n, float lr, float rho, float eps,
+             hipStream_t st) {
+  L1(k_rmsprop, n, w, g, v, wb, n, lr, rho, eps);
+}
+void to_bf16_copy(const float* w, uint16_t* wb, long long n, hipStream_t st) { L1(k_to_bf16, n, w, wb, n); }
+
+}  // namespace nn
+}  // namespace seg

@@ -52,6 +52,21 @@ struct KParams {
   double w[NTAP];
 };
 
+struct BatchSlot {
+  KParams p;
+  int ntile;   // tiles per segment
+  int item0;   // first work item of this slot
+  int quad;    // quad loader usable (W % 4 == 0 and W >= 16)
+  int pad;
+};
+
+struct BatchTable {
+  int nslots;
+  int total;   // work items over all slots
+  int pad[2];
+  BatchSlot slot[kMaxBatch];
+};
+
 __device__ __forceinline__ int reflect(int j, int n) {
   const int m = 2 * n;
   j %= m;
@@ -138,28 +153,24 @@ __device__ __forceinline__ void unpack4(uint2 v, bool rev, int (&x)[4]) {
   x[3] = rev ? a : d;
 }
 
-template <bool QUAD>
-__global__ __launch_bounds__(NT, 2) void k_block_stats(KParams p) {
-  __shared__ float Dl[DH * DW];
-  __shared__ float Rl[DH * DW];
-  __shared__ float Ul[TH * DW];
-  __shared__ float4 Wl[CH * NT];
+struct Smem {
+  float Dl[DH * DW];
+  float Rl[DH * DW];
+  float Ul[TH * DW];
+  float4 Wl[CH * NT];
+};
 
+// One (segment sl, tile) work item of one recording.
+template <bool QUAD>
+__device__ __forceinline__ void block_body(const KParams& p, int sl, int tile, Smem& sm) {
+  float* Dl = sm.Dl;
+  float* Rl = sm.Rl;
+  float* Ul = sm.Ul;
+  float4* Wl = sm.Wl;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int tiles_x = (p.W + TW - 1) / TW;
-  const int tiles_y = (p.H + TH - 1) / TH;
-  const int ntile = tiles_x * tiles_y;
-  const int nblk = ntile * p.nseg;
-  // Blocks are dealt round-robin over the 8 XCDs; give every XCD a
-  // contiguous range of (segment, tile) pairs so that neighbouring tiles of a
-  // segment share their halo rows in one L2.
-  const int per = (nblk + 7) / 8;
-  const int logical = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (logical >= nblk) return;
-  const int sl = logical / ntile;
-  const int tile = logical - sl * ntile;
   const int ty0 = (tile / tiles_x) * TH;
   const int tx0 = (tile % tiles_x) * TW;
   const long long M = (long long)p.H * p.W;
@@ -366,6 +377,46 @@ __global__ __launch_bounds__(NT, 2) void k_block_stats(KParams p) {
   }
 }
 
+template <bool QUAD>
+__global__ __launch_bounds__(NT, 2) void k_block_stats(KParams p) {
+  __shared__ Smem sm;
+  const int tiles_x = (p.W + TW - 1) / TW;
+  const int tiles_y = (p.H + TH - 1) / TH;
+  const int ntile = tiles_x * tiles_y;
+  const int nblk = ntile * p.nseg;
+  // Blocks are dealt round-robin over the 8 XCDs; give every XCD a
+  // contiguous range of (segment, tile) pairs so that neighbouring tiles of a
+  // segment share their halo rows in one L2.
+  const int per = (nblk + 7) / 8;
+  const int logical = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (logical >= nblk) return;
+  const int sl = logical / ntile;
+  block_body<QUAD>(p, sl, logical - sl * ntile, sm);
+}
+
+// Serving: one persistent launch over the work items of several recordings
+// described by a device-side slot table (so the launch can be captured once
+// in a graph and replayed after the table is rewritten).
+__global__ __launch_bounds__(NT, 2) void k_block_stats_batch(const BatchTable* __restrict__ tab) {
+  __shared__ Smem sm;
+  const int ns = tab->nslots;
+  const int total = tab->total;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    int s = 0;
+    while (s + 1 < ns && tab->slot[s + 1].item0 <= item) ++s;
+    const BatchSlot& bs = tab->slot[s];
+    const KParams p = bs.p;
+    const int local = item - bs.item0;
+    const int sl = local / bs.ntile;
+    const int tile = local - sl * bs.ntile;
+    if (bs.quad)
+      block_body<true>(p, sl, tile, sm);
+    else
+      block_body<false>(p, sl, tile, sm);
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 hipError_t launch_block_stats(const StreamLaunch& a, hipStream_t st) {
@@ -391,6 +442,47 @@ hipError_t launch_block_stats(const StreamLaunch& a, hipStream_t st) {
     hipLaunchKernelGGL(k_block_stats<true>, dim3((unsigned)(per * 8)), dim3(NT), 0, st, p);
   else
     hipLaunchKernelGGL(k_block_stats<false>, dim3((unsigned)(per * 8)), dim3(NT), 0, st, p);
+  return hipGetLastError();
+}
+
+size_t batch_table_bytes() { return sizeof(BatchTable); }
+
+// Fill the host copy of the slot table; returns the number of work items.
+int fill_batch_table(void* host_table, const StreamLaunch* launches, int count) {
+  BatchTable* t = static_cast<BatchTable*>(host_table);
+  int items = 0, ns = 0;
+  for (int k = 0; k < count; ++k) {
+    const StreamLaunch& a = launches[k];
+    if (a.nseg <= 0) continue;
+    BatchSlot& b = t->slot[ns++];
+    b.p.src0 = a.src0;
+    b.p.src1 = a.src1;
+    b.p.n0 = a.n0;
+    b.p.H = a.H;
+    b.p.W = a.W;
+    b.p.seg0 = a.seg0;
+    b.p.nseg = a.nseg;
+    b.p.T = a.T;
+    b.p.S = a.S;
+    b.p.D = a.D;
+    b.p.U = a.U;
+    b.p.P = a.P;
+    b.p.plane = a.plane;
+    for (int j = 0; j < NTAP; ++j) b.p.w[j] = a.w[j];
+    b.ntile = ((a.W + TW - 1) / TW) * ((a.H + TH - 1) / TH);
+    b.item0 = items;
+    b.quad = (a.W % 4 == 0 && a.W >= 16) ? 1 : 0;
+    b.pad = 0;
+    items += b.ntile * a.nseg;
+  }
+  t->nslots = ns;
+  t->total = items;
+  return items;
+}
+
+hipError_t launch_block_stats_batch(const void* dev_table, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_stats_batch, dim3(grid), dim3(NT), 0, st,
+                     static_cast<const BatchTable*>(dev_table));
   return hipGetLastError();
 }
 

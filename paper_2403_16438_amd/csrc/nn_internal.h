@@ -1,0 +1,51 @@
+// Internal declarations of the surrogate detector's kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace seg {
+namespace nn {
+
+// C (+)= op(A) op(B), operands FP32 or BF16 (given by the flags), FP32 out,
+// row-major C with ldc = N. splits > 1 splits K over blocks; the partials go
+// to `scratch` (splits * M * N floats) and are summed in order.
+struct GemmOp {
+  const void* A;
+  long long sam, sak;
+  bool a_bf16;
+  const void* B;
+  long long sbk, sbn;
+  bool b_bf16;
+  float* C;
+  int M, N, K;
+  int splits;
+  float* scratch;
+  bool accumulate;
+};
+hipError_t gemm(const GemmOp& g, hipStream_t st);
+
+void im2col3(const float* X, uint16_t* col, int C, int Bn, int H, int W, hipStream_t st);
+void col2im3(const float* dcol, float* dX, int C, int Bn, int H, int W, bool acc, hipStream_t st);
+void tnorm(const uint16_t* frames, float* out, int Bn, int L, long long HW, hipStream_t st);
+void im2col1(const float* in, uint16_t* col, int C, int Tin, int Tout, int KT, int S, int P, long long N,
+             hipStream_t st);
+void col2im1(const float* dcol, float* din, int C, int Tin, int Tout, int KT, int S, int P, long long N,
+             hipStream_t st);
+void bias_act(float* Y, const float* b, int C, long long N, bool relu, hipStream_t st);
+void relu_bwd(float* dY, const float* Y, long long n, hipStream_t st);
+void bias_grad(const float* dY, float* db, int C, long long N, hipStream_t st);
+void pool(const float* X, float* Y, uint8_t* arg, int CB, int H, int W, hipStream_t st);
+void pool_bwd(const float* dY, const uint8_t* arg, float* dX, int CB, int H, int W, bool acc, hipStream_t st);
+void up_scatter(const float* Z, const float* b, float* Y, int Co, int Bn, int h, int w, hipStream_t st);
+void up_gather(const float* dY, float* dZ, int Co, int Bn, int h, int w, hipStream_t st);
+void copy(const float* s, float* d, long long n, hipStream_t st);
+void add(float* d, const float* s, long long n, hipStream_t st);
+void bce(const float* z, const float* y, float* dz, float* prob, float* part, long long n, hipStream_t st);
+void rmsprop(float* w, const float* g, float* v, uint16_t* wb, long long n, float lr, float rho, float eps,
+             hipStream_t st);
+void to_bf16_copy(const float* w, uint16_t* wb, long long n, hipStream_t st);
+
+}  // namespace nn
+}  // namespace seg

@@ -94,7 +94,7 @@ Layout make_layout(const seg_config& c) {
   l.nmf_F = take(M * kMaxRank * 8);
   l.nmf_G = take(M * kMaxRank * 8);
   l.nmf_A = take(l.Ccap * kMaxRank * K * 8);
-  l.nmf_W = take(l.Ccap * (kMaxRank + 2) * K * 8);
+  l.nmf_W = take(l.Ccap * 2 * K * 8);
   l.nmf_N = take(l.Ccap * 4);
   l.cmom = take(5 * M * 8);
   l.total = o;
@@ -377,6 +377,9 @@ int seg_finalize(seg_session* s, void* stream) {
     na.max_rank = (int)c.nmf_max_rank;
     na.sweeps = (int)c.nmf_sweeps;
     na.delta = (double)c.spa_delta;
+    int max_mc = 0;
+    for (int k = 0; k < ncomp; ++k) max_mc = std::max(max_mc, coff[k + 1] - coff[k]);
+    seg::plan_nmf(na, max_mc);
     if ((e = fail(s, seg::launch_nmf(na, st)))) return e;
     const size_t npx = pix.size();
     std::vector<int> N(ncomp);
@@ -504,6 +507,158 @@ int seg_get_segment_maps(seg_session* s, int kind, uint32_t first, uint32_t coun
 
 int seg_destroy(seg_session* s) {
   delete s;
+  return SEG_OK;
+}
+
+}  // extern "C"
+
+struct seg_batch {
+  uint32_t max_slots;
+  void* dev_table;
+  void* host_table;      // pinned
+  int device;
+  int grid;              // persistent grid of the captured launch
+  hipStream_t capture;   // private stream used for the capture
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  hipEvent_t copied;     // the last table upload has completed
+  bool have_copy;
+};
+
+extern "C" {
+
+int seg_batch_bytes(uint32_t max_slots, size_t* bytes) {
+  if (!bytes || max_slots < 1 || max_slots > (uint32_t)seg::kMaxBatch) return SEG_E_INVAL;
+  *bytes = (seg::batch_table_bytes() + 255) & ~size_t(255);
+  return SEG_OK;
+}
+
+int seg_batch_create(uint32_t max_slots, void* dev_table, size_t bytes, seg_batch** out) {
+  if (!out || !dev_table) return SEG_E_INVAL;
+  *out = nullptr;
+  size_t need = 0;
+  int e = seg_batch_bytes(max_slots, &need);
+  if (e) return e;
+  if (bytes < need) return SEG_E_CAPACITY;
+  if (reinterpret_cast<uintptr_t>(dev_table) & 255) return SEG_E_INVAL;
+  seg_batch* b = new (std::nothrow) seg_batch();
+  if (!b) return SEG_E_INVAL;
+  b->max_slots = max_slots;
+  b->dev_table = dev_table;
+  b->have_copy = false;
+  int cus = 256;
+  if (hipGetDevice(&b->device) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess ||
+      hipHostMalloc(&b->host_table, seg::batch_table_bytes(), hipHostMallocDefault) != hipSuccess) {
+    delete b;
+    return SEG_E_DEVICE;
+  }
+  std::memset(b->host_table, 0, seg::batch_table_bytes());
+  b->grid = 2 * cus;  // two resident workgroups per CU
+  bool ok = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    const hipError_t le = seg::launch_block_stats_batch(b->dev_table, b->grid, b->capture);
+    const hipError_t ce = hipStreamEndCapture(b->capture, &b->graph);
+    ok = le == hipSuccess && ce == hipSuccess;
+  }
+  ok = ok && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+  if (!ok) {
+    (void)hipHostFree(b->host_table);
+    delete b;
+    return SEG_E_DEVICE;
+  }
+  *out = b;
+  return SEG_OK;
+}
+
+int seg_push_batch(seg_batch* b, seg_session* const* sessions, const uint16_t* const* dev_frames,
+                   const uint32_t* n_frames, uint32_t count, void* stream) {
+  if (!b || (count && (!sessions || !dev_frames || !n_frames)) || count > b->max_slots) return SEG_E_INVAL;
+  // validate everything first: on error nothing is pushed
+  for (uint32_t k = 0; k < count; ++k) {
+    seg_session* s = sessions[k];
+    if (!s) return SEG_E_INVAL;
+    if (s->state == State::Failed) return SEG_E_DEVICE;
+    if (s->state != State::Open) return SEG_E_STATE;
+    if (s->device != b->device) return SEG_E_INVAL;
+    if (n_frames[k] && !dev_frames[k]) return SEG_E_INVAL;
+    if (s->frames + n_frames[k] > s->cfg.max_frames) return SEG_E_CAPACITY;
+    for (uint32_t j = 0; j < k; ++j)
+      if (sessions[j] == s) return SEG_E_INVAL;
+  }
+  if (hipSetDevice(b->device) != hipSuccess) return SEG_E_DEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<seg::StreamLaunch> ls(count);
+  for (uint32_t k = 0; k < count; ++k) {
+    seg_session* s = sessions[k];
+    const uint32_t total = s->tail_n + n_frames[k];
+    seg::StreamLaunch& a = ls[k];
+    a = seg::StreamLaunch{};
+    a.src0 = at<uint16_t>(s, s->lay.tail);
+    a.src1 = dev_frames[k];
+    a.n0 = s->tail_n;
+    a.H = (int)s->cfg.height;
+    a.W = (int)s->cfg.width;
+    a.seg0 = (int)s->K;
+    a.nseg = (int)(total / seg::kSegLen);
+    a.T = at<float>(s, s->lay.T);
+    a.S = at<float>(s, s->lay.S);
+    a.D = at<float>(s, s->lay.D);
+    a.U = at<float>(s, s->lay.U);
+    a.P = at<float>(s, s->lay.P);
+    a.plane = (long long)s->Kmax * s->M;
+    a.w = s->w;
+  }
+  // the previous upload must have left the pinned table before it is rewritten
+  if (b->have_copy && hipEventSynchronize(b->copied) != hipSuccess) return SEG_E_DEVICE;
+  const int items = seg::fill_batch_table(b->host_table, ls.data(), (int)count);
+  if (items > 0) {
+    if (hipMemcpyAsync(b->dev_table, b->host_table, seg::batch_table_bytes(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipEventRecord(b->copied, st) != hipSuccess)
+      return SEG_E_DEVICE;
+    b->have_copy = true;
+    if (hipGraphLaunch(b->exec, st) != hipSuccess) return SEG_E_DEVICE;
+  }
+  // tails and counters, as in seg_push_frames
+  for (uint32_t k = 0; k < count; ++k) {
+    seg_session* s = sessions[k];
+    const uint32_t n = n_frames[k];
+    if (n == 0) continue;
+    const long long M = s->M;
+    const uint32_t total = s->tail_n + n;
+    const uint32_t nseg = total / seg::kSegLen;
+    const uint32_t rem = total - nseg * seg::kSegLen;
+    uint16_t* tail = at<uint16_t>(s, s->lay.tail);
+    hipError_t he = hipSuccess;
+    if (nseg > 0) {
+      if (rem)
+        he = hipMemcpyAsync(tail, dev_frames[k] + (size_t)(n - rem) * M, (size_t)rem * M * 2,
+                            hipMemcpyDeviceToDevice, st);
+    } else {
+      he = hipMemcpyAsync(tail + (size_t)s->tail_n * M, dev_frames[k], (size_t)n * M * 2,
+                          hipMemcpyDeviceToDevice, st);
+    }
+    if (fail(s, he)) return SEG_E_DEVICE;
+    s->K += nseg;
+    s->tail_n = rem;
+    s->frames += n;
+  }
+  return SEG_OK;
+}
+
+int seg_batch_destroy(seg_batch* b) {
+  if (!b) return SEG_OK;
+  (void)hipSetDevice(b->device);
+  if (b->have_copy) (void)hipEventSynchronize(b->copied);
+  (void)hipGraphExecDestroy(b->exec);
+  (void)hipGraphDestroy(b->graph);
+  (void)hipEventDestroy(b->copied);
+  (void)hipStreamDestroy(b->capture);
+  (void)hipHostFree(b->host_table);
+  delete b;
   return SEG_OK;
 }
 

@@ -16,6 +16,7 @@ constexpr int kMaxRadius = 12;    // smoothing taps |k| <= 12
 constexpr int kMaxRank = 8;       // NMF rank cap per component
 constexpr int kMaxDim = 2048;     // frame height / width limit
 constexpr int kMaxSegments = 4096;
+constexpr int kMaxBatch = 64;     // sessions per batched launch
 
 // Offsets (bytes) of every array inside the caller's workspace.
 struct Layout {
@@ -49,7 +50,7 @@ struct Layout {
   size_t nmf_A;     // f64 [Ccap][kMaxRank][Kmax]
   size_t nmf_N;     // i32 [Ccap] rank per component
   size_t nmf_G;     // f64 [M][kMaxRank] P A^T and SPA direction
-  size_t nmf_W;     // f64 [Ccap][kMaxRank + 2][Kmax] F^T P, column norms, projections
+  size_t nmf_W;     // f64 [Ccap][2][Kmax] SPA column flags and projections
   size_t cmom;      // f64 [5][M] pooled co-moments
   size_t reg_root;  // i32 [Rcap]
   size_t total;
@@ -107,6 +108,10 @@ struct StreamLaunch {
   const double* w;  // 2 * kMaxRadius + 1 taps (zero beyond the radius)
 };
 hipError_t launch_block_stats(const StreamLaunch& a, hipStream_t st);
+// serving: slot table for one persistent launch over several recordings
+size_t batch_table_bytes();
+int fill_batch_table(void* host_table, const StreamLaunch* launches, int count);
+hipError_t launch_block_stats_batch(const void* dev_table, int grid, hipStream_t st);
 
 struct FinalizeArgs {
   int H, W, M, K, Kmax;
@@ -151,7 +156,12 @@ struct NmfArgs {
   int* N;
   int max_rank, sweeps;
   double delta;
+  int Q;                 // pixel partitions of the column sums
+  bool lds_A, lds_F;     // A (and the partial sums) / F held in LDS
+  size_t lds_bytes;      // dynamic LDS per workgroup
 };
+// LDS plan for the NMF given the largest component and the segment count
+void plan_nmf(NmfArgs& a, int max_mc);
 hipError_t launch_nmf(const NmfArgs& a, hipStream_t st);
 
 }  // namespace seg
