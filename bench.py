@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--sessions", type=int, default=16)
     ap.add_argument("--blocks", type=int, default=20)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also copy the resident video once (a plain copy kernel of known size, "
+                         "to calibrate hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs the segmentation of a recording "
@@ -130,6 +133,11 @@ def main():
     sess0 = Session(H, W, T, dev)
     ws = sess0.workspace
     sess0.close()
+    if args.copy_probe:
+        vcopy = vdev.clone()
+        torch.cuda.synchronize()
+        log(f"copy probe: {vdev.numel() * 2} bytes read and written")
+        del vcopy
 
     def step():
         s = Session(H, W, T, dev, workspace=ws)

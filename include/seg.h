@@ -49,7 +49,10 @@ extern "C" {
 #define SEG_E_NOMODEL  -6  /* surrogate detector selected but no model loaded */
 
 /* detectors */
-#define SEG_DET_PLAIN 0
+#define SEG_DET_PLAIN     0  /* noise-normalised max - median events (Eq. 2)        */
+#define SEG_DET_SURROGATE 1  /* learned spiking-pixel maps (seg_nn.h, Sec. III-C);
+                                events where the probability >= event_z, NMF on the
+                                probabilities; height and width multiples of 4     */
 
 /* image kinds for seg_get_image (all [height][width]) */
 #define SEG_IMG_MEAN        0  /* float: mean of S_i over segments (Eq. 1)         */
@@ -73,7 +76,8 @@ typedef struct seg_config {
   uint32_t max_frames;      /* capacity of one session; sizes the workspace        */
   float    gauss_sigma;     /* sd of the smoothing Gaussian, 3 px (Sec. III-B)     */
   uint32_t gauss_radius;    /* taps |k| <= radius, 1..12 (12 = 4 sigma)            */
-  float    event_z;         /* theta: event when T_i / sigma >= theta (5.0)        */
+  float    event_z;         /* theta: event when T_i / sigma >= theta (5.0); for the
+                               surrogate, when the probability >= theta (0.5)     */
   uint32_t min_event_segs;  /* c_min: b = [sum_i b_i >= c_min] (2; 1 = the OR)     */
   uint32_t area_min, area_max;  /* region area bounds in pixels (16, 1600)         */
   float    solidity_min;    /* area / convex-hull area of pixel squares (0.75)     */
@@ -83,10 +87,11 @@ typedef struct seg_config {
   float    spa_delta;       /* SPA stops below delta x the first pick's norm (0.3) */
   float    footprint_level; /* mask = footprint >= level x its peak (0.25)         */
   float    sigma_floor;     /* no event where sigma < floor (1e-3)                 */
-  uint32_t detector;        /* SEG_DET_PLAIN                                      */
+  uint32_t detector;        /* SEG_DET_PLAIN or SEG_DET_SURROGATE                 */
 } seg_config;
 
 typedef struct seg_session seg_session;   /* opaque */
+struct seg_nn;                            /* the surrogate network, seg_nn.h */
 
 /* Fill *out with the default configuration for height x width frames and a
  * capacity of max_frames. Errors: SEG_E_INVAL (NULL out or zero size). */
@@ -183,8 +188,8 @@ int seg_batch_create(uint32_t max_slots, void* dev_table, size_t bytes, seg_batc
 
 /* Append n_frames[k] frames (dev_frames[k], device memory) to sessions[k] for
  * k < count, as seg_push_frames would, with one graph launch on `stream` for
- * all complete segments. Sessions must be distinct, open and on the batch's
- * device. All checks happen before anything is launched: on error nothing is
+ * all complete segments. Sessions must be distinct, open, on the batch's
+ * device and use the plain detector. All checks happen before anything is launched: on error nothing is
  * pushed. Errors: SEG_E_INVAL, SEG_E_STATE, SEG_E_CAPACITY, SEG_E_DEVICE. */
 int seg_push_batch(seg_batch* b, seg_session* const* sessions,
                    const uint16_t* const* dev_frames, const uint32_t* n_frames,
@@ -192,6 +197,12 @@ int seg_push_batch(seg_batch* b, seg_session* const* sessions,
 
 /* Release the batch object (not the caller's device table). */
 int seg_batch_destroy(seg_batch* b);
+
+/* Attach the surrogate network used by a SEG_DET_SURROGATE session (before
+ * the first push). The network must have been created for the session's
+ * height and width; it is used on the push stream, one segment at a time,
+ * and must outlive the session's pushes. Errors: SEG_E_INVAL, SEG_E_STATE. */
+int seg_set_model(seg_session* s, struct seg_nn* net);
 
 /* Release the session (not the caller's workspace). NULL is a no-op. */
 int seg_destroy(seg_session* s);

@@ -85,6 +85,9 @@ int seg_nn_gemm_test(const float* A, int a_trans, const float* B, int b_trans,
                      float* C, int M, int N, int K, int splits, float* scratch,
                      void* stream);
 
+/* Batch capacity and frame size the network was created for. */
+int seg_nn_shape(const seg_nn* n, uint32_t* batch, uint32_t* height, uint32_t* width);
+
 int seg_nn_destroy(seg_nn* n);
 
 #ifdef __cplusplus

@@ -22,6 +22,7 @@ SEG_E_DEVICE = -5
 SEG_E_NOMODEL = -6
 
 SEG_DET_PLAIN = 0
+SEG_DET_SURROGATE = 1
 
 SEG_IMG_MEAN, SEG_IMG_CORR, SEG_IMG_NOISE = 0, 1, 2
 SEG_IMG_EVENT_COUNT, SEG_IMG_MASK_COUNT, SEG_IMG_LABELS = 3, 4, 5
@@ -76,6 +77,20 @@ def _load():
         "seg_batch_create": (C.c_int, [u32, P, C.c_size_t, C.POINTER(P)]),
         "seg_push_batch": (C.c_int, [P, C.POINTER(P), C.POINTER(P), C.POINTER(u32), u32, P]),
         "seg_batch_destroy": (C.c_int, [P]),
+        "seg_nn_param_count": (C.c_int, [C.POINTER(C.c_size_t)]),
+        "seg_nn_param_layout": (C.c_int, [u32, C.POINTER(u32), C.POINTER(u32), C.POINTER(C.c_size_t),
+                                          C.POINTER(C.c_size_t)]),
+        "seg_nn_workspace_bytes": (C.c_int, [u32, u32, u32, C.POINTER(C.c_size_t)]),
+        "seg_nn_create": (C.c_int, [u32, u32, u32, P, P, C.c_size_t, C.POINTER(P)]),
+        "seg_nn_sync_weights": (C.c_int, [P, P]),
+        "seg_nn_forward": (C.c_int, [P, P, u32, P, P]),
+        "seg_nn_backward": (C.c_int, [P, P, P, u32, P, C.POINTER(C.c_float), P]),
+        "seg_nn_step": (C.c_int, [P, C.c_float, C.c_float, C.c_float, P]),
+        "seg_nn_logits": (C.c_int, [P, P, P]),
+        "seg_nn_gemm_test": (C.c_int, [P, C.c_int, P, C.c_int, P, C.c_int, C.c_int, C.c_int, C.c_int, P, P]),
+        "seg_nn_destroy": (C.c_int, [P]),
+        "seg_nn_shape": (C.c_int, [P, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]),
+        "seg_set_model": (C.c_int, [P, P]),
         "seg_strerror": (C.c_char_p, [C.c_int]),
         "seg_last_error": (C.c_int, [P]),
     }
@@ -90,8 +105,8 @@ lib = _load()
 
 
 def header_functions() -> list:
-    """Names of the functions declared in include/seg.h."""
-    text = open(HEADER).read()
+    """Names of the functions declared in include/seg.h and include/seg_nn.h."""
+    text = open(HEADER).read() + open(os.path.join(os.path.dirname(HEADER), "seg_nn.h")).read()
     return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(seg_\w+)\s*\(", text, re.M)))
 
 

@@ -1,6 +1,6 @@
 """Build libseg.so (HIP kernels + C ABI) for gfx950 in the package directory.
 
-    python -m paper_2403_16438_amd.build
+    python paper_2403_16438_amd/build.py      (or __graft_entry__.build())
 
 Every call compiles from source: the compare-exchange network header is
 regenerated, then hipcc compiles and links all sources into one shared library.

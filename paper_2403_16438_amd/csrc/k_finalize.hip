@@ -119,9 +119,14 @@ __global__ void k_events(FinalizeArgs a) {
   int cnt = 0;
   for (int i = 0; i < a.K; ++i) {
     const long long g = (long long)i * a.M + x;
-    const double z = ok ? (double)a.T[g] / s : 0.0;
-    const bool e = z >= a.theta;
-    a.p[g] = (float)fmax(0.0, z - a.theta);
+    bool e;
+    if (a.prob_mode) {
+      e = (double)a.p[g] >= a.theta;   // learned probability map
+    } else {
+      const double z = ok ? (double)a.T[g] / s : 0.0;
+      e = z >= a.theta;
+      a.p[g] = (float)fmax(0.0, z - a.theta);
+    }
     a.lab[g] = e ? (int)g : -1;
     cnt += e;
   }

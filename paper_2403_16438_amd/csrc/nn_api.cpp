@@ -568,6 +568,14 @@ int seg_nn_gemm_test(const float* A, int a_trans, const float* B, int b_trans, f
   return gemm(g, static_cast<hipStream_t>(stream)) == hipSuccess ? SEG_OK : SEG_E_DEVICE;
 }
 
+int seg_nn_shape(const seg_nn* n, uint32_t* batch, uint32_t* height, uint32_t* width) {
+  if (!n) return SEG_E_INVAL;
+  if (batch) *batch = (uint32_t)n->plan.B;
+  if (height) *height = (uint32_t)n->plan.H;
+  if (width) *width = (uint32_t)n->plan.W;
+  return SEG_OK;
+}
+
 int seg_nn_destroy(seg_nn* n) {
   delete n;
   return SEG_OK;

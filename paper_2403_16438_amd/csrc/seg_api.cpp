@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "seg_internal.h"
+#include "seg_nn.h"
 
 using seg::Layout;
 using seg::State;
@@ -38,7 +39,8 @@ int check_config(const seg_config* c) {
   if (!(c->spa_delta >= 0.f) || !(c->footprint_level > 0.f && c->footprint_level <= 1.f))
     return SEG_E_INVAL;
   if (!(c->sigma_floor >= 0.f)) return SEG_E_INVAL;
-  if (c->detector != SEG_DET_PLAIN) return SEG_E_INVAL;
+  if (c->detector != SEG_DET_PLAIN && c->detector != SEG_DET_SURROGATE) return SEG_E_INVAL;
+  if (c->detector == SEG_DET_SURROGATE && (c->height % 4 || c->width % 4)) return SEG_E_INVAL;
   return SEG_OK;
 }
 
@@ -97,6 +99,7 @@ Layout make_layout(const seg_config& c) {
   l.nmf_W = take(l.Ccap * 2 * K * 8);
   l.nmf_N = take(l.Ccap * 4);
   l.cmom = take(5 * M * 8);
+  l.stage = take(c.detector == SEG_DET_SURROGATE ? (size_t)kSegLen * M * 2 : 0);
   l.total = o;
   return l;
 }
@@ -108,6 +111,34 @@ namespace {
 template <class T>
 T* at(seg_session* s, size_t off) {
   return reinterpret_cast<T*>(s->ws + off);
+}
+
+int fail(seg_session* s, hipError_t e);
+
+// Surrogate detector: for each segment completed by this push, stage its 50
+// frames contiguously (they may straddle the carried tail and the caller's
+// buffer) and write the network's probability map into p[K + j].
+int surrogate_maps(seg_session* s, const uint16_t* dev_frames, uint32_t nseg, hipStream_t st) {
+  const size_t M = s->M;
+  uint16_t* tail = at<uint16_t>(s, s->lay.tail);
+  uint16_t* stage = at<uint16_t>(s, s->lay.stage);
+  float* p = at<float>(s, s->lay.p);
+  for (uint32_t j = 0; j < nseg; ++j) {
+    const long long f0 = (long long)j * seg::kSegLen;   // first frame, counted from the tail start
+    const long long in_tail = std::max(0LL, std::min<long long>(seg::kSegLen, (long long)s->tail_n - f0));
+    hipError_t he = hipSuccess;
+    if (in_tail > 0)
+      he = hipMemcpyAsync(stage, tail + (size_t)f0 * M, (size_t)in_tail * M * 2, hipMemcpyDeviceToDevice, st);
+    if (he == hipSuccess && in_tail < seg::kSegLen) {
+      const long long from = f0 + in_tail - (long long)s->tail_n;
+      he = hipMemcpyAsync(stage + (size_t)in_tail * M, dev_frames + (size_t)from * M,
+                          (size_t)(seg::kSegLen - in_tail) * M * 2, hipMemcpyDeviceToDevice, st);
+    }
+    if (fail(s, he)) return SEG_E_DEVICE;
+    const int r = seg_nn_forward(s->net, stage, 1, p + (size_t)(s->K + j) * M, st);
+    if (r) return fail(s, hipErrorUnknown);
+  }
+  return SEG_OK;
 }
 
 int fail(seg_session* s, hipError_t e) {
@@ -187,6 +218,7 @@ int seg_create(const seg_config* cfg, void* dev_workspace, size_t bytes, seg_ses
   s->state = State::Open;
   s->error = SEG_OK;
   s->n_comp = 0;
+  s->net = nullptr;
   // smoothing taps: exp(-k^2 / (2 sigma^2)) normalised over |k| <= radius
   const int r = (int)cfg->gauss_radius;
   const double sg = (double)cfg->gauss_sigma;
@@ -205,6 +237,7 @@ int seg_push_frames(seg_session* s, const uint16_t* dev_frames, uint32_t n, void
   if (s->state != State::Open) return SEG_E_STATE;
   if (n == 0) return SEG_OK;
   if (!dev_frames) return SEG_E_INVAL;
+  if (s->cfg.detector == SEG_DET_SURROGATE && !s->net) return SEG_E_NOMODEL;
   if (s->frames + n > s->cfg.max_frames) return SEG_E_CAPACITY;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long M = s->M;
@@ -229,6 +262,7 @@ int seg_push_frames(seg_session* s, const uint16_t* dev_frames, uint32_t n, void
     a.plane = (long long)s->Kmax * M;
     a.w = s->w;
     if ((e = fail(s, seg::launch_block_stats(a, st)))) return e;
+    if (s->cfg.detector == SEG_DET_SURROGATE && (e = surrogate_maps(s, dev_frames, nseg, st))) return e;
     if (rem) {
       const uint16_t* from = dev_frames + (size_t)(n - rem) * M;
       if ((e = fail(s, hipMemcpyAsync(tail, from, (size_t)rem * M * 2, hipMemcpyDeviceToDevice, st))))
@@ -332,6 +366,7 @@ int seg_finalize(seg_session* s, void* stream) {
   a.area_max = (int)c.area_max;
   a.min_event_segs = (int)c.min_event_segs;
   a.have_moments = true;
+  a.prob_mode = c.detector == SEG_DET_SURROGATE;
   if ((e = fail(s, seg::launch_finalize_maps(a, st)))) return e;
   int ncomp = 0;
   if ((e = fail(s, hipMemcpyAsync(&ncomp, a.counters, sizeof(int), hipMemcpyDeviceToHost, st)))) return e;
@@ -510,6 +545,15 @@ int seg_destroy(seg_session* s) {
   return SEG_OK;
 }
 
+int seg_set_model(seg_session* s, struct seg_nn* net) {
+  if (!s || !net || s->cfg.detector != SEG_DET_SURROGATE) return SEG_E_INVAL;
+  if (s->state != State::Open || s->frames != 0) return SEG_E_STATE;
+  uint32_t b = 0, h = 0, w = 0;
+  if (seg_nn_shape(net, &b, &h, &w) != SEG_OK || h != s->cfg.height || w != s->cfg.width) return SEG_E_SHAPE;
+  s->net = net;
+  return SEG_OK;
+}
+
 }  // extern "C"
 
 struct seg_batch {
@@ -582,7 +626,7 @@ int seg_push_batch(seg_batch* b, seg_session* const* sessions, const uint16_t* c
     if (!s) return SEG_E_INVAL;
     if (s->state == State::Failed) return SEG_E_DEVICE;
     if (s->state != State::Open) return SEG_E_STATE;
-    if (s->device != b->device) return SEG_E_INVAL;
+    if (s->device != b->device || s->cfg.detector != SEG_DET_PLAIN) return SEG_E_INVAL;
     if (n_frames[k] && !dev_frames[k]) return SEG_E_INVAL;
     if (s->frames + n_frames[k] > s->cfg.max_frames) return SEG_E_CAPACITY;
     for (uint32_t j = 0; j < k; ++j)

@@ -53,6 +53,7 @@ struct Layout {
   size_t nmf_W;     // f64 [Ccap][2][Kmax] SPA column flags and projections
   size_t cmom;      // f64 [5][M] pooled co-moments
   size_t reg_root;  // i32 [Rcap]
+  size_t stage;     // u16 [50][M] one segment's frames for the surrogate (else 0 bytes)
   size_t total;
   size_t Rcap;      // region capacity
   size_t Ccap;      // component capacity
@@ -87,6 +88,7 @@ struct seg_session {
   seg::State state;
   int error;           // sticky error
   double w[2 * seg::kMaxRadius + 1];
+  struct seg_nn* net; // surrogate network (SEG_DET_SURROGATE)
   // results (host copies after finalize)
   uint32_t n_comp;
   std::vector<seg::Footprint> fps;
@@ -141,6 +143,7 @@ struct FinalizeArgs {
   double theta, sigma_floor, solidity_min, ecc_thr;
   int area_min, area_max, min_event_segs;
   bool have_moments;
+  bool prob_mode;  // surrogate: p holds probabilities, events are p >= theta
 };
 // pointwise images, events, per-segment regions, kept masks, aggregate,
 // canonical components; writes the component count to counters[0]

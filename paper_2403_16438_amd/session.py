@@ -43,6 +43,11 @@ class Session:
             self.handle = abi.seg_create(self.cfg, aligned, self.nbytes)
         self.H, self.W = height, width
 
+    def set_model(self, net) -> None:
+        """Attach a Surrogate (SEG_DET_SURROGATE sessions, before the first push)."""
+        abi.check(abi.lib.seg_set_model(self.handle, net.handle), "seg_set_model")
+        self.net = net   # keep it alive while the session pushes
+
     # -- streaming
     def push(self, frames: torch.Tensor, stream: torch.cuda.Stream | None = None) -> None:
         if frames.device != self.device or not frames.is_contiguous():
@@ -101,11 +106,16 @@ class Session:
             pass
 
 
-def segment_video(video: np.ndarray, block: int | None = None, **overrides) -> Session:
+def segment_video(video: np.ndarray, block: int | None = None, net=None, **overrides) -> Session:
     """Push a host uint16 video [T, H, W] (in blocks of `block` frames) and
-    finalize. Returns the finalized session."""
+    finalize. Returns the finalized session. With `net` (a Surrogate) the
+    learned detector is used (events at probability >= 0.5, c_min = 1)."""
     T, H, W = video.shape
+    if net is not None:
+        overrides = dict(dict(detector=abi.SEG_DET_SURROGATE, event_z=0.5, min_event_segs=1), **overrides)
     s = Session(H, W, max(T, 50), **overrides)
+    if net is not None:
+        s.set_model(net)
     block = block or T
     for t0 in range(0, T, block):
         s.push(to_device_frames(video[t0:t0 + block], s.device))

@@ -1,0 +1,71 @@
+"""Training of the surrogate detector on simulated segments (Sec. III-C trains
+its U-Net on synthetic videos with binary cross-entropy and RMSProp).
+
+A training example is one 50-frame segment of a 64 x 64 video drawn from the
+simulator's config-4 scenes (2,000 frames each, 1-3 neurons... see
+synth.preset(4)); its label is the ground-truth mask of the neurons that spike
+in that segment (footprint >= 0.25 of peak). Frames are rendered on the GPU
+from the scene (synth.gpu); the forward, loss, backward and RMSProp update run
+in libseg.so.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from .surrogate import Surrogate, he_init
+
+SEG = 50
+
+
+class SceneBank:
+    """n simulated training videos (config 4: 64x64x2000) on the GPU."""
+
+    def __init__(self, n: int, seed0: int = 40000, device="cuda", **overrides):
+        from synth import preset
+        from synth.gpu import GpuScene
+        self.scenes = []
+        self.labels = []
+        for k in range(n):
+            cfg = preset(4, **overrides)
+            sc = GpuScene(cfg, seed0 + k, device)
+            self.scenes.append(sc)
+            self.labels.append(torch.from_numpy(sc.truth.segment_masks(SEG).astype(np.float32)).to(device))
+        self.K = self.scenes[0].cfg.frames // SEG
+        self.H, self.W = self.scenes[0].cfg.height, self.scenes[0].cfg.width
+        self.device = torch.device(device)
+
+    def batch(self, rng, B):
+        frames = torch.empty((B, SEG, self.H, self.W), dtype=torch.int16, device=self.device)
+        labels = torch.empty((B, self.H, self.W), dtype=torch.float32, device=self.device)
+        for b in range(B):
+            k = int(rng.integers(len(self.scenes)))
+            i = int(rng.integers(self.K))
+            self.scenes[k].render(i * SEG, (i + 1) * SEG, out=frames[b])
+            labels[b] = self.labels[k][i]
+        return frames, labels
+
+
+def train(steps: int = 400, batch: int = 16, lr: float = 1e-3, n_videos: int = 200, seed: int = 0,
+          device="cuda", log=None, bank: SceneBank | None = None):
+    """Train a fresh surrogate; returns (Surrogate, losses)."""
+    bank = bank or SceneBank(n_videos, device=device)
+    net = Surrogate(batch, bank.H, bank.W, he_init(seed), device)
+    rng = np.random.default_rng(seed)
+    losses = []
+    t0 = time.time()
+    for s in range(steps):
+        frames, labels = bank.batch(rng, batch)
+        loss, _ = net.backward(frames, labels)
+        net.step(lr=lr)
+        losses.append(loss)
+        if log and (s % 50 == 0 or s == steps - 1):
+            log(f"step {s} loss {loss:.4f} ({time.time() - t0:.1f}s)")
+    return net, losses
+
+
+def for_frames(net: Surrogate, height: int, width: int, device="cuda") -> Surrogate:
+    """A batch-1 network for other frame sizes with the same weights."""
+    return Surrogate(1, height, width, net.theta(), device)

@@ -7,10 +7,12 @@ for p in (ROOT, HERE):
     if p not in sys.path:
         sys.path.insert(0, p)
 
-# Tests load the library that is built; they build it only when none exists.
-if not os.path.exists(os.path.join(ROOT, "paper_2403_16438_amd", "libseg.so")):
-    from paper_2403_16438_amd.build import build
-    build()
+# Tests load the libraries that are built; they build them only when none exists.
+if not (os.path.exists(os.path.join(ROOT, "paper_2403_16438_amd", "libseg.so"))
+        and os.path.exists(os.path.join(ROOT, "synth", "libsynth.so"))):
+    sys.path.insert(0, ROOT)
+    import __graft_entry__
+    __graft_entry__.build()
 
 
 def pytest_configure(config):

@@ -1,0 +1,96 @@
+"""Surrogate detector on the GPU: the BF16 MFMA product against an exact
+product of the BF16-rounded operands, and the network's loss and gradients
+against the FP64 reference (oracle/nn_ref.py) at the same BF16 weights."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nn_ref
+from paper_2403_16438_amd.surrogate import Surrogate, gemm_test, he_init, param_layout
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("M,N,K,at,bt,splits", [(64, 64, 32, 0, 0, 1), (37, 70, 45, 0, 0, 1),
+                                                (37, 70, 45, 1, 0, 1), (37, 70, 45, 0, 1, 1),
+                                                (5, 300, 7, 1, 1, 1), (128, 288, 4100, 0, 1, 16),
+                                                (256, 130, 96, 1, 0, 3)])
+def test_gemm_layout_and_splits(M, N, K, at, bt, splits):
+    rng = np.random.default_rng(M * 7 + N + K)
+    A = rng.standard_normal((K, M) if at else (M, K)).astype(np.float32)
+    B = rng.standard_normal((N, K) if bt else (K, N)).astype(np.float32)
+    C = gemm_test(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), bool(at), bool(bt), splits).cpu().numpy()
+    Ab = nn_ref.bf16_round(A.T if at else A)
+    Bb = nn_ref.bf16_round(B.T if bt else B)
+    ref = Ab @ Bb
+    scale = (np.abs(Ab) @ np.abs(Bb)).max()
+    assert np.abs(C - ref).max() <= 2e-6 * scale * np.sqrt(K / 32) + 1e-6
+
+
+@pytest.fixture(scope="module")
+def case():
+    rng = np.random.default_rng(11)
+    Bn, H, W = 2, 16, 16
+    frames = rng.poisson(1000, size=(Bn, 50, H, W)).astype(np.uint16)
+    frames[0, 10:12, 5:9, 5:9] += 250
+    frames[1, 30:32, 8:12, 2:6] += 250
+    labels = np.zeros((Bn, H, W), np.float32)
+    labels[0, 5:9, 5:9] = 1
+    labels[1, 8:12, 2:6] = 1
+    theta = he_init(3)
+    theta += (0.01 * rng.standard_normal(theta.size)).astype(np.float32)
+    return frames, labels, theta
+
+
+def _ref_theta(theta):
+    t = theta.astype(np.float64).copy()
+    for name, r, c, wo, bo in param_layout():
+        t[wo:wo + r * c] = nn_ref.bf16_round(theta[wo:wo + r * c])
+    return t
+
+
+def test_loss_and_gradients_vs_reference(case):
+    frames, labels, theta = case
+    sur = Surrogate(2, 16, 16, theta)
+    fd = torch.from_numpy(frames.view(np.int16)).cuda()
+    ld = torch.from_numpy(labels).cuda()
+    loss, g = sur.backward(fd, ld, want_grad=True)
+    g = g.cpu().numpy().astype(np.float64)
+    rloss, rg = nn_ref.loss_and_grad(_ref_theta(theta), frames, labels)
+    assert abs(loss - rloss) <= 1e-2 * abs(rloss), (loss, rloss)
+    # Every GEMM rounds both operands to BF16 (relative 2^-9), and forward
+    # rounding flips a few ReLU / max-pool decisions relative to FP64, so the
+    # norm-wise error grows with the number of layers a gradient crosses:
+    # measured 0.1 % at the output layer, ~1 % through the decoder, ~10 % at
+    # the first temporal layer. Directions must agree everywhere.
+    errs, cos = {}, {}
+    for name, r, c, wo, bo in param_layout():
+        sl = slice(wo, bo + (r // 4 if name in ("u2", "u1") else r))
+        den = np.linalg.norm(rg[sl])
+        errs[name] = np.linalg.norm(g[sl] - rg[sl]) / max(den, 1e-30)
+        cos[name] = float(g[sl] @ rg[sl] / max(np.linalg.norm(g[sl]) * den, 1e-30))
+    assert min(cos.values()) >= 0.99, cos
+    assert max(errs[k] for k in ("out", "d1b", "d1a", "u1", "d2b")) <= 3e-2, errs
+    assert max(errs.values()) <= 0.15, errs
+
+
+def test_forward_probabilities(case):
+    frames, labels, theta = case
+    sur = Surrogate(2, 16, 16, theta)
+    p = sur.forward(torch.from_numpy(frames.view(np.int16)).cuda()).cpu().numpy()
+    logit, _, _ = nn_ref.forward(_ref_theta(theta), frames)
+    ref = 1.0 / (1.0 + np.exp(-logit))
+    assert np.abs(p - ref).max() <= 2e-2
+
+
+def test_rmsprop_reduces_loss(case):
+    frames, labels, theta = case
+    sur = Surrogate(2, 16, 16, theta)
+    fd = torch.from_numpy(frames.view(np.int16)).cuda()
+    ld = torch.from_numpy(labels).cuda()
+    losses = []
+    for _ in range(40):
+        loss, _ = sur.backward(fd, ld)
+        losses.append(loss)
+        sur.step(lr=1e-3)
+    assert losses[-1] < 0.5 * losses[0], losses[::8]
