@@ -54,6 +54,15 @@ extern "C" {
                                 events where the probability >= event_z, NMF on the
                                 probabilities; height and width multiples of 4     */
 
+/* execution of the per-component NMF (Eq. 3); every path computes the same
+ * factorisation, they differ in the order of sums over pixels only */
+#define SEG_NMF_AUTO   0  /* split when it applies, else one workgroup per component */
+#define SEG_NMF_SINGLE 1  /* one workgroup per component                            */
+#define SEG_NMF_SPLIT  2  /* each component over several co-resident workgroups;
+                             seg_finalize fails with SEG_E_CAPACITY where the split
+                             does not apply (no cooperative launch, too many
+                             segments for LDS, more slices than compute units)     */
+
 /* image kinds for seg_get_image (all [height][width]) */
 #define SEG_IMG_MEAN        0  /* float: mean of S_i over segments (Eq. 1)         */
 #define SEG_IMG_CORR        1  /* float: 8-neighbour correlation image             */
@@ -88,6 +97,7 @@ typedef struct seg_config {
   float    footprint_level; /* mask = footprint >= level x its peak (0.25)         */
   float    sigma_floor;     /* no event where sigma < floor (1e-3)                 */
   uint32_t detector;        /* SEG_DET_PLAIN or SEG_DET_SURROGATE                 */
+  uint32_t nmf_path;        /* SEG_NMF_AUTO, SEG_NMF_SINGLE or SEG_NMF_SPLIT       */
 } seg_config;
 
 typedef struct seg_session seg_session;   /* opaque */

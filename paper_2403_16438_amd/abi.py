@@ -23,6 +23,7 @@ SEG_E_NOMODEL = -6
 
 SEG_DET_PLAIN = 0
 SEG_DET_SURROGATE = 1
+SEG_NMF_AUTO, SEG_NMF_SINGLE, SEG_NMF_SPLIT = 0, 1, 2
 
 SEG_IMG_MEAN, SEG_IMG_CORR, SEG_IMG_NOISE = 0, 1, 2
 SEG_IMG_EVENT_COUNT, SEG_IMG_MASK_COUNT, SEG_IMG_LABELS = 3, 4, 5
@@ -38,7 +39,8 @@ class seg_config(C.Structure):
                 ("solidity_min", C.c_float), ("ecc_max", C.c_float),
                 ("nmf_max_rank", C.c_uint32), ("nmf_sweeps", C.c_uint32),
                 ("spa_delta", C.c_float), ("footprint_level", C.c_float),
-                ("sigma_floor", C.c_float), ("detector", C.c_uint32)]
+                ("sigma_floor", C.c_float), ("detector", C.c_uint32),
+                ("nmf_path", C.c_uint32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

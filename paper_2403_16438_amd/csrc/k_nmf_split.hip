@@ -1,0 +1,559 @@
+// Per-component NMF P_c ~ F A (Eq. 3, Sec. III-D) with each component split
+// over several workgroups that run at the same time (cooperative launch).
+//
+// Workgroup w of component c owns a contiguous range of the component's
+// pixels (rows of P_c) and keeps those rows of P_c in LDS (FP32, exact) for
+// the whole factorisation, with an odd row stride so that both the row-wise
+// and the column-wise sweeps are free of bank conflicts. Everything that needs
+// all pixels of the component is a sum (or max) over pixels, so each
+// workgroup writes its partial over its own rows to an exchange slot in HBM,
+// the component's workgroups meet at a barrier, and each one adds the slots
+// of all workgroups in the same fixed order. They thus hold bit-identical
+// totals and take identical decisions without further communication:
+//   SPA     per step: partial squared column norms of the residual, then the
+//           partial projections onto the picked direction (two exchanges);
+//           the residual rows stay with their owner (HBM, owner-only)
+//   init    partial maxima of the picked columns (one exchange)
+//   HALS    per sweep one exchange of the partial F^T F and F^T P; every
+//           workgroup then runs the same A update (A is small and is kept
+//           whole in each workgroup's LDS), forms A A^T itself and updates
+//           the F rows it owns from its LDS rows of P_c
+//   scale   partial column maxima of F (one exchange)
+// The arithmetic is the single-workgroup kernel's (same update order, FP64,
+// clipping, zero-Gram rule); only the summation order over pixels differs.
+//
+// Barrier: a per-component arrival counter (agent-scope release/acquire).
+// The launch is cooperative, so all workgroups are resident; the wait is
+// still bounded by a wall-clock limit, after which the component is marked
+// abandoned, every workgroup of it leaves, and the error flag is set.
+#include <algorithm>
+#include <climits>
+#include <type_traits>
+
+#include "seg_internal.h"
+
+namespace seg {
+namespace {
+
+constexpr int CT = 1024;
+constexpr int CW = CT / 64;
+constexpr int R8 = kMaxRank;
+constexpr int NPAIR = R8 * (R8 + 1) / 2;
+
+__device__ __forceinline__ double wsum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// pair k of the upper triangle of an NR x NR matrix, row by row
+template <int NR>
+__device__ __forceinline__ void pair_of(int k, int& n1, int& n2) {
+  n1 = 0;
+  while (k >= NR - n1) {
+    k -= NR - n1;
+    ++n1;
+  }
+  n2 = n1 + k;
+}
+
+__device__ double block_max(double v, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double m = red[0];
+  for (int ww = 1; ww < CW; ++ww) m = fmax(m, red[ww]);
+  __syncthreads();
+  return m;
+}
+
+// argmax with lowest index on ties
+__device__ void block_argmax(double v, int idx, double* red, int* redi, double* best, int* bidx) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off);
+    const int oi = __shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+  if (lane == 0) {
+    red[w] = v;
+    redi[w] = idx;
+  }
+  __syncthreads();
+  double b = red[0];
+  int bi = redi[0];
+  for (int ww = 1; ww < CW; ++ww)
+    if (red[ww] > b || (red[ww] == b && redi[ww] < bi)) {
+      b = red[ww];
+      bi = redi[ww];
+    }
+  *best = b;
+  *bidx = bi;
+  __syncthreads();
+}
+
+// All workgroups of one component meet here; `target` is the number of
+// arrivals that completes this meeting. Returns false when the component was
+// abandoned (time limit), uniformly for the whole workgroup.
+__device__ bool meet(unsigned* arrivals, unsigned* abandoned, unsigned* error, unsigned target,
+                     long long limit, int* flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // release the workgroup's slot writes, arrive, poll without acquiring
+    // (an acquire per poll would invalidate the caches every time), then
+    // acquire once
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    const long long t0 = wall_clock64();
+    while (__hip_atomic_load(arrivals, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(abandoned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        ok = 0;
+        break;
+      }
+      if (wall_clock64() - t0 > limit) {
+        __hip_atomic_store(abandoned, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *flag = ok;
+  }
+  __syncthreads();
+  return *flag != 0;
+}
+
+__global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
+  extern __shared__ double dyn[];
+  __shared__ double red[CW];
+  __shared__ int redi[CW];
+  __shared__ double gF[R8 * R8], gA[R8 * R8];
+  __shared__ double red2[CT];   // Gram chunk sums (chunks x pairs <= CT)
+  __shared__ int picks[R8];
+  __shared__ int flag;
+  const int g = blockIdx.x, t = threadIdx.x;
+  const int c = s.wg_comp[g];
+  const int w0 = s.wg_base[c], nw = s.wg_base[c + 1] - w0, r = g - w0;
+  const int off = a.coff[c], Mc = a.coff[c + 1] - off;
+  const int mw = s.mw, lo = r * mw, ml = min(mw, Mc - lo);  // own rows [lo, lo + ml)
+  const int K = a.K, Kp = s.Kp;
+  // LDS: A [K][R8], F [mw][R8], scratch [scr], P rows [mw][Kp] (float)
+  double* A = dyn;
+  double* F = A + (size_t)K * R8;
+  double* scr = F + (size_t)mw * R8;
+  float* Pl = reinterpret_cast<float*>(scr + s.scr);
+  double* R = a.R + (long long)(off + lo) * K;  // own residual rows [ml][K], HBM
+  unsigned* arrivals = s.sync + c;
+  unsigned* abandoned = s.sync + a.ncomp + c;
+  unsigned* error = s.sync + 2 * a.ncomp;
+  unsigned ex = 0;  // exchanges done
+  auto slot = [&](int w, unsigned e) { return s.xbuf + ((size_t)(w0 + w) * 2 + (e & 1)) * s.XS; };
+#define MEET() \
+  if (!meet(arrivals, abandoned, error, (ex + 1) * (unsigned)nw, s.limit, &flag)) return
+
+  // gather own rows: consecutive threads read consecutive pixels of a plane
+  for (int e = t; e < ml * K; e += CT) {
+    const int i = e / ml, m = e - i * ml;
+    Pl[m * Kp + i] = a.p[(long long)i * a.M + a.pix[off + lo + m]];
+  }
+  __syncthreads();
+  for (int e = t; e < ml * K; e += CT) {
+    const int m = e / K, i = e - m * K;
+    R[e] = (double)Pl[m * Kp + i];
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- SPA
+  double* vec = scr;      // [K] projections
+  double* U = scr + K;    // [mw] own entries of the picked direction
+  double* nz = A;         // [K] nonzero-column flags (A is free until HALS)
+  int N = 0;
+  double ref = 0.0;
+  while (N < a.max_rank) {
+    {
+      double* xs = slot(r, ex);
+      for (int i = t; i < K; i += CT) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int m = 0;
+        for (; m + 4 <= ml; m += 4) {
+          const double r0 = R[(long long)m * K + i], r1 = R[(long long)(m + 1) * K + i];
+          const double r2 = R[(long long)(m + 2) * K + i], r3 = R[(long long)(m + 3) * K + i];
+          s0 += r0 * r0;
+          s1 += r1 * r1;
+          s2 += r2 * r2;
+          s3 += r3 * r3;
+        }
+        for (; m < ml; ++m) {
+          const double v = R[(long long)m * K + i];
+          s0 += v * v;
+        }
+        xs[i] = (s0 + s1) + (s2 + s3);
+      }
+    }
+    MEET();
+    double bv = -1.0;
+    int bi = INT_MAX;
+    for (int i = t; i < K; i += CT) {
+      double sq = 0.0;
+      for (int w = 0; w < nw; ++w) sq += slot(w, ex)[i];
+      if (N == 0) nz[i] = sq > 0.0 ? 1.0 : 0.0;  // the residual is still P (>= 0)
+      const double nv = nz[i] > 0.0 ? sqrt(sq) : -1.0;
+      if (nv > bv) {
+        bv = nv;
+        bi = i;
+      }
+    }
+    ++ex;
+    double best;
+    int j;
+    block_argmax(bv, bi, red, redi, &best, &j);
+    if (best <= 0.0) break;
+    if (N == 0) ref = best;
+    else if (best < a.delta * ref) break;
+    if (t == 0) picks[N] = j;
+    ++N;
+    for (int m = t; m < ml; m += CT) U[m] = R[(long long)m * K + j] / best;
+    __syncthreads();
+    {
+      double* xs = slot(r, ex);
+      for (int i = t; i < K; i += CT) {
+        double s0 = 0.0, s1 = 0.0;
+        int m = 0;
+        for (; m + 2 <= ml; m += 2) {
+          s0 += U[m] * R[(long long)m * K + i];
+          s1 += U[m + 1] * R[(long long)(m + 1) * K + i];
+        }
+        if (m < ml) s0 += U[m] * R[(long long)m * K + i];
+        xs[i] = s0 + s1;
+      }
+    }
+    MEET();
+    for (int i = t; i < K; i += CT) {
+      double v = 0.0;
+      for (int w = 0; w < nw; ++w) v += slot(w, ex)[i];
+      vec[i] = v;
+    }
+    ++ex;
+    __syncthreads();
+    for (int e = t; e < ml * K; e += CT) {
+      const int m = e / K, i = e - m * K;
+      R[e] -= U[m] * vec[i];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+
+  if (N > 0) {
+    // ---------------------------------------------- initial footprints
+    {
+      double* xs = slot(r, ex);
+      for (int n = 0; n < N; ++n) {
+        const int col = picks[n];
+        double mx = 0.0;
+        for (int m = t; m < ml; m += CT) mx = fmax(mx, (double)Pl[m * Kp + col]);
+        mx = block_max(mx, red);
+        if (t == 0) xs[n] = mx;
+      }
+    }
+    MEET();
+    for (int m = t; m < ml; m += CT)
+      for (int n = 0; n < R8; ++n) {
+        double v = 0.0;
+        if (n < N) {
+          double mx = 0.0;
+          for (int w = 0; w < nw; ++w) mx = fmax(mx, slot(w, ex)[n]);
+          v = (double)Pl[m * Kp + picks[n]] / mx;
+        }
+        F[m * R8 + n] = v;
+      }
+    ++ex;
+    for (int e = t; e < K * R8; e += CT) A[e] = 0.0;
+    __syncthreads();
+
+    // HALS, compiled per rank so that the sequential row/column updates run
+    // without predication
+    auto hals = [&](auto rank) -> bool {
+      constexpr int NR = decltype(rank)::value;
+      constexpr int NP = NR * (NR + 1) / 2;
+      constexpr int GC = CT / NP;           // chunks of the Gram sums
+      const int Qb = s.Qb, Kq = s.Kq;
+      const int mq = (ml + Qb - 1) / Qb;    // own rows per partition of F^T P
+      const int kc = (K + Kq - 1) / Kq;     // segments per range of P A^T
+      double* FtP = scr;                    // [NR][K] totals (after the meeting)
+      for (int sweep = -1; sweep < a.sweeps; ++sweep) {
+        // ---- partial F^T F (pair k, rows h mod GC) and F^T P over own rows
+        double* xs = slot(r, ex);
+        if (t < NP * GC) {
+          const int k = t % NP, h = t / NP;
+          int n1, n2;
+          pair_of<NR>(k, n1, n2);
+          double v = 0.0;
+          for (int m = h; m < ml; m += GC) v += F[m * R8 + n1] * F[m * R8 + n2];
+          red2[h * NP + k] = v;
+        }
+        for (int e = t; e < Qb * K; e += CT) {
+          const int q = e / K, i = e - q * K;
+          const int m0 = q * mq, m1 = min(ml, m0 + mq);
+          double fp[NR];
+#pragma unroll
+          for (int n = 0; n < NR; ++n) fp[n] = 0.0;
+#pragma unroll 4
+          for (int m = m0; m < m1; ++m) {
+            const double pv = (double)Pl[m * Kp + i];
+#pragma unroll
+            for (int n = 0; n < NR; ++n) fp[n] += F[m * R8 + n] * pv;
+          }
+#pragma unroll
+          for (int n = 0; n < NR; ++n) scr[((size_t)q * NR + n) * K + i] = fp[n];
+        }
+        __syncthreads();
+        if (t < NP) {
+          double v = 0.0;
+          for (int h = 0; h < GC; ++h) v += red2[h * NP + t];
+          xs[R8 * K + t] = v;
+        }
+        for (int e = t; e < NR * K; e += CT) {
+          double v = 0.0;
+          for (int q = 0; q < Qb; ++q) v += scr[(size_t)q * NR * K + e];
+          xs[e] = v;
+        }
+        if (!meet(arrivals, abandoned, error, (ex + 1) * (unsigned)nw, s.limit, &flag)) return false;
+        // ---- totals over the component's workgroups (slot order) into LDS;
+        // sixteen slots are loaded at a time, then added in order
+        if (t < NP) {
+          int n1, n2;
+          pair_of<NR>(t, n1, n2);
+          double v = 0.0;
+          for (int w = 0; w < nw; ++w) v += slot(w, ex)[R8 * K + t];
+          gF[n1 * R8 + n2] = v;
+          gF[n2 * R8 + n1] = v;
+        }
+        for (int e = t; e < NR * K; e += CT) {
+          double v = 0.0;
+          for (int wb = 0; wb < nw; wb += 16) {
+            double x[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) x[j] = wb + j < nw ? slot(wb + j, ex)[e] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+              if (wb + j < nw) v += x[j];
+          }
+          FtP[e] = v;
+        }
+        ++ex;
+        __syncthreads();
+        // ---- the A update (rows of A in order), every workgroup alike
+        for (int i = t; i < K; i += CT) {
+          double av[NR];
+#pragma unroll
+          for (int n = 0; n < NR; ++n) av[n] = A[i * R8 + n];
+#pragma unroll
+          for (int n = 0; n < NR; ++n) {
+            // from rank 6 on, hoisting all Gram reads would spill: keep them per row
+            if constexpr (NR > 5) asm volatile("" ::: "memory");
+            const double d = gF[n * R8 + n];
+            if (d > 0.0) {
+              double sg = 0.0;
+#pragma unroll
+              for (int n2 = 0; n2 < NR; ++n2) sg += gF[n * R8 + n2] * av[n2];
+              av[n] = fmax(0.0, av[n] + (FtP[n * K + i] - sg) / d);
+            }
+          }
+#pragma unroll
+          for (int n = 0; n < NR; ++n) A[i * R8 + n] = av[n];
+        }
+        __syncthreads();
+        if (sweep < 0) continue;
+        // ---- A A^T (pair k, segments h mod GC), then P A^T of own rows
+        if (t < NP * GC) {
+          const int k = t % NP, h = t / NP;
+          int n1, n2;
+          pair_of<NR>(k, n1, n2);
+          double v = 0.0;
+          for (int i = h; i < K; i += GC) v += A[i * R8 + n1] * A[i * R8 + n2];
+          red2[h * NP + k] = v;
+        }
+        if (t < Kq * mw) {
+          const int m = t % mw, kq = t / mw;
+          if (m < ml) {
+            const int i0 = kq * kc, i1 = min(K, i0 + kc);
+            double gp[NR];
+#pragma unroll
+            for (int n = 0; n < NR; ++n) gp[n] = 0.0;
+#pragma unroll 4
+            for (int i = i0; i < i1; ++i) {
+              const double pv = (double)Pl[m * Kp + i];
+#pragma unroll
+              for (int n = 0; n < NR; ++n) gp[n] += pv * A[i * R8 + n];
+            }
+#pragma unroll
+            for (int n = 0; n < NR; ++n) scr[((size_t)kq * mw + m) * NR + n] = gp[n];
+          }
+        }
+        __syncthreads();
+        if (t < NP) {
+          int n1, n2;
+          pair_of<NR>(t, n1, n2);
+          double v = 0.0;
+          for (int h = 0; h < GC; ++h) v += red2[h * NP + t];
+          gA[n1 * R8 + n2] = v;
+          gA[n2 * R8 + n1] = v;
+        }
+        __syncthreads();
+        // ---- the own F rows (columns of F in order)
+        for (int m = t; m < ml; m += CT) {
+          double gp[NR], f[NR];
+#pragma unroll
+          for (int n = 0; n < NR; ++n) {
+            gp[n] = 0.0;
+            f[n] = F[m * R8 + n];
+          }
+          for (int kq = 0; kq < Kq; ++kq)
+#pragma unroll
+            for (int n = 0; n < NR; ++n) gp[n] += scr[((size_t)kq * mw + m) * NR + n];
+#pragma unroll
+          for (int n = 0; n < NR; ++n) {
+            if constexpr (NR > 5) asm volatile("" ::: "memory");
+            const double d = gA[n * R8 + n];
+            if (d > 0.0) {
+              double sg = 0.0;
+#pragma unroll
+              for (int n2 = 0; n2 < NR; ++n2) sg += f[n2] * gA[n2 * R8 + n];
+              f[n] = fmax(0.0, f[n] + (gp[n] - sg) / d);
+            }
+          }
+#pragma unroll
+          for (int n = 0; n < NR; ++n) F[m * R8 + n] = f[n];
+        }
+        __syncthreads();
+      }
+      return true;
+    };
+    bool ok = true;
+    switch (N) {
+      case 1: ok = hals(std::integral_constant<int, 1>{}); break;
+      case 2: ok = hals(std::integral_constant<int, 2>{}); break;
+      case 3: ok = hals(std::integral_constant<int, 3>{}); break;
+      case 4: ok = hals(std::integral_constant<int, 4>{}); break;
+      case 5: ok = hals(std::integral_constant<int, 5>{}); break;
+      case 6: ok = hals(std::integral_constant<int, 6>{}); break;
+      case 7: ok = hals(std::integral_constant<int, 7>{}); break;
+      default: ok = hals(std::integral_constant<int, 8>{}); break;
+    }
+    if (!ok) return;
+
+    // ------------------------------------------ scale to peak 1, export
+    {
+      double* xs = slot(r, ex);
+      for (int n = 0; n < N; ++n) {
+        double mx = 0.0;
+        for (int m = t; m < ml; m += CT) mx = fmax(mx, F[m * R8 + n]);
+        mx = block_max(mx, red);
+        if (t == 0) xs[n] = mx;
+      }
+    }
+    MEET();
+    double* Fg = a.F + (long long)(off + lo) * R8;
+    double* Ag = a.A + (long long)c * R8 * a.Kmax;
+    for (int n = 0; n < N; ++n) {
+      double mx = 0.0;
+      for (int w = 0; w < nw; ++w) mx = fmax(mx, slot(w, ex)[n]);
+      const double sc = mx > 0.0 ? mx : 1.0;
+      for (int m = t; m < ml; m += CT) Fg[(long long)m * R8 + n] = F[m * R8 + n] / sc;
+      if (r == 0)
+        for (int i = t; i < K; i += CT) Ag[(long long)n * a.Kmax + i] = A[i * R8 + n] * sc;
+    }
+    ++ex;
+  }
+#undef MEET
+  if (r == 0 && t == 0) a.N[c] = N;
+}
+
+__global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+size_t split_lds(int K, int mw, int Qb, int Kq, int* scr_out) {
+  const int Kp = K | 1;
+  const size_t scr = std::max<size_t>({(size_t)Qb * R8 * K, (size_t)Kq * mw * R8, (size_t)K + mw});  // >= R8 K
+  if (scr_out) *scr_out = (int)scr;
+  return 8 * ((size_t)K * R8 + (size_t)mw * R8 + scr) + 4 * (size_t)mw * Kp;
+}
+
+}  // namespace
+
+bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff, size_t xbuf_bytes,
+                    std::vector<int>& wg_comp, std::vector<int>& wg_base) {
+  int dev = 0, coop = 0, ncu = 0, max_lds = 0, clock_khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
+    return false;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return false;
+  if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || clock_khz <= 0)
+    return false;
+  const size_t budget = max_lds > 16384 ? (size_t)max_lds - 12288 : 0;  // static LDS ~11 KB
+  const int K = a.K;
+  const int ncomp = a.ncomp;
+  if (K < 1 || ncomp < 1) return false;
+  const int Qb = std::max(1, std::min(4, CT / K));
+  for (int mw = 32; mw <= CT; mw += 32) {
+    long long G = 0;
+    for (int k = 0; k < ncomp; ++k) G += (coff[k + 1] - coff[k] + mw - 1) / mw;
+    if (G > ncu) continue;                       // one workgroup per compute unit
+    const int Kq = CT / mw;
+    int scr = 0;
+    const size_t lds = split_lds(K, mw, Qb, Kq, &scr);
+    if (lds > budget) return false;              // larger slices only need more
+    const int XS = ((R8 * K + NPAIR) + 31) / 32 * 32;
+    if ((size_t)G * 2 * XS * 8 > xbuf_bytes) return false;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_nmf_split, CT, lds) != hipSuccess || occ < 1)
+      return false;
+    s.G = (int)G;
+    s.mw = mw;
+    s.Kp = K | 1;
+    s.Qb = Qb;
+    s.Kq = Kq;
+    s.scr = scr;
+    s.XS = XS;
+    s.lds_bytes = lds;
+    s.limit = (long long)clock_khz * 1000LL * 2;  // two seconds of wall clock
+    wg_comp.assign((size_t)G, 0);
+    wg_base.assign((size_t)ncomp + 1, 0);
+    int gi = 0;
+    for (int k = 0; k < ncomp; ++k) {
+      wg_base[k] = gi;
+      const int nwk = (coff[k + 1] - coff[k] + mw - 1) / mw;
+      for (int j = 0; j < nwk; ++j) wg_comp[gi++] = k;
+    }
+    wg_base[ncomp] = gi;
+    return true;
+  }
+  return false;
+}
+
+hipError_t launch_nmf_split(const NmfArgs& a, const NmfSplit& s, hipStream_t st) {
+  const int nsync = 2 * a.ncomp + 1;
+  hipLaunchKernelGGL(k_fill_u32, dim3((nsync + 255) / 256), dim3(256), 0, st, s.sync, nsync, 0u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_nmf_split),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)s.lds_bytes);
+  if (e != hipSuccess) return e;
+  NmfArgs aa = a;
+  NmfSplit ss = s;
+  void* args[] = {&aa, &ss};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_nmf_split), dim3(s.G), dim3(CT), args,
+                                    (unsigned)s.lds_bytes, st);
+}
+
+}  // namespace seg

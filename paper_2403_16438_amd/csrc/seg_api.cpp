@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -41,6 +42,7 @@ int check_config(const seg_config* c) {
   if (!(c->sigma_floor >= 0.f)) return SEG_E_INVAL;
   if (c->detector != SEG_DET_PLAIN && c->detector != SEG_DET_SURROGATE) return SEG_E_INVAL;
   if (c->detector == SEG_DET_SURROGATE && (c->height % 4 || c->width % 4)) return SEG_E_INVAL;
+  if (c->nmf_path > SEG_NMF_SPLIT) return SEG_E_INVAL;
   return SEG_OK;
 }
 
@@ -180,6 +182,7 @@ int seg_default_config(uint32_t height, uint32_t width, uint32_t max_frames, seg
   c.footprint_level = 0.25f;
   c.sigma_floor = 1e-3f;
   c.detector = SEG_DET_PLAIN;
+  c.nmf_path = SEG_NMF_AUTO;
   *out = c;
   return SEG_OK;
 }
@@ -412,17 +415,56 @@ int seg_finalize(seg_session* s, void* stream) {
     na.max_rank = (int)c.nmf_max_rank;
     na.sweeps = (int)c.nmf_sweeps;
     na.delta = (double)c.spa_delta;
-    int max_mc = 0;
-    for (int k = 0; k < ncomp; ++k) max_mc = std::max(max_mc, coff[k + 1] - coff[k]);
-    seg::plan_nmf(na, max_mc);
-    if ((e = fail(s, seg::launch_nmf(na, st)))) return e;
+    // split path: the exchange slots reuse the pixel-major P_c area, the
+    // workgroup tables the SPA-direction area and the meeting counters the
+    // SPA-flag area (all three belong to the single-workgroup kernel)
+    seg::NmfSplit sp{};
+    std::vector<int> wg_comp, wg_base;
+    bool split = c.nmf_path != SEG_NMF_SINGLE &&
+                 seg::plan_nmf_split(sp, na, coff, (size_t)s->M * s->Kmax * 8, wg_comp, wg_base);
+    if (!split && c.nmf_path == SEG_NMF_SPLIT) return SEG_E_CAPACITY;
+    // cooperative grids of concurrent finalizes could each hold part of the
+    // device while waiting for the rest: one split NMF at a time per process
+    static std::mutex split_mutex;
+    std::unique_lock<std::mutex> hold(split_mutex, std::defer_lock);
+    if (split) {
+      int* tab = at<int>(s, l.nmf_G);
+      if ((e = fail(s, hipMemcpyAsync(tab, wg_comp.data(), wg_comp.size() * 4, hipMemcpyHostToDevice, st))))
+        return e;
+      if ((e = fail(s, hipMemcpyAsync(tab + wg_comp.size(), wg_base.data(), wg_base.size() * 4,
+                                      hipMemcpyHostToDevice, st))))
+        return e;
+      sp.wg_comp = tab;
+      sp.wg_base = tab + wg_comp.size();
+      sp.xbuf = na.P;
+      sp.sync = reinterpret_cast<unsigned*>(na.Wk);
+      hold.lock();
+      const hipError_t le = seg::launch_nmf_split(na, sp, st);
+      if (le != hipSuccess) {
+        (void)hipGetLastError();
+        hold.unlock();
+        if (c.nmf_path == SEG_NMF_SPLIT || le != hipErrorCooperativeLaunchTooLarge) return fail(s, le);
+        split = false;  // the device is shared: one workgroup per component
+      }
+    }
+    if (!split) {
+      int max_mc = 0;
+      for (int k = 0; k < ncomp; ++k) max_mc = std::max(max_mc, coff[k + 1] - coff[k]);
+      seg::plan_nmf(na, max_mc);
+      if ((e = fail(s, seg::launch_nmf(na, st)))) return e;
+    }
     const size_t npx = pix.size();
     std::vector<int> N(ncomp);
     std::vector<double> F(npx * seg::kMaxRank), A((size_t)ncomp * seg::kMaxRank * s->Kmax);
+    unsigned split_error = 0;
     if ((e = fail(s, hipMemcpyAsync(N.data(), na.N, ncomp * 4, hipMemcpyDeviceToHost, st)))) return e;
     if ((e = fail(s, hipMemcpyAsync(F.data(), na.F, F.size() * 8, hipMemcpyDeviceToHost, st)))) return e;
     if ((e = fail(s, hipMemcpyAsync(A.data(), na.A, A.size() * 8, hipMemcpyDeviceToHost, st)))) return e;
+    if (split && (e = fail(s, hipMemcpyAsync(&split_error, sp.sync + 2 * ncomp, 4, hipMemcpyDeviceToHost, st))))
+      return e;
     if ((e = fail(s, hipStreamSynchronize(st)))) return e;
+    if (hold.owns_lock()) hold.unlock();
+    if (split_error) return fail(s, hipErrorLaunchTimeOut);  // a meeting was abandoned
     const double level = (double)c.footprint_level;
     for (int k = 0; k < ncomp; ++k) {
       const int off = coff[k], Mc = coff[k + 1] - coff[k];

@@ -167,4 +167,27 @@ struct NmfArgs {
 void plan_nmf(NmfArgs& a, int max_mc);
 hipError_t launch_nmf(const NmfArgs& a, hipStream_t st);
 
+// NMF with every component split over co-resident workgroups (k_nmf_split)
+struct NmfSplit {
+  int G;                 // workgroups of the cooperative grid
+  int mw;                // pixels (rows of P_c) per workgroup
+  int Kp;                // LDS row stride of the P_c rows (odd)
+  int Qb;                // row partitions of the partial F^T P
+  int Kq;                // segment ranges of the partial P A^T
+  int scr;               // doubles of LDS scratch
+  int XS;                // doubles per exchange slot
+  size_t lds_bytes;      // dynamic LDS per workgroup
+  long long limit;       // wall-clock ticks a meeting may wait
+  const int* wg_comp;    // [G] component of each workgroup
+  const int* wg_base;    // [ncomp + 1] first workgroup of each component
+  double* xbuf;          // [G][2][XS] exchange slots
+  unsigned* sync;        // [2 ncomp + 1] arrivals, abandon flags, error flag
+};
+// Chooses the split (smallest slice with one workgroup per compute unit that
+// fits LDS and xbuf_bytes); false when the split path does not apply. Fills
+// the host copies of the workgroup tables.
+bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff, size_t xbuf_bytes,
+                    std::vector<int>& wg_comp, std::vector<int>& wg_base);
+hipError_t launch_nmf_split(const NmfArgs& a, const NmfSplit& s, hipStream_t st);
+
 }  // namespace seg

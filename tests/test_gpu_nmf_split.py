@@ -1,0 +1,81 @@
+"""The split NMF (each component over several co-resident workgroups) against
+the oracle and against the one-workgroup-per-component kernel.
+
+Both paths compute the same factorisation (Eq. 3) and differ only in the
+order of the sums over a component's pixels, so the bar is the oracle's:
+same components with the same number of footprints, mask IoU >= 0.99; on top,
+the two GPU paths agree closely in weights and the split path is
+bit-reproducible from run to run.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2403_16438_amd import abi, segment_video
+from synth import preset, simulate
+
+from parity import compare_footprints, params_from_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wide():
+    """256 x 256, 30 neurons, 2,000 frames: components of 200-1,000 pixels,
+    i.e. up to ~30 workgroups per component."""
+    video, _ = simulate(preset(2, frames=2000), 2000)
+    sess = segment_video(video, nmf_path=abi.SEG_NMF_SPLIT)
+    ref = oracle.segment(video, params_from_config(sess.cfg))
+    return video, sess, ref
+
+
+def test_split_matches_oracle(wide):
+    video, sess, ref = wide
+    assert len(ref.footprints) >= 20
+    compare_footprints(sess.footprints(), ref.footprints)
+
+
+def test_split_matches_single_workgroup(wide):
+    video, sess, ref = wide
+    one = segment_video(video, nmf_path=abi.SEG_NMF_SINGLE).footprints()
+    two = sess.footprints()
+    assert np.array_equal(one["component"], two["component"])
+    assert np.array_equal(one["masks"], two["masks"])
+    assert np.abs(one["weights"] - two["weights"]).max() <= 1e-5
+    rel = np.abs(one["activity"] - two["activity"]).max() / np.abs(one["activity"]).max()
+    assert rel <= 1e-5
+
+
+def test_split_is_reproducible(wide):
+    video, sess, ref = wide
+    again = segment_video(video, nmf_path=abi.SEG_NMF_SPLIT).footprints()
+    first = sess.footprints()
+    assert np.array_equal(again["weights"], first["weights"])
+    assert np.array_equal(again["activity"], first["activity"])
+
+
+def test_auto_path_small_case():
+    """64 x 64 x 1,000 (20 segments): the automatic choice (split) against the
+    oracle."""
+    video, _ = simulate(preset(1), 0)
+    sess = segment_video(video)
+    ref = oracle.segment(video, params_from_config(sess.cfg))
+    compare_footprints(sess.footprints(), ref.footprints)
+
+
+def test_split_refuses_too_many_segments():
+    """4,096 segments do not fit a 32-pixel slice in LDS: the forced split
+    path reports SEG_E_CAPACITY, the automatic path falls back."""
+    rng = np.random.default_rng(5)
+    T, H, W = 4096 * 50, 16, 16
+    video = rng.poisson(400.0, size=(T, H, W)).astype(np.uint16)
+    for k in (3, 700, 2500):                     # a 6 x 6 blob fires in three segments
+        video[k * 50 + 20:k * 50 + 23, 5:11, 5:11] += 600
+    with pytest.raises(abi.SegError) as e:
+        segment_video(video, block=20000, nmf_path=abi.SEG_NMF_SPLIT)
+    assert e.value.code == abi.SEG_E_CAPACITY
+    sess = segment_video(video, block=20000)
+    fp = sess.footprints()
+    assert fp["masks"].shape[0] == 1
+    assert fp["masks"][0, 5:11, 5:11].all()
