@@ -11,6 +11,8 @@
 //               hull of the pixel-square corners, exact integer shoelace)
 //   aggregate   b_i = kept regions, n_b = sum_i b_i, b = [n_b >= c_min],
 //               components of b numbered 1..n by minimum raster index
+#include <climits>
+
 #include "seg_internal.h"
 
 // The region decisions repeat the reference arithmetic operation by operation
@@ -245,24 +247,70 @@ __global__ void k_region_zero(FinalizeArgs a, int* __restrict__ root) {
   }
 }
 
+// Region moments and bounding boxes. Consecutive pixels of a wave that carry
+// the same label form runs; each run is reduced with shuffles onto its first
+// lane, which issues the atomics (integer, so the totals do not depend on
+// the order).
 __global__ void k_region_accum(FinalizeArgs a, long long n, int* __restrict__ root) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const int l = a.lab[g];
+  const int lane = threadIdx.x & 63;
+  const int l = g < n ? a.lab[g] : -1;
+  unsigned cnt = 0, sx = 0, sy = 0;
+  unsigned long long sxx = 0, syy = 0, sxy = 0;
+  int x0 = INT_MAX, x1 = -1, y0 = INT_MAX, y1 = -1;
+  if (l >= 0) {
+    const int x = (int)(g % a.M);
+    const unsigned yy = (unsigned)(x / a.W), xx = (unsigned)(x - (int)yy * a.W);
+    cnt = 1;
+    sx = xx;
+    sy = yy;
+    sxx = (unsigned long long)xx * xx;
+    syy = (unsigned long long)yy * yy;
+    sxy = (unsigned long long)xx * yy;
+    x0 = x1 = (int)xx;
+    y0 = y1 = (int)yy;
+  }
+  const int lp = __shfl_up(l, 1);
+  const bool head = l >= 0 && (lane == 0 || lp != l);
+  int key = head ? lane : -1;  // first lane of the run: inclusive max-scan of the heads
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(key, d);
+    if (lane >= d) key = max(key, o);
+  }
+  if (l < 0) key = -2;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int ko = __shfl_down(key, d);
+    const unsigned c_ = __shfl_down(cnt, d), sx_ = __shfl_down(sx, d), sy_ = __shfl_down(sy, d);
+    const unsigned long long sxx_ = __shfl_down(sxx, d), syy_ = __shfl_down(syy, d), sxy_ = __shfl_down(sxy, d);
+    const int x0_ = __shfl_down(x0, d), x1_ = __shfl_down(x1, d);
+    const int y0_ = __shfl_down(y0, d), y1_ = __shfl_down(y1, d);
+    if (lane + d < 64 && ko == key) {
+      cnt += c_;
+      sx += sx_;
+      sy += sy_;
+      sxx += sxx_;
+      syy += syy_;
+      sxy += sxy_;
+      x0 = min(x0, x0_);
+      x1 = max(x1, x1_);
+      y0 = min(y0, y0_);
+      y1 = max(y1, y1_);
+    }
+  }
   if (l < 0) return;
   const int r = a.rid[l];
-  const int x = (int)(g % a.M);
-  const unsigned yy = (unsigned)(x / a.W), xx = (unsigned)(x - (int)yy * a.W);
-  atomicAdd(&a.reg_area[r], 1u);
-  atomicAdd(&a.reg_sx[r], xx);
-  atomicAdd(&a.reg_sy[r], yy);
-  atomicAdd(&a.reg_sxx[r], (unsigned long long)xx * xx);
-  atomicAdd(&a.reg_syy[r], (unsigned long long)yy * yy);
-  atomicAdd(&a.reg_sxy[r], (unsigned long long)xx * yy);
-  atomicMin(&a.reg_box[4 * r + 0], (int)xx);
-  atomicMax(&a.reg_box[4 * r + 1], (int)xx);
-  atomicMin(&a.reg_box[4 * r + 2], (int)yy);
-  atomicMax(&a.reg_box[4 * r + 3], (int)yy);
+  if (head) {
+    atomicAdd(&a.reg_area[r], cnt);
+    atomicAdd(&a.reg_sx[r], sx);
+    atomicAdd(&a.reg_sy[r], sy);
+    atomicAdd(&a.reg_sxx[r], sxx);
+    atomicAdd(&a.reg_syy[r], syy);
+    atomicAdd(&a.reg_sxy[r], sxy);
+    atomicMin(&a.reg_box[4 * r + 0], x0);
+    atomicMax(&a.reg_box[4 * r + 1], x1);
+    atomicMin(&a.reg_box[4 * r + 2], y0);
+    atomicMax(&a.reg_box[4 * r + 3], y1);
+  }
   if (l == (int)g) root[r] = l;
 }
 

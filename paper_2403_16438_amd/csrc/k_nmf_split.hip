@@ -95,6 +95,13 @@ __device__ void block_argmax(double v, int idx, double* red, int* redi, double* 
   __syncthreads();
 }
 
+// Slot writes are agent-scope stores: they go through to the level where all
+// XCDs see them, so the release at the meeting finds no dirty slot lines to
+// write back from the L2.
+__device__ __forceinline__ void put(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // All workgroups of one component meet here; `target` is the number of
 // arrivals that completes this meeting. Returns false when the component was
 // abandoned (time limit), uniformly for the whole workgroup.
@@ -143,10 +150,11 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
   const int off = a.coff[c], Mc = a.coff[c + 1] - off;
   const int mw = s.mw, lo = r * mw, ml = min(mw, Mc - lo);  // own rows [lo, lo + ml)
   const int K = a.K, Kp = s.Kp;
-  // LDS: A [K][R8], F [mw][R8], scratch [scr], P rows [mw][Kp] (float)
+  // LDS: A [K][R8], F [mw][R8], P A^T [mw][R8], scratch [scr], P rows [mw][Kp] (float)
   double* A = dyn;
   double* F = A + (size_t)K * R8;
-  double* scr = F + (size_t)mw * R8;
+  double* GP = F + (size_t)mw * R8;
+  double* scr = GP + (size_t)mw * R8;
   float* Pl = reinterpret_cast<float*>(scr + s.scr);
   double* R = a.R + (long long)(off + lo) * K;  // own residual rows [ml][K], HBM
   unsigned* arrivals = s.sync + c;
@@ -154,6 +162,20 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
   unsigned* error = s.sync + 2 * a.ncomp;
   unsigned ex = 0;  // exchanges done
   auto slot = [&](int w, unsigned e) { return s.xbuf + ((size_t)(w0 + w) * 2 + (e & 1)) * s.XS; };
+  // sum (or max) of element j over the component's slots of exchange e, in
+  // slot order; sixteen loads are in flight at a time
+  auto gather = [&](size_t j, unsigned e, bool take_max) {
+    double v = 0.0;
+    for (int wb = 0; wb < nw; wb += 16) {
+      double x[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) x[q] = wb + q < nw ? slot(wb + q, e)[j] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (wb + q < nw) v = take_max ? fmax(v, x[q]) : v + x[q];
+    }
+    return v;
+  };
 #define MEET() \
   if (!meet(arrivals, abandoned, error, (ex + 1) * (unsigned)nw, s.limit, &flag)) return
 
@@ -193,15 +215,14 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
           const double v = R[(long long)m * K + i];
           s0 += v * v;
         }
-        xs[i] = (s0 + s1) + (s2 + s3);
+        put(xs + i, (s0 + s1) + (s2 + s3));
       }
     }
     MEET();
     double bv = -1.0;
     int bi = INT_MAX;
     for (int i = t; i < K; i += CT) {
-      double sq = 0.0;
-      for (int w = 0; w < nw; ++w) sq += slot(w, ex)[i];
+      const double sq = gather(i, ex, false);
       if (N == 0) nz[i] = sq > 0.0 ? 1.0 : 0.0;  // the residual is still P (>= 0)
       const double nv = nz[i] > 0.0 ? sqrt(sq) : -1.0;
       if (nv > bv) {
@@ -230,14 +251,12 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
           s1 += U[m + 1] * R[(long long)(m + 1) * K + i];
         }
         if (m < ml) s0 += U[m] * R[(long long)m * K + i];
-        xs[i] = s0 + s1;
+        put(xs + i, s0 + s1);
       }
     }
     MEET();
     for (int i = t; i < K; i += CT) {
-      double v = 0.0;
-      for (int w = 0; w < nw; ++w) v += slot(w, ex)[i];
-      vec[i] = v;
+      vec[i] = gather(i, ex, false);
     }
     ++ex;
     __syncthreads();
@@ -258,7 +277,7 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
         double mx = 0.0;
         for (int m = t; m < ml; m += CT) mx = fmax(mx, (double)Pl[m * Kp + col]);
         mx = block_max(mx, red);
-        if (t == 0) xs[n] = mx;
+        if (t == 0) put(xs + n, mx);
       }
     }
     MEET();
@@ -266,9 +285,7 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
       for (int n = 0; n < R8; ++n) {
         double v = 0.0;
         if (n < N) {
-          double mx = 0.0;
-          for (int w = 0; w < nw; ++w) mx = fmax(mx, slot(w, ex)[n]);
-          v = (double)Pl[m * Kp + picks[n]] / mx;
+          v = (double)Pl[m * Kp + picks[n]] / gather(n, ex, true);
         }
         F[m * R8 + n] = v;
       }
@@ -316,36 +333,23 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
         if (t < NP) {
           double v = 0.0;
           for (int h = 0; h < GC; ++h) v += red2[h * NP + t];
-          xs[R8 * K + t] = v;
+          put(xs + R8 * K + t, v);
         }
         for (int e = t; e < NR * K; e += CT) {
           double v = 0.0;
           for (int q = 0; q < Qb; ++q) v += scr[(size_t)q * NR * K + e];
-          xs[e] = v;
+          put(xs + e, v);
         }
         if (!meet(arrivals, abandoned, error, (ex + 1) * (unsigned)nw, s.limit, &flag)) return false;
-        // ---- totals over the component's workgroups (slot order) into LDS;
-        // sixteen slots are loaded at a time, then added in order
+        // ---- totals over the component's workgroups (slot order) into LDS
         if (t < NP) {
           int n1, n2;
           pair_of<NR>(t, n1, n2);
-          double v = 0.0;
-          for (int w = 0; w < nw; ++w) v += slot(w, ex)[R8 * K + t];
+          const double v = gather(R8 * K + t, ex, false);
           gF[n1 * R8 + n2] = v;
           gF[n2 * R8 + n1] = v;
         }
-        for (int e = t; e < NR * K; e += CT) {
-          double v = 0.0;
-          for (int wb = 0; wb < nw; wb += 16) {
-            double x[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) x[j] = wb + j < nw ? slot(wb + j, ex)[e] : 0.0;
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-              if (wb + j < nw) v += x[j];
-          }
-          FtP[e] = v;
-        }
+        for (int e = t; e < NR * K; e += CT) FtP[e] = gather(e, ex, false);
         ++ex;
         __syncthreads();
         // ---- the A update (rows of A in order), every workgroup alike
@@ -405,18 +409,21 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
           gA[n1 * R8 + n2] = v;
           gA[n2 * R8 + n1] = v;
         }
+        for (int e = t; e < ml * NR; e += CT) {   // P A^T of own rows: ranges in order
+          const int m = e / NR, n = e - m * NR;
+          double v = 0.0;
+          for (int kq = 0; kq < Kq; ++kq) v += scr[((size_t)kq * mw + m) * NR + n];
+          GP[e] = v;
+        }
         __syncthreads();
         // ---- the own F rows (columns of F in order)
         for (int m = t; m < ml; m += CT) {
           double gp[NR], f[NR];
 #pragma unroll
           for (int n = 0; n < NR; ++n) {
-            gp[n] = 0.0;
+            gp[n] = GP[m * NR + n];
             f[n] = F[m * R8 + n];
           }
-          for (int kq = 0; kq < Kq; ++kq)
-#pragma unroll
-            for (int n = 0; n < NR; ++n) gp[n] += scr[((size_t)kq * mw + m) * NR + n];
 #pragma unroll
           for (int n = 0; n < NR; ++n) {
             if constexpr (NR > 5) asm volatile("" ::: "memory");
@@ -455,15 +462,14 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
         double mx = 0.0;
         for (int m = t; m < ml; m += CT) mx = fmax(mx, F[m * R8 + n]);
         mx = block_max(mx, red);
-        if (t == 0) xs[n] = mx;
+        if (t == 0) put(xs + n, mx);
       }
     }
     MEET();
     double* Fg = a.F + (long long)(off + lo) * R8;
     double* Ag = a.A + (long long)c * R8 * a.Kmax;
     for (int n = 0; n < N; ++n) {
-      double mx = 0.0;
-      for (int w = 0; w < nw; ++w) mx = fmax(mx, slot(w, ex)[n]);
+      const double mx = gather(n, ex, true);
       const double sc = mx > 0.0 ? mx : 1.0;
       for (int m = t; m < ml; m += CT) Fg[(long long)m * R8 + n] = F[m * R8 + n] / sc;
       if (r == 0)
@@ -480,11 +486,28 @@ __global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
   if (i < n) p[i] = v;
 }
 
+// Largest row partitions Qb (<= 4) and segment ranges Kq for which the
+// workgroup's LDS fits the budget; false when even Qb = Kq = 1 does not.
+bool split_fit(int K, int mw, size_t budget, int& Qb, int& Kq, int& scr, size_t& lds);
+
 size_t split_lds(int K, int mw, int Qb, int Kq, int* scr_out) {
   const int Kp = K | 1;
   const size_t scr = std::max<size_t>({(size_t)Qb * R8 * K, (size_t)Kq * mw * R8, (size_t)K + mw});  // >= R8 K
   if (scr_out) *scr_out = (int)scr;
-  return 8 * ((size_t)K * R8 + (size_t)mw * R8 + scr) + 4 * (size_t)mw * Kp;
+  return 8 * ((size_t)K * R8 + 2 * (size_t)mw * R8 + scr) + 4 * (size_t)mw * Kp;
+}
+
+bool split_fit(int K, int mw, size_t budget, int& Qb, int& Kq, int& scr, size_t& lds) {
+  Qb = std::max(1, std::min(4, CT / K));
+  Kq = std::max(1, CT / mw);
+  for (;;) {
+    lds = split_lds(K, mw, Qb, Kq, &scr);
+    if (lds <= budget) return true;
+    if (Qb == 1 && Kq == 1) return false;
+    if ((size_t)Qb * K >= (size_t)Kq * mw && Qb > 1) Qb /= 2;
+    else if (Kq > 1) Kq /= 2;
+    else Qb /= 2;
+  }
 }
 
 }  // namespace
@@ -504,15 +527,13 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
   const int K = a.K;
   const int ncomp = a.ncomp;
   if (K < 1 || ncomp < 1) return false;
-  const int Qb = std::max(1, std::min(4, CT / K));
   for (int mw = 32; mw <= CT; mw += 32) {
     long long G = 0;
     for (int k = 0; k < ncomp; ++k) G += (coff[k + 1] - coff[k] + mw - 1) / mw;
     if (G > ncu) continue;                       // one workgroup per compute unit
-    const int Kq = CT / mw;
-    int scr = 0;
-    const size_t lds = split_lds(K, mw, Qb, Kq, &scr);
-    if (lds > budget) return false;              // larger slices only need more
+    int Qb = 1, Kq = 1, scr = 0;
+    size_t lds = 0;
+    if (!split_fit(K, mw, budget, Qb, Kq, scr, lds)) return false;  // larger slices only need more
     const int XS = ((R8 * K + NPAIR) + 31) / 32 * 32;
     if ((size_t)G * 2 * XS * 8 > xbuf_bytes) return false;
     int occ = 0;

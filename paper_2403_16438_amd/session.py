@@ -109,10 +109,10 @@ class Session:
 def segment_video(video: np.ndarray, block: int | None = None, net=None, **overrides) -> Session:
     """Push a host uint16 video [T, H, W] (in blocks of `block` frames) and
     finalize. Returns the finalized session. With `net` (a Surrogate) the
-    learned detector is used (events at probability >= 0.5, c_min = 1)."""
+    learned detector is used (events at probability >= 0.5, c_min = 2)."""
     T, H, W = video.shape
     if net is not None:
-        overrides = dict(dict(detector=abi.SEG_DET_SURROGATE, event_z=0.5, min_event_segs=1), **overrides)
+        overrides = dict(dict(detector=abi.SEG_DET_SURROGATE, event_z=0.5, min_event_segs=2), **overrides)
     s = Session(H, W, max(T, 50), **overrides)
     if net is not None:
         s.set_model(net)

@@ -21,15 +21,20 @@ SEG = 50
 
 
 class SceneBank:
-    """n simulated training videos (config 4: 64x64x2000) on the GPU."""
+    """n simulated training videos (config 4: 64x64x2000) on the GPU; the
+    spike amplitudes alternate between the two dF/F references of the
+    simulator (relative to the local total fluorescence, and the dimmer one
+    relative to the neuron's own), so that the network sees events on both
+    sides of the plain method's threshold."""
 
-    def __init__(self, n: int, seed0: int = 40000, device="cuda", **overrides):
+    def __init__(self, n: int, seed0: int = 40000, device="cuda", mixed: bool = True, **overrides):
         from synth import preset
         from synth.gpu import GpuScene
         self.scenes = []
         self.labels = []
         for k in range(n):
-            cfg = preset(4, **overrides)
+            mode = {"dff_reference": "neuron" if mixed and k % 2 else "total"}
+            cfg = preset(4, **dict(mode, **overrides))
             sc = GpuScene(cfg, seed0 + k, device)
             self.scenes.append(sc)
             self.labels.append(torch.from_numpy(sc.truth.segment_masks(SEG).astype(np.float32)).to(device))

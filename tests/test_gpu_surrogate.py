@@ -16,14 +16,15 @@ pytestmark = pytest.mark.gpu
 
 
 def _video(h, w, frames, seed, **kw):
-    cfg = preset(2, height=h, width=w, frames=frames, n_neurons=8, n_overlap=2, **kw)
+    kw = dict(dict(n_neurons=8, n_overlap=2), **kw)
+    cfg = preset(2, height=h, width=w, frames=frames, **kw)
     sc = GpuScene(cfg, seed)
     return sc.render(0, frames).cpu().numpy().view(np.uint16), sc.truth
 
 
 def test_session_maps_equal_network_output():
     """The session's detection maps are the network's probabilities per segment."""
-    v, _ = _video(64, 64, 250, 31)
+    v, _ = _video(64, 64, 250, 31, n_neurons=3, n_overlap=0, min_sep=16.0)
     net = Surrogate(1, 64, 64, he_init(5))
     sess = segment_video(v, block=70, net=net)
     P = sess.segment_maps(abi.SEG_MAP_P).cpu().numpy()
@@ -48,29 +49,43 @@ def test_surrogate_needs_a_model_and_shape():
 
 @pytest.fixture(scope="module")
 def trained():
-    bank = SceneBank(120, device="cuda")
-    net, losses = train(steps=250, batch=16, lr=1e-3, bank=bank)
+    """3,000 RMSProp steps of batch 16 on 2,000 simulated 64x64 videos (half
+    with the dimmer neuron-relative dF/F), all on the GPU (about a minute)."""
+    bank = SceneBank(2000, device="cuda")
+    net, losses = train(steps=3000, batch=16, lr=1e-3, bank=bank)
     return net, losses
 
 
 def test_training_converges(trained):
     net, losses = trained
-    first, last = np.mean(losses[:20]), np.mean(losses[-20:])
+    first, last = np.mean(losses[:50]), np.mean(losses[-50:])
     assert last < 0.6 * first, (first, last)
 
 
+def _f1_pair(net, dff, seeds):
+    """Mean footprint F1 (IoU 0.3) of the plain and the surrogate detector
+    (c_min = 2 for both) on held-out 128 x 128 x 2,000 videos."""
+    plain, sur = [], []
+    n128 = for_frames(net, 128, 128)
+    for seed in seeds:
+        v, truth = _video(128, 128, 2000, seed, dff_range=dff)
+        plain.append(oracle.match_f1(segment_video(v).footprints()["masks"], truth.masks())["f1"])
+        sur.append(oracle.match_f1(segment_video(v, net=n128).footprints()["masks"], truth.masks())["f1"])
+    return float(np.mean(plain)), float(np.mean(sur))
+
+
 def test_gain_over_plain(trained, record_property):
-    """Footprint F1 (IoU 0.3) of both detectors against ground truth on two
-    held-out videos: dF/F relative to the local total baseline, and the hard
-    mode where it is relative to the neuron's own fluorescence (dimmer)."""
+    """What the trained network gains over the plain detector: on dim spikes
+    (dF/F 2-5 %), where the plain method's 5-sigma threshold on single-frame
+    maxima misses events, the learned detector (which integrates the spike's
+    time course) finds more neurons; on the default amplitudes (5-15 %) the
+    plain method stays ahead."""
     net, _ = trained
-    out = {}
-    for mode in ("total", "neuron"):
-        v, truth = _video(128, 128, 2000, 2000, dff_reference=mode)
-        plain = segment_video(v).footprints()["masks"]
-        sur = segment_video(v, net=for_frames(net, 128, 128)).footprints()["masks"]
-        out[mode] = (oracle.match_f1(plain, truth.masks())["f1"], oracle.match_f1(sur, truth.masks())["f1"])
-        record_property(f"f1_{mode}", out[mode])
-    print("F1 plain / surrogate:", out)
-    assert out["total"][0] >= 0.8          # the plain detector on its own terms
-    assert out["total"][1] > 0.0           # the surrogate finds neurons after a short training
+    dim = _f1_pair(net, (0.02, 0.05), (2000, 2001, 2002, 2003))
+    default = _f1_pair(net, (0.05, 0.15), (2000, 2001))
+    record_property("f1_dim_plain_surrogate", dim)
+    record_property("f1_default_plain_surrogate", default)
+    print("F1 plain / surrogate: dim", dim, "default", default)
+    assert dim[1] > dim[0], dim              # the gain where the threshold fails
+    assert default[0] >= 0.85, default        # the plain method on its own terms
+    assert default[1] >= 0.6, default         # the surrogate stays usable there
