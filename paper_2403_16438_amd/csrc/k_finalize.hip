@@ -70,6 +70,9 @@ __global__ void k_moments(FinalizeArgs a, double* __restrict__ C) {
     double acc = 0.0;
     if (a.have_moments && ny < a.H && nx >= 0 && nx < a.W) {
       const int y = ny * a.W + nx;
+      // unrolled so that several segments' loads are in flight; the sum
+      // still runs in segment order
+#pragma unroll 8
       for (int i = 0; i < a.K; ++i) {
         const long long b = (long long)i * a.M;
         acc += (double)a.P[o * a.plane + b + x] -
@@ -84,6 +87,7 @@ __global__ void k_pointwise(FinalizeArgs a, const double* __restrict__ C) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= a.M) return;
   double sd = 0.0, ss = 0.0;
+#pragma unroll 8
   for (int i = 0; i < a.K; ++i) {
     sd += (double)a.D[(long long)i * a.M + x];
     ss += (double)a.S[(long long)i * a.M + x];
@@ -119,6 +123,7 @@ __global__ void k_events(FinalizeArgs a) {
   const double s = a.sigma[x];
   const bool ok = s >= a.sigma_floor;
   int cnt = 0;
+#pragma unroll 8
   for (int i = 0; i < a.K; ++i) {
     const long long g = (long long)i * a.M + x;
     bool e;
@@ -433,6 +438,7 @@ __global__ void k_kept(FinalizeArgs a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= a.M) return;
   int nb = 0;
+#pragma unroll 8
   for (int i = 0; i < a.K; ++i) {
     const long long g = (long long)i * a.M + x;
     const int l = a.lab[g];

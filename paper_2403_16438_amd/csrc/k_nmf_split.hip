@@ -36,9 +36,12 @@ namespace seg {
 namespace {
 
 constexpr int CT = 1024;
-constexpr int CW = CT / 64;
+constexpr int CW = CT / 64;   // 16 waves: the MFMA phases assign work by wave
 constexpr int R8 = kMaxRank;
-constexpr int NPAIR = R8 * (R8 + 1) / 2;
+
+// FP64 MFMA 16x16x4: lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16)
+// and holds D(4 j + l / 16, l % 16) in element j.
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double wsum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -145,6 +148,7 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
   __shared__ int picks[R8];
   __shared__ int flag;
   const int g = blockIdx.x, t = threadIdx.x;
+  const int wv = t >> 6, lr = t & 15, lk = (t >> 4) & 3;   // wave, MFMA lane row / k
   const int c = s.wg_comp[g];
   const int w0 = s.wg_base[c], nw = s.wg_base[c + 1] - w0, r = g - w0;
   const int off = a.coff[c], Mc = a.coff[c + 1] - off;
@@ -298,54 +302,40 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
     auto hals = [&](auto rank) -> bool {
       constexpr int NR = decltype(rank)::value;
       constexpr int NP = NR * (NR + 1) / 2;
-      constexpr int GC = CT / NP;           // chunks of the Gram sums
-      const int Qb = s.Qb, Kq = s.Kq;
-      const int mq = (ml + Qb - 1) / Qb;    // own rows per partition of F^T P
-      const int kc = (K + Kq - 1) / Kq;     // segments per range of P A^T
       double* FtP = scr;                    // [NR][K] totals (after the meeting)
+      const int nt = (K + 15) / 16;         // 16-segment tiles of F^T P
       for (int sweep = -1; sweep < a.sweeps; ++sweep) {
-        // ---- partial F^T F (pair k, rows h mod GC) and F^T P over own rows
+        // ---- partial F^T P (tiles 0 .. nt-1) and F^T F (tile nt) over own
+        // rows on FP64 MFMA, written straight to this workgroup's slot
         double* xs = slot(r, ex);
-        if (t < NP * GC) {
-          const int k = t % NP, h = t / NP;
-          int n1, n2;
-          pair_of<NR>(k, n1, n2);
-          double v = 0.0;
-          for (int m = h; m < ml; m += GC) v += F[m * R8 + n1] * F[m * R8 + n2];
-          red2[h * NP + k] = v;
-        }
-        for (int e = t; e < Qb * K; e += CT) {
-          const int q = e / K, i = e - q * K;
-          const int m0 = q * mq, m1 = min(ml, m0 + mq);
-          double fp[NR];
-#pragma unroll
-          for (int n = 0; n < NR; ++n) fp[n] = 0.0;
-#pragma unroll 4
-          for (int m = m0; m < m1; ++m) {
-            const double pv = (double)Pl[m * Kp + i];
-#pragma unroll
-            for (int n = 0; n < NR; ++n) fp[n] += F[m * R8 + n] * pv;
+        for (int ti = wv; ti <= nt; ti += CW) {
+          const bool gram = ti == nt;
+          const int i = ti * 16 + lr;
+          d4 acc = {0.0, 0.0, 0.0, 0.0};
+          for (int m0 = 0; m0 < ml; m0 += 4) {
+            const int m = m0 + lk;
+            const double fv = m < ml && lr < NR ? F[m * R8 + lr] : 0.0;
+            const double pv = gram ? fv : (m < ml && i < K ? (double)Pl[m * Kp + i] : 0.0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fv, pv, acc, 0, 0, 0);
           }
 #pragma unroll
-          for (int n = 0; n < NR; ++n) scr[((size_t)q * NR + n) * K + i] = fp[n];
-        }
-        __syncthreads();
-        if (t < NP) {
-          double v = 0.0;
-          for (int h = 0; h < GC; ++h) v += red2[h * NP + t];
-          put(xs + R8 * K + t, v);
-        }
-        for (int e = t; e < NR * K; e += CT) {
-          double v = 0.0;
-          for (int q = 0; q < Qb; ++q) v += scr[(size_t)q * NR * K + e];
-          put(xs + e, v);
+          for (int j = 0; j < 4; ++j) {
+            const int n = 4 * j + lk;
+            if (n < NR) {
+              if (gram) {
+                if (lr < NR) put(xs + R8 * K + n * R8 + lr, acc[j]);
+              } else if (i < K) {
+                put(xs + (size_t)n * K + i, acc[j]);
+              }
+            }
+          }
         }
         if (!meet(arrivals, abandoned, error, (ex + 1) * (unsigned)nw, s.limit, &flag)) return false;
         // ---- totals over the component's workgroups (slot order) into LDS
-        if (t < NP) {
+        if (t < NP) {   // upper triangle, mirrored
           int n1, n2;
           pair_of<NR>(t, n1, n2);
-          const double v = gather(R8 * K + t, ex, false);
+          const double v = gather(R8 * K + n1 * R8 + n2, ex, false);
           gF[n1 * R8 + n2] = v;
           gF[n2 * R8 + n1] = v;
         }
@@ -374,48 +364,62 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
         }
         __syncthreads();
         if (sweep < 0) continue;
-        // ---- A A^T (pair k, segments h mod GC), then P A^T of own rows
-        if (t < NP * GC) {
-          const int k = t % NP, h = t / NP;
-          int n1, n2;
-          pair_of<NR>(k, n1, n2);
-          double v = 0.0;
-          for (int i = h; i < K; i += GC) v += A[i * R8 + n1] * A[i * R8 + n2];
-          red2[h * NP + k] = v;
-        }
-        if (t < Kq * mw) {
-          const int m = t % mw, kq = t / mw;
-          if (m < ml) {
-            const int i0 = kq * kc, i1 = min(K, i0 + kc);
-            double gp[NR];
+        // ---- P A^T of own rows (16-row tiles x KS segment parts, waves
+        // 0..11) and A A^T (four segment parts, waves 12..15) on FP64 MFMA
+        {
+          const int rt = (ml + 15) / 16;
+          const int KS = 12 / rt;
+          if (wv < 12) {
+            if (wv < rt * KS) {
+              const int rtile = wv / KS, ks = wv - rtile * KS;
+              const int kc4 = ((K + KS - 1) / KS + 3) & ~3;
+              const int i0 = ks * kc4, i1 = min(K, i0 + kc4);
+              const int m = rtile * 16 + lr;
+              d4 acc = {0.0, 0.0, 0.0, 0.0};
+              for (int ib = i0; ib < i1; ib += 4) {
+                const int i = ib + lk;
+                const double pv = m < ml && i < i1 ? (double)Pl[m * Kp + i] : 0.0;
+                const double av = i < i1 && lr < NR ? A[i * R8 + lr] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pv, av, acc, 0, 0, 0);
+              }
 #pragma unroll
-            for (int n = 0; n < NR; ++n) gp[n] = 0.0;
-#pragma unroll 4
-            for (int i = i0; i < i1; ++i) {
-              const double pv = (double)Pl[m * Kp + i];
-#pragma unroll
-              for (int n = 0; n < NR; ++n) gp[n] += pv * A[i * R8 + n];
+              for (int j = 0; j < 4; ++j)
+                if (lr < R8) scr[((size_t)wv * 16 + 4 * j + lk) * R8 + lr] = acc[j];
+            }
+          } else {
+            const int ka = wv - 12;
+            const int kc4 = ((K + 3) / 4 + 3) & ~3;
+            const int i0 = ka * kc4, i1 = min(K, i0 + kc4);
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int ib = i0; ib < i1; ib += 4) {
+              const int i = ib + lk;
+              const double av = i < i1 && lr < NR ? A[i * R8 + lr] : 0.0;
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, av, acc, 0, 0, 0);
             }
 #pragma unroll
-            for (int n = 0; n < NR; ++n) scr[((size_t)kq * mw + m) * NR + n] = gp[n];
+            for (int j = 0; j < 4; ++j) {
+              const int n1 = 4 * j + lk;
+              if (n1 < R8 && lr < R8) red2[ka * 64 + n1 * R8 + lr] = acc[j];
+            }
           }
+          __syncthreads();
+          if (t < NP) {   // A A^T: the four parts in order, upper triangle mirrored
+            int n1, n2;
+            pair_of<NR>(t, n1, n2);
+            const double v = ((red2[n1 * R8 + n2] + red2[64 + n1 * R8 + n2]) + red2[128 + n1 * R8 + n2]) +
+                             red2[192 + n1 * R8 + n2];
+            gA[n1 * R8 + n2] = v;
+            gA[n2 * R8 + n1] = v;
+          }
+          for (int e = t; e < ml * NR; e += CT) {   // P A^T of own rows: parts in order
+            const int m = e / NR, n = e - m * NR;
+            const int rtile = m >> 4, mm = m & 15;
+            double v = 0.0;
+            for (int ks = 0; ks < KS; ++ks) v += scr[((size_t)(rtile * KS + ks) * 16 + mm) * R8 + n];
+            GP[e] = v;
+          }
+          __syncthreads();
         }
-        __syncthreads();
-        if (t < NP) {
-          int n1, n2;
-          pair_of<NR>(t, n1, n2);
-          double v = 0.0;
-          for (int h = 0; h < GC; ++h) v += red2[h * NP + t];
-          gA[n1 * R8 + n2] = v;
-          gA[n2 * R8 + n1] = v;
-        }
-        for (int e = t; e < ml * NR; e += CT) {   // P A^T of own rows: ranges in order
-          const int m = e / NR, n = e - m * NR;
-          double v = 0.0;
-          for (int kq = 0; kq < Kq; ++kq) v += scr[((size_t)kq * mw + m) * NR + n];
-          GP[e] = v;
-        }
-        __syncthreads();
         // ---- the own F rows (columns of F in order)
         for (int m = t; m < ml; m += CT) {
           double gp[NR], f[NR];
@@ -486,28 +490,13 @@ __global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
   if (i < n) p[i] = v;
 }
 
-// Largest row partitions Qb (<= 4) and segment ranges Kq for which the
-// workgroup's LDS fits the budget; false when even Qb = Kq = 1 does not.
-bool split_fit(int K, int mw, size_t budget, int& Qb, int& Kq, int& scr, size_t& lds);
-
-size_t split_lds(int K, int mw, int Qb, int Kq, int* scr_out) {
+// Dynamic LDS of one workgroup: A [K][R8], F and P A^T [mw][R8], scratch
+// (F^T P totals, the twelve P A^T parts, or the SPA vectors), P rows [mw][Kp].
+size_t split_lds(int K, int mw, int* scr_out) {
   const int Kp = K | 1;
-  const size_t scr = std::max<size_t>({(size_t)Qb * R8 * K, (size_t)Kq * mw * R8, (size_t)K + mw});  // >= R8 K
+  const size_t scr = std::max<size_t>({(size_t)R8 * K, (size_t)12 * 16 * R8, (size_t)K + mw});
   if (scr_out) *scr_out = (int)scr;
   return 8 * ((size_t)K * R8 + 2 * (size_t)mw * R8 + scr) + 4 * (size_t)mw * Kp;
-}
-
-bool split_fit(int K, int mw, size_t budget, int& Qb, int& Kq, int& scr, size_t& lds) {
-  Qb = std::max(1, std::min(4, CT / K));
-  Kq = std::max(1, CT / mw);
-  for (;;) {
-    lds = split_lds(K, mw, Qb, Kq, &scr);
-    if (lds <= budget) return true;
-    if (Qb == 1 && Kq == 1) return false;
-    if ((size_t)Qb * K >= (size_t)Kq * mw && Qb > 1) Qb /= 2;
-    else if (Kq > 1) Kq /= 2;
-    else Qb /= 2;
-  }
 }
 
 }  // namespace
@@ -527,14 +516,18 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
   const int K = a.K;
   const int ncomp = a.ncomp;
   if (K < 1 || ncomp < 1) return false;
-  for (int mw = 32; mw <= CT; mw += 32) {
+  // slice widths in order of preference (measured: 96 rows balance the
+  // per-sweep exchange against the per-workgroup work); at most twelve
+  // 16-row tiles
+  const int widths[] = {96, 128, 160, 192, 64, 32};
+  for (const int mw : widths) {
     long long G = 0;
     for (int k = 0; k < ncomp; ++k) G += (coff[k + 1] - coff[k] + mw - 1) / mw;
     if (G > ncu) continue;                       // one workgroup per compute unit
-    int Qb = 1, Kq = 1, scr = 0;
-    size_t lds = 0;
-    if (!split_fit(K, mw, budget, Qb, Kq, scr, lds)) return false;  // larger slices only need more
-    const int XS = ((R8 * K + NPAIR) + 31) / 32 * 32;
+    int scr = 0;
+    const size_t lds = split_lds(K, mw, &scr);
+    if (lds > budget) continue;
+    const int XS = ((R8 * K + R8 * R8) + 31) / 32 * 32;
     if ((size_t)G * 2 * XS * 8 > xbuf_bytes) return false;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_nmf_split, CT, lds) != hipSuccess || occ < 1)
@@ -542,8 +535,6 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
     s.G = (int)G;
     s.mw = mw;
     s.Kp = K | 1;
-    s.Qb = Qb;
-    s.Kq = Kq;
     s.scr = scr;
     s.XS = XS;
     s.lds_bytes = lds;

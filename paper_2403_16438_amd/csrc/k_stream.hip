@@ -235,7 +235,8 @@ __device__ __forceinline__ void block_body(const KParams& p, int sl, int tile, S
 
   // 40 of the 50 window values live in VGPRs (chunks 0..3); the chunk being
   // filled lives in a per-thread LDS slot, so the frame loop needs no
-  // compile-time frame index. Completed chunks rotate into the registers.
+  // compile-time frame index. The chunk loop is unrolled, so a completed
+  // chunk c moves once into its own registers win[c].
   float win[NCH - 1][CH][NPX];
   float Uacc[NPX], Pacc[5][NPX];
 #pragma unroll
@@ -253,7 +254,7 @@ __device__ __forceinline__ void block_body(const KParams& p, int sl, int tile, S
       if (k < qp.nk) pf[k] = *reinterpret_cast<const uint2*>(fr + qp.off[k]);
   }
 
-#pragma unroll 1
+#pragma unroll
   for (int c = 0; c < NCH; ++c) {
 #pragma unroll 1
     for (int f = 0; f < CH; ++f) {
@@ -326,18 +327,12 @@ __device__ __forceinline__ void block_body(const KParams& p, int sl, int tile, S
     }
     if (c < NCH - 1) {
 #pragma unroll
-      for (int s = 0; s < NCH - 2; ++s)
-#pragma unroll
-        for (int f = 0; f < CH; ++f)
-#pragma unroll
-          for (int i = 0; i < NPX; ++i) win[s][f][i] = win[s + 1][f][i];
-#pragma unroll
       for (int f = 0; f < CH; ++f) {
         const float4 q = Wl[f * NT + tid];
-        win[NCH - 2][f][0] = q.x;
-        win[NCH - 2][f][1] = q.y;
-        win[NCH - 2][f][2] = q.z;
-        win[NCH - 2][f][3] = q.w;
+        win[c][f][0] = q.x;
+        win[c][f][1] = q.y;
+        win[c][f][2] = q.z;
+        win[c][f][3] = q.w;
       }
     }
   }

@@ -172,8 +172,6 @@ struct NmfSplit {
   int G;                 // workgroups of the cooperative grid
   int mw;                // pixels (rows of P_c) per workgroup
   int Kp;                // LDS row stride of the P_c rows (odd)
-  int Qb;                // row partitions of the partial F^T P
-  int Kq;                // segment ranges of the partial P A^T
   int scr;               // doubles of LDS scratch
   int XS;                // doubles per exchange slot
   size_t lds_bytes;      // dynamic LDS per workgroup
