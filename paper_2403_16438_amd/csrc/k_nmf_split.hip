@@ -180,6 +180,26 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
     }
     return v;
   };
+  // two elements at once, twelve slots per round of memory latency
+  auto gather2 = [&](size_t j0, size_t j1, unsigned e, double& v0, double& v1) {
+    v0 = 0.0;
+    v1 = 0.0;
+    for (int wb = 0; wb < nw; wb += 12) {
+      double x[12], y[12];
+#pragma unroll
+      for (int q = 0; q < 12; ++q) {
+        const double* sp = slot(wb + q, e);
+        x[q] = wb + q < nw ? sp[j0] : 0.0;
+        y[q] = wb + q < nw ? sp[j1] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 12; ++q)
+        if (wb + q < nw) {
+          v0 += x[q];
+          v1 += y[q];
+        }
+    }
+  };
 #define MEET() \
   if (!meet(arrivals, abandoned, error, (ex + 1) * (unsigned)nw, s.limit, &flag)) return
 
@@ -339,7 +359,16 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
           gF[n1 * R8 + n2] = v;
           gF[n2 * R8 + n1] = v;
         }
-        for (int e = t; e < NR * K; e += CT) FtP[e] = gather(e, ex, false);
+        for (int e = t; e < NR * K; e += 2 * CT) {
+          if (e + CT < NR * K) {
+            double v0, v1;
+            gather2(e, e + CT, ex, v0, v1);
+            FtP[e] = v0;
+            FtP[e + CT] = v1;
+          } else {
+            FtP[e] = gather(e, ex, false);
+          }
+        }
         ++ex;
         __syncthreads();
         // ---- the A update (rows of A in order), every workgroup alike
