@@ -217,6 +217,24 @@ int seg_set_model(seg_session* s, struct seg_nn* net);
 /* Release the session (not the caller's workspace). NULL is a no-op. */
 int seg_destroy(seg_session* s);
 
+/* Device timing and work of the last seg_finalize (from HIP events recorded
+ * on the caller's stream around the launches; no extra synchronisation). */
+typedef struct seg_profile {
+  float    maps_ms;          /* events, regions, aggregation, components (a7-a9) */
+  float    nmf_ms;           /* the per-component NMF launch (a10)               */
+  double   nmf_flops;        /* its algorithmic FP64 operations: SPA steps plus
+                                HALS products F^T P, P A^T (2 M_c K N each), the
+                                Gram matrices and the row/column updates         */
+  uint32_t nmf_path;         /* SEG_NMF_SINGLE or SEG_NMF_SPLIT as taken         */
+  uint32_t nmf_workgroups;   /* workgroups of that launch                        */
+  uint32_t components;       /* components of the aggregate mask                 */
+  uint32_t max_rank;         /* largest SPA rank among them                      */
+} seg_profile;
+
+/* Fill *out for the last seg_finalize. Errors: SEG_E_INVAL (NULL),
+ * SEG_E_STATE (not finalized). */
+int seg_get_profile(const seg_session* s, seg_profile* out);
+
 /* Static description of a status code. */
 const char* seg_strerror(int code);
 

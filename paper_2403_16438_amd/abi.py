@@ -46,6 +46,15 @@ class seg_config(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class seg_profile(C.Structure):
+    _fields_ = [("maps_ms", C.c_float), ("nmf_ms", C.c_float), ("nmf_flops", C.c_double),
+                ("nmf_path", C.c_uint32), ("nmf_workgroups", C.c_uint32),
+                ("components", C.c_uint32), ("max_rank", C.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class SegError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
@@ -72,6 +81,7 @@ def _load():
         "seg_num_segments": (C.c_int, [P, C.POINTER(u32)]),
         "seg_get_footprints": (C.c_int, [P, u32, C.POINTER(u32), P, P, P, P]),
         "seg_get_image": (C.c_int, [P, C.c_int, P]),
+        "seg_get_profile": (C.c_int, [P, C.POINTER(seg_profile)]),
         "seg_get_segment_maps": (C.c_int, [P, C.c_int, u32, u32, P, P]),
         "seg_load_summaries": (C.c_int, [P, u32, P, P, P, P, P]),
         "seg_destroy": (C.c_int, [P]),
@@ -206,3 +216,8 @@ def seg_push_batch(b, sessions, dev_frames, n_frames, stream: int) -> None:
 def seg_batch_destroy(b) -> None:
     lib.seg_batch_destroy(b)
 
+
+def seg_get_profile(h) -> dict:
+    out = seg_profile()
+    check(lib.seg_get_profile(h, C.byref(out)), "seg_get_profile")
+    return out.as_dict()

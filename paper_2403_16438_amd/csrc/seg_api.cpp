@@ -230,6 +230,14 @@ int seg_create(const seg_config* cfg, void* dev_workspace, size_t bytes, seg_ses
   for (int k = -seg::kMaxRadius; k <= seg::kMaxRadius; ++k)
     s->w[k + seg::kMaxRadius] =
         (k >= -r && k <= r) ? std::exp(-(double)(k * k) / (2.0 * sg * sg)) / sum : 0.0;
+  s->have_ev = true;
+  for (int k = 0; k < 4; ++k)
+    if (hipEventCreate(&s->ev[k]) != hipSuccess) {
+      for (int j = 0; j < k; ++j) (void)hipEventDestroy(s->ev[j]);
+      delete s;
+      return SEG_E_DEVICE;
+    }
+  s->prof = seg_profile{};
   *out = s;
   return SEG_OK;
 }
@@ -370,7 +378,11 @@ int seg_finalize(seg_session* s, void* stream) {
   a.min_event_segs = (int)c.min_event_segs;
   a.have_moments = true;
   a.prob_mode = c.detector == SEG_DET_SURROGATE;
+  s->prof = seg_profile{};
+  bool nmf_timed = false;
+  if ((e = fail(s, hipEventRecord(s->ev[0], st)))) return e;
   if ((e = fail(s, seg::launch_finalize_maps(a, st)))) return e;
+  if ((e = fail(s, hipEventRecord(s->ev[1], st)))) return e;
   int ncomp = 0;
   if ((e = fail(s, hipMemcpyAsync(&ncomp, a.counters, sizeof(int), hipMemcpyDeviceToHost, st)))) return e;
   std::vector<int> comp(s->M);
@@ -439,6 +451,7 @@ int seg_finalize(seg_session* s, void* stream) {
       sp.xbuf = na.P;
       sp.sync = reinterpret_cast<unsigned*>(na.Wk);
       hold.lock();
+      if ((e = fail(s, hipEventRecord(s->ev[2], st)))) return e;
       const hipError_t le = seg::launch_nmf_split(na, sp, st);
       if (le != hipSuccess) {
         (void)hipGetLastError();
@@ -451,8 +464,11 @@ int seg_finalize(seg_session* s, void* stream) {
       int max_mc = 0;
       for (int k = 0; k < ncomp; ++k) max_mc = std::max(max_mc, coff[k + 1] - coff[k]);
       seg::plan_nmf(na, max_mc);
+      if ((e = fail(s, hipEventRecord(s->ev[2], st)))) return e;
       if ((e = fail(s, seg::launch_nmf(na, st)))) return e;
     }
+    if ((e = fail(s, hipEventRecord(s->ev[3], st)))) return e;
+    nmf_timed = true;
     const size_t npx = pix.size();
     std::vector<int> N(ncomp);
     std::vector<double> F(npx * seg::kMaxRank), A((size_t)ncomp * seg::kMaxRank * s->Kmax);
@@ -465,6 +481,24 @@ int seg_finalize(seg_session* s, void* stream) {
     if ((e = fail(s, hipStreamSynchronize(st)))) return e;
     if (hold.owns_lock()) hold.unlock();
     if (split_error) return fail(s, hipErrorLaunchTimeOut);  // a meeting was abandoned
+    // algorithmic work of the NMF (seg_profile)
+    {
+      const double Kd = (double)s->K, S = (double)c.nmf_sweeps;
+      double fl = 0.0;
+      uint32_t rmax = 0;
+      for (int k = 0; k < ncomp; ++k) {
+        const double Mc = (double)(coff[k + 1] - coff[k]), Nn = (double)N[k];
+        rmax = std::max(rmax, (uint32_t)N[k]);
+        fl += (6.0 * Nn + 2.0) * Mc * Kd;                                   // SPA
+        if (N[k] == 0) continue;
+        fl += (S + 1.0) * (2.0 * Mc * Kd * Nn + Mc * Nn * (Nn + 1.0) + 2.0 * Kd * Nn * Nn);  // A updates
+        fl += S * (2.0 * Mc * Kd * Nn + Kd * Nn * (Nn + 1.0) + 2.0 * Mc * Nn * Nn);          // F updates
+      }
+      s->prof.nmf_flops = fl;
+      s->prof.max_rank = rmax;
+      s->prof.nmf_path = split ? SEG_NMF_SPLIT : SEG_NMF_SINGLE;
+      s->prof.nmf_workgroups = split ? (uint32_t)sp.G : (uint32_t)ncomp;
+    }
     const double level = (double)c.footprint_level;
     for (int k = 0; k < ncomp; ++k) {
       const int off = coff[k], Mc = coff[k + 1] - coff[k];
@@ -502,6 +536,12 @@ int seg_finalize(seg_session* s, void* stream) {
                        [](const seg::Footprint& x, const seg::Footprint& y) { return x.peak < y.peak; });
       for (auto& it : items) s->fps.push_back(std::move(it));
     }
+  }
+  s->prof.components = (uint32_t)ncomp;
+  {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->ev[0], s->ev[1]) == hipSuccess) s->prof.maps_ms = ms;
+    if (nmf_timed && hipEventElapsedTime(&ms, s->ev[2], s->ev[3]) == hipSuccess) s->prof.nmf_ms = ms;
   }
   s->state = State::Finalized;
   return SEG_OK;
@@ -583,7 +623,16 @@ int seg_get_segment_maps(seg_session* s, int kind, uint32_t first, uint32_t coun
 }
 
 int seg_destroy(seg_session* s) {
+  if (s && s->have_ev)
+    for (int k = 0; k < 4; ++k) (void)hipEventDestroy(s->ev[k]);
   delete s;
+  return SEG_OK;
+}
+
+int seg_get_profile(const seg_session* s, seg_profile* out) {
+  if (!s || !out) return SEG_E_INVAL;
+  if (s->state != State::Finalized) return SEG_E_STATE;
+  *out = s->prof;
   return SEG_OK;
 }
 

@@ -92,6 +92,9 @@ struct seg_session {
   // results (host copies after finalize)
   uint32_t n_comp;
   std::vector<seg::Footprint> fps;
+  hipEvent_t ev[4];    // finalize timing: maps start/end, NMF start/end
+  bool have_ev;
+  seg_profile prof;
 };
 
 namespace seg {

@@ -76,6 +76,10 @@ class Session:
         abi.seg_get_footprints(self.handle, n, w, m, a, c)
         return dict(weights=w, masks=m.astype(bool), activity=a, component=c)
 
+    def profile(self) -> dict:
+        """Device times (HIP events) and NMF work of the last finalize."""
+        return abi.seg_get_profile(self.handle)
+
     def image(self, kind: int) -> np.ndarray:
         dt = np.float32 if kind in (abi.SEG_IMG_MEAN, abi.SEG_IMG_CORR, abi.SEG_IMG_NOISE) else np.int32
         out = np.zeros((self.H, self.W), dt)

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2403_16438_amd import abi, segment_video
+from paper_2403_16438_amd import Session, abi, segment_video
 from synth import preset, simulate
 
 from parity import compare_footprints, params_from_config
@@ -79,3 +79,31 @@ def test_split_refuses_too_many_segments():
     fp = sess.footprints()
     assert fp["masks"].shape[0] == 1
     assert fp["masks"][0, 5:11, 5:11].all()
+
+
+def test_profile_reports_the_finalize(wide):
+    """seg_get_profile: event-timed device work of the last finalize and the
+    NMF's algorithmic operation count (formula recomputed here from the
+    components and ranks)."""
+    video, sess, ref = wide
+    prof = sess.profile()
+    labels = sess.image(abi.SEG_IMG_LABELS)
+    assert prof["components"] == labels.max() == ref.n_comp
+    assert prof["nmf_path"] == abi.SEG_NMF_SPLIT
+    assert prof["nmf_ms"] > 0.0 and prof["maps_ms"] > 0.0
+    assert 1 <= prof["max_rank"] <= sess.cfg.nmf_max_rank
+    K, S = sess.num_segments, sess.cfg.nmf_sweeps
+    sizes = np.bincount(labels.ravel())[1:]
+    # lower bound with rank 1 for every component, upper with the largest rank
+    lo = sum(8 * m * K + (S + 1) * (2 * m * K + 2 * m + 2 * K) + S * (2 * m * K + 2 * K + 2 * m) for m in sizes)
+    N = prof["max_rank"]
+    hi = sum((6 * N + 2) * m * K + (S + 1) * (2 * m * K * N + m * N * (N + 1) + 2 * K * N * N)
+             + S * (2 * m * K * N + K * N * (N + 1) + 2 * m * N * N) for m in sizes)
+    assert lo <= prof["nmf_flops"] <= hi
+
+
+def test_profile_needs_a_finalize():
+    s = Session(32, 32, 100)
+    with pytest.raises(abi.SegError) as e:
+        s.profile()
+    assert e.value.code == abi.SEG_E_STATE
