@@ -1,0 +1,118 @@
+"""Parity at the workload sizes, in the launch configuration bench.py times.
+
+256 x 256 x 10,000 (the benchmark video, seed 2000, pushed in one call as
+bench.py does): the whole FP64 oracle against the GPU path. The bars are
+those of the small parity tests: summary images within 1e-4, counts and
+labels bit-exact outside the threshold window, footprints with IoU >= 0.99.
+
+512 x 512 x 20,000 streamed in 500-frame blocks: the oracle on sampled
+segments (their summaries), the block push against a single push of the
+whole video (bit-exact, all outputs), and footprints against the planted
+truth.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2403_16438_amd import abi, Session, to_device_frames
+from synth import preset, simulate
+from synth.gpu import GpuScene
+
+from parity import EVENT_WINDOW, assert_image_close, compare_footprints, params_from_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bench_video():
+    video, truth = simulate(preset(2), 2000)
+    T, H, W = video.shape
+    sess = Session(H, W, T)
+    sess.push(to_device_frames(video, torch.device("cuda:0")))
+    sess.finalize()
+    torch.cuda.synchronize()
+    prm = params_from_config(sess.cfg)
+    ref = oracle.segment(video, prm)
+    return video, truth, sess, prm, ref
+
+
+def test_benchmark_video_summaries(bench_video):
+    video, truth, sess, prm, ref = bench_video
+    assert sess.num_segments == 200
+    S = sess.segment_maps(abi.SEG_MAP_S).cpu().numpy()
+    T = sess.segment_maps(abi.SEG_MAP_T).cpu().numpy()
+    assert np.array_equal(S, ref.S.astype(np.float32))
+    for i in range(0, 200, 7):
+        assert_image_close(T[i], ref.T[i], what=f"T[{i}]")
+    assert_image_close(T, ref.T, what="T (all segments)")
+    assert_image_close(sess.image(abi.SEG_IMG_NOISE), ref.sigma, what="sigma")
+    assert_image_close(sess.image(abi.SEG_IMG_MEAN), ref.mean, what="mean")
+    assert_image_close(sess.image(abi.SEG_IMG_CORR), ref.corr, what="corr")
+
+
+def test_benchmark_video_events_and_labels(bench_video):
+    video, truth, sess, prm, ref = bench_video
+    window = (ref.event_margin <= EVENT_WINDOW * prm.event_z).any(0)
+    count = sess.image(abi.SEG_IMG_EVENT_COUNT)
+    assert np.array_equal(count[~window], ref.count[~window])
+    if not window.any():
+        assert np.array_equal(sess.image(abi.SEG_IMG_MASK_COUNT), ref.nb)
+        assert np.array_equal(sess.image(abi.SEG_IMG_LABELS), ref.labels)
+
+
+def test_benchmark_video_footprints(bench_video):
+    video, truth, sess, prm, ref = bench_video
+    fp = sess.footprints()
+    assert len(ref.footprints) >= 20
+    compare_footprints(fp, ref.footprints)
+    assert oracle.match_f1(fp["masks"], truth.masks())["f1"] >= 0.9
+
+
+@pytest.fixture(scope="module")
+def large_field():
+    cfg = preset(3)
+    scene = GpuScene(cfg, 3000)
+    T, H, W = cfg.frames, cfg.height, cfg.width
+    video = scene.render(0, T)                                  # device, 10.5 GB
+    blocks = Session(H, W, T)
+    for t0 in range(0, T, 500):
+        blocks.push(video[t0:t0 + 500])
+    blocks.finalize()
+    whole = Session(H, W, T)
+    whole.push(video)
+    whole.finalize()
+    torch.cuda.synchronize()
+    return cfg, scene, video, blocks, whole
+
+
+def test_large_field_sampled_segments(large_field):
+    cfg, scene, video, blocks, whole = large_field
+    prm = params_from_config(blocks.cfg)
+    for i in (0, 173, 399):
+        seg = video[50 * i:50 * (i + 1)].cpu().numpy().view(np.uint16)
+        ref = oracle.summarize_segment(seg, prm)
+        S = blocks.segment_maps(abi.SEG_MAP_S, i, 1).cpu().numpy()[0]
+        T = blocks.segment_maps(abi.SEG_MAP_T, i, 1).cpu().numpy()[0]
+        assert np.array_equal(S, ref["S"].astype(np.float32)), i
+        assert_image_close(T, ref["T"], what=f"T[{i}]")
+
+
+def test_large_field_blocks_equal_whole(large_field):
+    cfg, scene, video, blocks, whole = large_field
+    for kind in (abi.SEG_MAP_S, abi.SEG_MAP_T, abi.SEG_MAP_P):
+        assert torch.equal(blocks.segment_maps(kind), whole.segment_maps(kind)), kind
+    for kind in (abi.SEG_IMG_NOISE, abi.SEG_IMG_CORR, abi.SEG_IMG_LABELS):
+        assert np.array_equal(blocks.image(kind), whole.image(kind)), kind
+    a, b = blocks.footprints(), whole.footprints()
+    assert np.array_equal(a["weights"], b["weights"])
+    assert np.array_equal(a["activity"], b["activity"])
+
+
+def test_large_field_truth(large_field, record_property):
+    cfg, scene, video, blocks, whole = large_field
+    fp = blocks.footprints()
+    f1 = oracle.match_f1(fp["masks"], scene.truth.masks())
+    record_property("f1_512", f1["f1"])
+    print("512x512x20000: footprints", fp["masks"].shape[0], "truth", len(scene.truth.masks()), "F1", f1)
+    assert f1["f1"] >= 0.7

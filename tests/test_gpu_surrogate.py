@@ -89,3 +89,33 @@ def test_gain_over_plain(trained, record_property):
     assert dim[1] > dim[0], dim              # the gain where the threshold fails
     assert default[0] >= 0.85, default        # the plain method on its own terms
     assert default[1] >= 0.6, default         # the surrogate stays usable there
+
+
+def test_benchmark_shaped_video(trained, record_property):
+    """The trained network against the plain path on a 256 x 256 x 10,000
+    video of the benchmark's shape: footprint F1 of both and their push
+    times (recorded; the surrogate is expected to be slower here)."""
+    import time
+    net, _ = trained
+    cfg = preset(2)
+    scene = GpuScene(cfg, 2001)
+    video = scene.render(0, cfg.frames)
+    out = {}
+    for name in ("plain", "surrogate"):
+        if name == "plain":
+            s = Session(256, 256, cfg.frames)
+        else:
+            s = Session(256, 256, cfg.frames, detector=abi.SEG_DET_SURROGATE, event_z=0.5, min_event_segs=2)
+            s.set_model(for_frames(net, 256, 256))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.push(video)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.finalize()
+        f1 = oracle.match_f1(s.footprints()["masks"], scene.truth.masks())["f1"]
+        out[name] = (f1, t1 - t0)
+        record_property(f"{name}_f1_push_s", out[name])
+    print("256x256x10000 (F1, push s):", out)
+    assert out["plain"][0] >= 0.9
+    assert out["surrogate"][0] >= 0.4
