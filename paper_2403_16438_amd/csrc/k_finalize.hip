@@ -2,7 +2,8 @@
 //   pointwise   noise scale sigma(x), mean image (Eq. 1 averaged), pooled
 //               co-moments and the 8-neighbour correlation image
 //   events      z_i = T_i / sigma, e_i = [z_i >= theta], p_i = max(0, z_i - theta),
-//               event count per pixel (a per-pixel loop over segments: no atomics)
+//               event count per pixel (segment chunks on the grid's y axis,
+//               integer atomics, so the count does not depend on the order)
 //   regions     8-connected components of every e_i by union-find whose roots
 //               are the minimum pixel index of each component; roots are
 //               compacted into region ids; per region: area, first and second
@@ -94,6 +95,8 @@ __global__ void k_pointwise(FinalizeArgs a, const double* __restrict__ C) {
   }
   a.sigma[x] = sqrt(2.0 * 3.14159265358979323846) * sd / (double)a.K;
   a.mean[x] = (float)(ss / (double)a.K);
+  a.count[x] = 0;   // accumulated by k_events
+  a.nb[x] = 0;      // accumulated by k_kept
   // correlation image: mean of rho over in-frame 8-neighbours
   const int yy = x / a.W, xx = x - yy * a.W;
   const int dy[4] = {0, 1, 1, 1};
@@ -117,14 +120,23 @@ __global__ void k_pointwise(FinalizeArgs a, const double* __restrict__ C) {
 
 // ------------------------------------------------------------------- events
 
+constexpr int KCH = 8;   // segment chunks of the per-pixel loops (grid y)
+
+__device__ __forceinline__ void seg_chunk(int K, int& i0, int& i1) {
+  const int per = (K + KCH - 1) / KCH;
+  i0 = min(K, (int)blockIdx.y * per);
+  i1 = min(K, i0 + per);
+}
+
 __global__ void k_events(FinalizeArgs a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= a.M) return;
   const double s = a.sigma[x];
   const bool ok = s >= a.sigma_floor;
-  int cnt = 0;
-#pragma unroll 8
-  for (int i = 0; i < a.K; ++i) {
+  int cnt = 0, i0, i1;
+  seg_chunk(a.K, i0, i1);
+#pragma unroll 4
+  for (int i = i0; i < i1; ++i) {
     const long long g = (long long)i * a.M + x;
     bool e;
     if (a.prob_mode) {
@@ -137,7 +149,7 @@ __global__ void k_events(FinalizeArgs a) {
     a.lab[g] = e ? (int)g : -1;
     cnt += e;
   }
-  a.count[x] = cnt;
+  if (cnt) atomicAdd(&a.count[x], cnt);
 }
 
 // ------------------------------------------------- connected components
@@ -150,13 +162,22 @@ __global__ void k_ccl_merge(int* __restrict__ lab, int H, int W, long long n) {
   const long long M = (long long)H * W;
   const int x = (int)(g % M);
   const int yy = x / W, xx = x - yy * W;
-  // neighbours already visited in raster order: W, NW, N, NE
-  if (xx > 0 && lab[g - 1] >= 0) uf_unite(lab, (int)g, (int)(g - 1));
-  if (yy > 0) {
-    const long long up = g - W;
+  // neighbours earlier in raster order: W, NW, N, NE. Every foreground pixel
+  // links its own, so links implied by a neighbour's are skipped: with W
+  // set, W has linked NW and N (or N through NW), leaving NE when N is
+  // clear; with N set, N has linked NW, and NE links N itself.
+  const bool w = xx > 0 && lab[g - 1] >= 0;
+  const long long up = g - W;
+  const bool n_ = yy > 0 && lab[up] >= 0;
+  const bool ne = yy > 0 && xx + 1 < W && lab[up + 1] >= 0;
+  if (w) {
+    uf_unite(lab, (int)g, (int)(g - 1));
+    if (!n_ && ne) uf_unite(lab, (int)g, (int)(up + 1));
+  } else if (n_) {
+    uf_unite(lab, (int)g, (int)up);
+  } else if (yy > 0) {
     if (xx > 0 && lab[up - 1] >= 0) uf_unite(lab, (int)g, (int)(up - 1));
-    if (lab[up] >= 0) uf_unite(lab, (int)g, (int)up);
-    if (xx + 1 < W && lab[up + 1] >= 0) uf_unite(lab, (int)g, (int)(up + 1));
+    if (ne) uf_unite(lab, (int)g, (int)(up + 1));
   }
 }
 
@@ -437,17 +458,24 @@ __global__ __launch_bounds__(64) void k_region_decide(FinalizeArgs a, const int*
 __global__ void k_kept(FinalizeArgs a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= a.M) return;
-  int nb = 0;
-#pragma unroll 8
-  for (int i = 0; i < a.K; ++i) {
+  int nb = 0, i0, i1;
+  seg_chunk(a.K, i0, i1);
+#pragma unroll 4
+  for (int i = i0; i < i1; ++i) {
     const long long g = (long long)i * a.M + x;
     const int l = a.lab[g];
     const int b = l >= 0 ? a.reg_keep[a.rid[l]] : 0;
     a.bmask[g] = (uint8_t)b;
     nb += b;
   }
-  a.nb[x] = nb;
-  a.blab[x] = nb >= a.min_event_segs ? x : -1;
+  if (nb) atomicAdd(&a.nb[x], nb);
+}
+
+// the aggregate mask b = [n_b >= c_min] as union-find seeds
+__global__ void k_aggregate(FinalizeArgs a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.M) return;
+  a.blab[x] = a.nb[x] >= a.min_event_segs ? x : -1;
 }
 
 __global__ void k_component_labels(FinalizeArgs a) {
@@ -482,7 +510,7 @@ hipError_t launch_finalize_maps(const FinalizeArgs& a, hipStream_t st) {
   const long long KM = (long long)a.K * a.M;
   hipLaunchKernelGGL(k_moments, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a, C);
   hipLaunchKernelGGL(k_pointwise, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a, (const double*)C);
-  hipLaunchKernelGGL(k_events, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a);
+  hipLaunchKernelGGL(k_events, dim3(blocks(a.M, BS), KCH), dim3(BS), 0, st, a);
   hipLaunchKernelGGL(k_ccl_merge, dim3(blocks(KM, BS)), dim3(BS), 0, st, a.lab, a.H, a.W, KM);
   hipLaunchKernelGGL(k_ccl_flatten, dim3(blocks(KM, BS)), dim3(BS), 0, st, a.lab, KM);
   hipError_t e = compact_roots(a.lab, KM, a.scan, a.scan_cap, &a.counters[1], a.rid, st);
@@ -490,7 +518,8 @@ hipError_t launch_finalize_maps(const FinalizeArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_region_zero, dim3(1024), dim3(BS), 0, st, a, root);
   hipLaunchKernelGGL(k_region_accum, dim3(blocks(KM, BS)), dim3(BS), 0, st, a, KM, root);
   hipLaunchKernelGGL(k_region_decide, dim3(4096), dim3(64), 0, st, a, (const int*)root);
-  hipLaunchKernelGGL(k_kept, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a);
+  hipLaunchKernelGGL(k_kept, dim3(blocks(a.M, BS), KCH), dim3(BS), 0, st, a);
+  hipLaunchKernelGGL(k_aggregate, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a);
   hipLaunchKernelGGL(k_ccl_merge, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a.blab, a.H, a.W, (long long)a.M);
   hipLaunchKernelGGL(k_ccl_flatten, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a.blab, (long long)a.M);
   // component ids reuse the rid array (the per-segment ids are no longer needed)
