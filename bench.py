@@ -127,6 +127,8 @@ def serve_bench(args):
         "wall_s": out["wall_s"], "peak_admitted_gb": out["peak_bytes"] / 2 ** 30,
         "budget_gb": args.budget_gb,
         "max_admission_wait_s": max(out["admit_wait_s"].values()),
+        "admission_s": {"mean": float(np.mean(out["admit_s"])), "max": float(np.max(out["admit_s"]))},
+        "longest_loop_stalls_s": [round(g, 4) for g, _ in out["loop_gaps"][:5]],
         "data": "synthetic (GPU-rendered sessions, seeds 5000+s)",
         "config": {"workload": "16 sessions, frame sizes {128^2, 256^2, 512x128, 512^2}, "
                                "500-1000 fps, Poisson arrivals (0.5 s mean gap), 500-frame blocks"},

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
   const int g = blockIdx.x, t = threadIdx.x;
   const int wv = t >> 6, lr = t & 15, lk = (t >> 4) & 3;   // wave, MFMA lane row / k
   const int c = s.wg_comp[g];
-  const int w0 = s.wg_base[c], nw = s.wg_base[c + 1] - w0, r = g - w0;
+  const int w0 = s.wg_base[c], nw = s.wg_n[c], r = g - w0;
   const int off = a.coff[c], Mc = a.coff[c + 1] - off;
   const int mw = s.mw, lo = r * mw, ml = min(mw, Mc - lo);  // own rows [lo, lo + ml)
   const int K = a.K, Kp = s.Kp;
@@ -531,7 +531,7 @@ size_t split_lds(int K, int mw, int* scr_out) {
 }  // namespace
 
 bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff, size_t xbuf_bytes,
-                    std::vector<int>& wg_comp, std::vector<int>& wg_base) {
+                    NmfSplitTables& tab) {
   int dev = 0, coop = 0, ncu = 0, max_lds = 0, clock_khz = 0;
   if (hipGetDevice(&dev) != hipSuccess) return false;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
@@ -545,48 +545,78 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
   const int K = a.K;
   const int ncomp = a.ncomp;
   if (K < 1 || ncomp < 1) return false;
-  // slice widths in order of preference (measured: 96 rows balance the
-  // per-sweep exchange against the per-workgroup work); at most twelve
-  // 16-row tiles
+  const int XS = ((R8 * K + R8 * R8) + 31) / 32 * 32;
+  if ((size_t)ncu * 2 * XS * 8 > xbuf_bytes) return false;
+  // Slice widths in order of preference (measured: 96 rows balance the
+  // per-sweep exchange against the per-workgroup work; at most twelve
+  // 16-row tiles). Components are packed, in order, into launches of at most
+  // one workgroup per compute unit; each launch costs about the same (its
+  // sweeps are latency bound), so the width with the fewest launches wins.
   const int widths[] = {96, 128, 160, 192, 64, 32};
+  int best_mw = 0, best_groups = 0;
   for (const int mw : widths) {
-    long long G = 0;
-    for (int k = 0; k < ncomp; ++k) G += (coff[k + 1] - coff[k] + mw - 1) / mw;
-    if (G > ncu) continue;                       // one workgroup per compute unit
     int scr = 0;
-    const size_t lds = split_lds(K, mw, &scr);
-    if (lds > budget) continue;
-    const int XS = ((R8 * K + R8 * R8) + 31) / 32 * 32;
-    if ((size_t)G * 2 * XS * 8 > xbuf_bytes) return false;
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_nmf_split, CT, lds) != hipSuccess || occ < 1)
-      return false;
-    s.G = (int)G;
-    s.mw = mw;
-    s.Kp = K | 1;
-    s.scr = scr;
-    s.XS = XS;
-    s.lds_bytes = lds;
-    s.limit = (long long)clock_khz * 1000LL * 2;  // two seconds of wall clock
-    wg_comp.assign((size_t)G, 0);
-    wg_base.assign((size_t)ncomp + 1, 0);
-    int gi = 0;
-    for (int k = 0; k < ncomp; ++k) {
-      wg_base[k] = gi;
+    if (split_lds(K, mw, &scr) > budget) continue;
+    int groups = 1, in_group = 0;
+    bool fits = true;
+    for (int k = 0; k < ncomp && fits; ++k) {
       const int nwk = (coff[k + 1] - coff[k] + mw - 1) / mw;
-      for (int j = 0; j < nwk; ++j) wg_comp[gi++] = k;
+      if (nwk > ncu) fits = false;
+      else if (in_group + nwk > ncu) {
+        ++groups;
+        in_group = nwk;
+      } else {
+        in_group += nwk;
+      }
     }
-    wg_base[ncomp] = gi;
-    return true;
+    if (fits && (best_mw == 0 || groups < best_groups)) {
+      best_mw = mw;
+      best_groups = groups;
+    }
   }
-  return false;
+  if (best_mw == 0) return false;
+  const int mw = best_mw;
+  int scr = 0;
+  const size_t lds = split_lds(K, mw, &scr);
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_nmf_split, CT, lds) != hipSuccess || occ < 1)
+    return false;
+  s.mw = mw;
+  s.Kp = K | 1;
+  s.scr = scr;
+  s.XS = XS;
+  s.lds_bytes = lds;
+  s.limit = (long long)clock_khz * 1000LL * 2;  // two seconds of wall clock
+  tab.comp.clear();
+  tab.base.assign((size_t)ncomp, 0);
+  tab.n.assign((size_t)ncomp, 0);
+  tab.groups.clear();
+  int start = 0, in_group = 0;
+  for (int k = 0; k < ncomp; ++k) {
+    const int nwk = (coff[k + 1] - coff[k] + mw - 1) / mw;
+    if (in_group + nwk > ncu) {
+      tab.groups.push_back({start, in_group});
+      start += in_group;
+      in_group = 0;
+    }
+    tab.base[k] = in_group;              // first workgroup within its launch
+    tab.n[k] = nwk;
+    for (int j = 0; j < nwk; ++j) tab.comp.push_back(k);
+    in_group += nwk;
+  }
+  tab.groups.push_back({start, in_group});
+  s.G = (int)tab.comp.size();
+  return true;
 }
 
-hipError_t launch_nmf_split(const NmfArgs& a, const NmfSplit& s, hipStream_t st) {
-  const int nsync = 2 * a.ncomp + 1;
-  hipLaunchKernelGGL(k_fill_u32, dim3((nsync + 255) / 256), dim3(256), 0, st, s.sync, nsync, 0u);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+hipError_t launch_nmf_split(const NmfArgs& a, const NmfSplit& s, bool first, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (first) {   // the counters and flags of every component, once per plan
+    const int nsync = 2 * a.ncomp + 1;
+    hipLaunchKernelGGL(k_fill_u32, dim3((nsync + 255) / 256), dim3(256), 0, st, s.sync, nsync, 0u);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_nmf_split),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)s.lds_bytes);
   if (e != hipSuccess) return e;

@@ -431,9 +431,9 @@ int seg_finalize(seg_session* s, void* stream) {
     // workgroup tables the SPA-direction area and the meeting counters the
     // SPA-flag area (all three belong to the single-workgroup kernel)
     seg::NmfSplit sp{};
-    std::vector<int> wg_comp, wg_base;
+    seg::NmfSplitTables tabs;
     bool split = c.nmf_path != SEG_NMF_SINGLE &&
-                 seg::plan_nmf_split(sp, na, coff, (size_t)s->M * s->Kmax * 8, wg_comp, wg_base);
+                 seg::plan_nmf_split(sp, na, coff, (size_t)s->M * s->Kmax * 8, tabs);
     if (!split && c.nmf_path == SEG_NMF_SPLIT) return SEG_E_CAPACITY;
     // cooperative grids of concurrent finalizes could each hold part of the
     // device while waiting for the rest: one split NMF at a time per process
@@ -441,18 +441,28 @@ int seg_finalize(seg_session* s, void* stream) {
     std::unique_lock<std::mutex> hold(split_mutex, std::defer_lock);
     if (split) {
       int* tab = at<int>(s, l.nmf_G);
-      if ((e = fail(s, hipMemcpyAsync(tab, wg_comp.data(), wg_comp.size() * 4, hipMemcpyHostToDevice, st))))
+      const size_t G = tabs.comp.size();
+      if ((e = fail(s, hipMemcpyAsync(tab, tabs.comp.data(), G * 4, hipMemcpyHostToDevice, st)))) return e;
+      if ((e = fail(s, hipMemcpyAsync(tab + G, tabs.base.data(), (size_t)ncomp * 4, hipMemcpyHostToDevice, st))))
         return e;
-      if ((e = fail(s, hipMemcpyAsync(tab + wg_comp.size(), wg_base.data(), wg_base.size() * 4,
-                                      hipMemcpyHostToDevice, st))))
+      if ((e = fail(s, hipMemcpyAsync(tab + G + ncomp, tabs.n.data(), (size_t)ncomp * 4, hipMemcpyHostToDevice,
+                                      st))))
         return e;
-      sp.wg_comp = tab;
-      sp.wg_base = tab + wg_comp.size();
+      sp.wg_base = tab + G;
+      sp.wg_n = tab + G + ncomp;
       sp.xbuf = na.P;
       sp.sync = reinterpret_cast<unsigned*>(na.Wk);
       hold.lock();
       if ((e = fail(s, hipEventRecord(s->ev[2], st)))) return e;
-      const hipError_t le = seg::launch_nmf_split(na, sp, st);
+      // launches in order on the stream; each reuses the slots and counters
+      hipError_t le = hipSuccess;
+      for (size_t gi = 0; gi < tabs.groups.size(); ++gi) {
+        seg::NmfSplit one = sp;
+        one.G = tabs.groups[gi].second;
+        one.wg_comp = tab + tabs.groups[gi].first;
+        le = seg::launch_nmf_split(na, one, gi == 0, st);
+        if (le != hipSuccess) break;
+      }
       if (le != hipSuccess) {
         (void)hipGetLastError();
         hold.unlock();

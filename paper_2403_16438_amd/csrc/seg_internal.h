@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 #include "seg.h"
@@ -172,23 +173,32 @@ hipError_t launch_nmf(const NmfArgs& a, hipStream_t st);
 
 // NMF with every component split over co-resident workgroups (k_nmf_split)
 struct NmfSplit {
-  int G;                 // workgroups of the cooperative grid
+  int G;                 // workgroups of one cooperative launch (all of them in the plan)
   int mw;                // pixels (rows of P_c) per workgroup
   int Kp;                // LDS row stride of the P_c rows (odd)
   int scr;               // doubles of LDS scratch
   int XS;                // doubles per exchange slot
   size_t lds_bytes;      // dynamic LDS per workgroup
   long long limit;       // wall-clock ticks a meeting may wait
-  const int* wg_comp;    // [G] component of each workgroup
-  const int* wg_base;    // [ncomp + 1] first workgroup of each component
+  const int* wg_comp;    // [G] component of each workgroup of the launch
+  const int* wg_base;    // [ncomp] first workgroup of each component within its launch
+  const int* wg_n;       // [ncomp] workgroups of each component
   double* xbuf;          // [G][2][XS] exchange slots
   unsigned* sync;        // [2 ncomp + 1] arrivals, abandon flags, error flag
 };
-// Chooses the split (smallest slice with one workgroup per compute unit that
-// fits LDS and xbuf_bytes); false when the split path does not apply. Fills
-// the host copies of the workgroup tables.
+// Host copies of the workgroup tables and the launches (first workgroup in
+// `comp`, workgroup count) of a split plan.
+struct NmfSplitTables {
+  std::vector<int> comp, base, n;
+  std::vector<std::pair<int, int>> groups;
+};
+// Chooses the slice width (fewest launches of at most one workgroup per
+// compute unit that fit LDS and xbuf_bytes) and packs the components into
+// launches; false when the split path does not apply.
 bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff, size_t xbuf_bytes,
-                    std::vector<int>& wg_comp, std::vector<int>& wg_base);
-hipError_t launch_nmf_split(const NmfArgs& a, const NmfSplit& s, hipStream_t st);
+                    NmfSplitTables& tab);
+// One launch of the plan (s.G and s.wg_comp select it); `first` clears the
+// meeting counters and flags of all components.
+hipError_t launch_nmf_split(const NmfArgs& a, const NmfSplit& s, bool first, hipStream_t st);
 
 }  // namespace seg

@@ -1,9 +1,11 @@
 """Streaming server: concurrent recording sessions with continuous batching.
 
-* Admission by HBM budget: a session is admitted when its workspace plus its
-  two frame-block staging buffers fit in what the budget has left; otherwise
-  it waits in a FIFO queue and is admitted when a finishing session frees
-  memory.
+* Admission by HBM budget: the budget is one device allocation made when the
+  server starts (an arena), carved first-fit into session workspaces and
+  frame-block staging buffers, so that nothing calls the device allocator
+  while sessions stream. A session is admitted when its workspace plus its
+  two staging buffers fit in the arena; otherwise it waits in a FIFO queue
+  and is admitted when a finishing session returns its memory.
 * Each admitted session keeps its running state on the device (the library
   workspace). Its camera releases one block of frames every
   block_frames / fps seconds; the block is rendered into a staging buffer on
@@ -29,6 +31,41 @@ import torch
 
 from . import abi
 from .session import Session
+
+
+class Arena:
+    """One device allocation carved into 256-byte aligned pieces (first fit,
+    neighbouring free pieces merged on release)."""
+
+    def __init__(self, nbytes: int, device):
+        self.nbytes = (int(nbytes) + 255) & ~255
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.free = [(0, self.nbytes)]          # sorted (offset, size)
+
+    def alloc(self, n: int):
+        n = (int(n) + 255) & ~255
+        for k, (o, sz) in enumerate(self.free):
+            if sz >= n:
+                if sz == n:
+                    self.free.pop(k)
+                else:
+                    self.free[k] = (o + n, sz - n)
+                return o, n
+        return None
+
+    def release(self, o: int, n: int) -> None:
+        self.free.append((o, n))
+        self.free.sort()
+        merged = []
+        for fo, fs in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == fo:
+                merged[-1] = (merged[-1][0], merged[-1][1] + fs)
+            else:
+                merged.append((fo, fs))
+        self.free = merged
+
+    def view(self, o: int, n: int) -> torch.Tensor:
+        return self.buf[o:o + n]
 
 
 class Batch:
@@ -77,7 +114,7 @@ class _Live:
     sess: Session
     scene: object
     staging: list
-    nbytes: int
+    piece: tuple               # (offset, bytes) in the arena
     admitted: float
     rendered: int = 0          # blocks rendered into staging
     pushed: int = 0            # blocks pushed
@@ -99,19 +136,32 @@ class Server:
         self.compute = torch.cuda.Stream(self.device)
         self.camera = torch.cuda.Stream(self.device)
         self.finals = torch.cuda.Stream(self.device)
+        self.arena = Arena(self.budget, self.device)
 
     @staticmethod
-    def session_bytes(spec: SessionSpec) -> int:
+    def workspace_bytes(spec: SessionSpec) -> int:
         c = spec.cfg
         cfg = abi.seg_default_config(c.height, c.width, spec.blocks * spec.block_frames)
-        return abi.seg_workspace_bytes(cfg) + 256 + 2 * spec.block_frames * c.height * c.width * 2
+        return (abi.seg_workspace_bytes(cfg) + 256 + 255) & ~255
+
+    @staticmethod
+    def staging_bytes(spec: SessionSpec) -> int:
+        return (spec.block_frames * spec.cfg.height * spec.cfg.width * 2 + 255) & ~255
+
+    @classmethod
+    def session_bytes(cls, spec: SessionSpec) -> int:
+        return cls.workspace_bytes(spec) + 2 * cls.staging_bytes(spec)
 
     def run(self, specs, on_block=None) -> dict:
         from synth.gpu import GpuScene
         specs = sorted(specs, key=lambda s: s.arrival)
         for s in specs:
-            if self.session_bytes(s) > self.budget:
+            if self.session_bytes(s) > self.arena.nbytes:
                 raise ValueError(f"session {s.name} alone exceeds the HBM budget")
+        # the cameras (synthetic scenes rendering frames on the GPU) exist
+        # before the server starts, as the recording hardware would
+        scenes = {sp.name: GpuScene(sp.cfg, sp.seed, self.device) for sp in specs}
+        torch.cuda.synchronize(self.device)
         t0 = time.perf_counter()
         now = lambda: (time.perf_counter() - t0) * self.time_scale   # recording time (s)
         pending = list(specs)
@@ -127,11 +177,24 @@ class Server:
         nblocks = 0
         frames_done = 0
         pool = ThreadPoolExecutor(1)
+        admit_s = []        # wall seconds spent admitting each session
+        gaps = []           # (gap seconds, recording time) of the longest loop iterations
+        t_prev = time.perf_counter()
 
         def release_time(lv, j):
             return lv.spec.arrival + (j + 1) * lv.spec.block_frames / lv.spec.fps
 
+        fin_log = []        # (recording time at start, wall seconds) of each finalize
+
         def finalize(lv):
+            tf = time.perf_counter()
+            tstart = now()
+            try:
+                return _finalize(lv)
+            finally:
+                fin_log.append((tstart, time.perf_counter() - tf))
+
+        def _finalize(lv):
             with torch.cuda.stream(self.finals):
                 self.finals.wait_event(lv.last_event)
                 lv.sess.finalize(self.finals)
@@ -143,21 +206,32 @@ class Server:
             return out
 
         while pending or queue or live:
+            t_it = time.perf_counter()
+            if t_it - t_prev > 0.02:
+                gaps.append((t_it - t_prev, now()))
+            t_prev = t_it
             tnow = now()
             while pending and pending[0].arrival <= tnow:
                 queue.append(pending.pop(0))
             # admission (FIFO, by HBM budget)
-            while queue and used + self.session_bytes(queue[0]) <= self.budget:
-                sp = queue.pop(0)
-                nb = self.session_bytes(sp)
-                with torch.cuda.device(self.device):
-                    sess = Session(sp.cfg.height, sp.cfg.width, sp.blocks * sp.block_frames, self.device)
-                    scene = GpuScene(sp.cfg, sp.seed, self.device)
-                    staging = [torch.empty((sp.block_frames, sp.cfg.height, sp.cfg.width), dtype=torch.int16,
-                                           device=self.device) for _ in range(2)]
-                live[sp.name] = _Live(sp, sess, scene, staging, nb, tnow)
+            while queue:
+                sp = queue[0]
+                piece = self.arena.alloc(self.session_bytes(sp))
+                if piece is None:
+                    break
+                queue.pop(0)
+                ta = time.perf_counter()
+                o, n = piece
+                wsb, sb = self.workspace_bytes(sp), self.staging_bytes(sp)
+                shape = (sp.block_frames, sp.cfg.height, sp.cfg.width)
+                staging = [self.arena.view(o + wsb + k * sb, sb)[:2 * shape[0] * shape[1] * shape[2]]
+                           .view(torch.int16).view(shape) for k in range(2)]
+                sess = Session(sp.cfg.height, sp.cfg.width, sp.blocks * sp.block_frames, self.device,
+                               workspace=self.arena.view(o, wsb))
+                live[sp.name] = _Live(sp, sess, scenes[sp.name], staging, piece, tnow)
+                admit_s.append(time.perf_counter() - ta)
                 admit_wait[sp.name] = tnow - sp.arrival
-                used += nb
+                used += n
                 peak_used = max(peak_used, used)
             # camera: render released blocks (two staging buffers per session)
             for lv in live.values():
@@ -211,7 +285,8 @@ class Server:
                 elif lv.finalizing is not None and lv.finalizing.done():
                     results[name] = lv.finalizing.result()
                     lv.sess.close()
-                    used -= lv.nbytes
+                    self.arena.release(*lv.piece)
+                    used -= lv.piece[1]
                     del live[name]
             if not ready:
                 time.sleep(0.0005)
@@ -225,7 +300,8 @@ class Server:
                     p50_ms=float(np.percentile(lat_ms, 50)) if len(lat) else None,
                     p99_ms=float(np.percentile(lat_ms, 99)) if len(lat) else None,
                     max_ms=float(lat_ms.max()) if len(lat) else None,
-                    admit_wait_s=admit_wait, peak_bytes=peak_used, budget=self.budget)
+                    admit_wait_s=admit_wait, peak_bytes=peak_used, budget=self.budget,
+                    admit_s=admit_s, loop_gaps=sorted(gaps, reverse=True)[:10], finalizes=fin_log)
 
     def close(self):
         self.batch.close()

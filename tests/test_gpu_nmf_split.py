@@ -107,3 +107,25 @@ def test_profile_needs_a_finalize():
     with pytest.raises(abi.SegError) as e:
         s.profile()
     assert e.value.code == abi.SEG_E_STATE
+
+
+def test_split_over_several_launches():
+    """512 x 512 frames with about 90 components need more workgroups than
+    compute units: the split plan packs them into several cooperative
+    launches, and the result matches the one-workgroup-per-component path."""
+    from synth.gpu import GpuScene
+    cfg = preset(2, height=512, width=512, frames=5000, n_neurons=120, n_overlap=24)
+    video = GpuScene(cfg, 4242).render(0, cfg.frames)
+    out = {}
+    for path in (abi.SEG_NMF_SPLIT, abi.SEG_NMF_SINGLE):
+        s = Session(512, 512, cfg.frames, nmf_path=path)
+        s.push(video)
+        s.finalize()
+        out[path] = (s.footprints(), s.profile())
+    fs, ps = out[abi.SEG_NMF_SPLIT]
+    f1, p1 = out[abi.SEG_NMF_SINGLE]
+    assert ps["nmf_path"] == abi.SEG_NMF_SPLIT and p1["nmf_path"] == abi.SEG_NMF_SINGLE
+    assert ps["nmf_workgroups"] > 256          # more than one launch
+    assert np.array_equal(fs["component"], f1["component"])
+    assert np.array_equal(fs["masks"], f1["masks"])
+    assert np.abs(fs["weights"] - f1["weights"]).max() <= 1e-5
