@@ -530,12 +530,12 @@ int seg_finalize(seg_session* s, void* stream) {
         seg::Footprint fp;
         fp.component = k + 1;
         fp.peak = pix[off + arg];
-        fp.weights.assign(s->M, 0.f);
-        fp.mask.assign(s->M, 0);
+        fp.w.resize(Mc);
+        fp.on.resize(Mc);
         for (int m = 0; m < Mc; ++m) {
           const double v = F[(size_t)(off + m) * seg::kMaxRank + n];
-          fp.weights[pix[off + m]] = (float)v;
-          fp.mask[pix[off + m]] = v >= level;
+          fp.w[m] = (float)v;
+          fp.on[m] = v >= level;
         }
         fp.activity.resize(s->K);
         for (uint32_t i = 0; i < s->K; ++i)
@@ -546,6 +546,8 @@ int seg_finalize(seg_session* s, void* stream) {
                        [](const seg::Footprint& x, const seg::Footprint& y) { return x.peak < y.peak; });
       for (auto& it : items) s->fps.push_back(std::move(it));
     }
+    s->comp_pix = std::move(pix);
+    s->comp_off = std::move(coff);
   }
   s->prof.components = (uint32_t)ncomp;
   {
@@ -566,8 +568,19 @@ int seg_get_footprints(seg_session* s, uint32_t capacity, uint32_t* n_out, float
   const uint32_t n = std::min<uint32_t>(capacity, (uint32_t)s->fps.size());
   for (uint32_t j = 0; j < n; ++j) {
     const seg::Footprint& f = s->fps[j];
-    if (weights) std::memcpy(weights + (size_t)j * s->M, f.weights.data(), (size_t)s->M * 4);
-    if (masks) std::memcpy(masks + (size_t)j * s->M, f.mask.data(), s->M);
+    const int off = s->comp_off[f.component - 1];
+    const int* px = s->comp_pix.data() + off;
+    const size_t Mc = f.w.size();
+    if (weights) {
+      float* wj = weights + (size_t)j * s->M;
+      std::memset(wj, 0, (size_t)s->M * 4);
+      for (size_t m = 0; m < Mc; ++m) wj[px[m]] = f.w[m];
+    }
+    if (masks) {
+      uint8_t* mj = masks + (size_t)j * s->M;
+      std::memset(mj, 0, s->M);
+      for (size_t m = 0; m < Mc; ++m) mj[px[m]] = f.on[m];
+    }
     if (activity) std::memcpy(activity + (size_t)j * s->K, f.activity.data(), (size_t)s->K * 4);
     if (component) component[j] = f.component;
   }

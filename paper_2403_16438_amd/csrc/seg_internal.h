@@ -63,11 +63,14 @@ struct Layout {
 
 Layout make_layout(const seg_config& c);
 
+// A footprint is kept sparse: its weights on the pixels of its component
+// (raster order, the session's component pixel lists); seg_get_footprints
+// expands it to dense frames.
 struct Footprint {
-  int component;
-  int peak;
-  std::vector<float> weights;  // [M]
-  std::vector<uint8_t> mask;   // [M]
+  int component;               // 1-based
+  int peak;                    // raster index of the largest weight
+  std::vector<float> w;        // [M_c] weights of the component's pixels
+  std::vector<uint8_t> on;     // [M_c] mask: FP64 weight >= the footprint level
   std::vector<float> activity; // [K]
 };
 
@@ -93,6 +96,7 @@ struct seg_session {
   // results (host copies after finalize)
   uint32_t n_comp;
   std::vector<seg::Footprint> fps;
+  std::vector<int> comp_pix, comp_off;   // component pixel lists (CSR, raster order)
   hipEvent_t ev[4];    // finalize timing: maps start/end, NMF start/end
   bool have_ev;
   seg_profile prof;
