@@ -41,8 +41,8 @@ FLOPS_PER_PXF = 2 * 2 * 25                 # separable 25-tap smoothing, 2 passe
 ROOT = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(ROOT, "paper_2403_16438_amd", "csrc")
 KERNEL_SOURCES = {
-    "k_block_stats": ["k_stream.hip", "gen_selnet.py", "seg_internal.h"],
-    "k_nmf_split": ["k_nmf_split.hip", "seg_internal.h"],
+    "k_block_stats": ["k_stream.hip", "gen_selnet.py", "seg_kernels.h"],
+    "k_nmf_split": ["k_nmf_split.hip", "seg_kernels.h"],
 }
 WORKLOAD = "256x256x10000"
 

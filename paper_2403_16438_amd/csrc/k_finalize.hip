@@ -14,7 +14,7 @@
 //               components of b numbered 1..n by minimum raster index
 #include <climits>
 
-#include "seg_internal.h"
+#include "seg_kernels.h"
 
 // The region decisions repeat the reference arithmetic operation by operation
 // in FP64; no multiply-add contraction anywhere in this file.

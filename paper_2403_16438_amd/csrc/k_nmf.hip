@@ -21,7 +21,7 @@
 // Every reduction has a fixed order, so results are bit-reproducible.
 #include <algorithm>
 
-#include "seg_internal.h"
+#include "seg_kernels.h"
 
 namespace seg {
 namespace {

@@ -30,7 +30,7 @@
 #include <climits>
 #include <type_traits>
 
-#include "seg_internal.h"
+#include "seg_kernels.h"
 
 namespace seg {
 namespace {

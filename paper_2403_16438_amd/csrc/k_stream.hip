@@ -20,7 +20,7 @@
 // values in VGPRs (40) and a per-thread LDS slot (the chunk being filled);
 // after the segment a compare-exchange network gives the
 // median, the maximum and the 25 smallest values.
-#include "seg_internal.h"
+#include "seg_kernels.h"
 #include "selnet_gen.h"
 
 namespace seg {
