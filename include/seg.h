@@ -217,6 +217,26 @@ int seg_set_model(seg_session* s, struct seg_nn* net);
 /* Release the session (not the caller's workspace). NULL is a no-op. */
 int seg_destroy(seg_session* s);
 
+/* Checkpoint and resume of an open session (a long recording, or moving it
+ * to another device). The state is what later pushes and the finalize need:
+ * the frames carried toward the next segment and every completed segment's
+ * summaries (T, S, D, U and the five co-moment sums; for the surrogate
+ * detector also its probability maps), behind a header with the
+ * configuration. Copies are ordered on `stream` and complete on return.
+ *
+ * seg_state_bytes: host bytes seg_export_state writes for this session now.
+ * seg_export_state: write the state to `host` (at least seg_state_bytes).
+ *   Errors: SEG_E_INVAL, SEG_E_STATE (finalized), SEG_E_CAPACITY (buffer too
+ *   small), SEG_E_DEVICE.
+ * seg_import_state: restore a state into a fresh session (nothing pushed)
+ *   created with the same configuration; pushes then continue where the
+ *   exported session stopped, with bit-identical results. Errors: SEG_E_INVAL
+ *   (NULL, not a state, or another configuration), SEG_E_STATE (session not
+ *   fresh), SEG_E_CAPACITY (buffer shorter than the state), SEG_E_DEVICE. */
+int seg_state_bytes(const seg_session* s, size_t* bytes);
+int seg_export_state(seg_session* s, void* host, size_t bytes, void* stream);
+int seg_import_state(seg_session* s, const void* host, size_t bytes, void* stream);
+
 /* Device timing and work of the last seg_finalize (from HIP events recorded
  * on the caller's stream around the launches; no extra synchronisation). */
 typedef struct seg_profile {

@@ -82,6 +82,9 @@ def _load():
         "seg_get_footprints": (C.c_int, [P, u32, C.POINTER(u32), P, P, P, P]),
         "seg_get_image": (C.c_int, [P, C.c_int, P]),
         "seg_get_profile": (C.c_int, [P, C.POINTER(seg_profile)]),
+        "seg_state_bytes": (C.c_int, [P, C.POINTER(C.c_size_t)]),
+        "seg_export_state": (C.c_int, [P, P, C.c_size_t, P]),
+        "seg_import_state": (C.c_int, [P, P, C.c_size_t, P]),
         "seg_get_segment_maps": (C.c_int, [P, C.c_int, u32, u32, P, P]),
         "seg_load_summaries": (C.c_int, [P, u32, P, P, P, P, P]),
         "seg_destroy": (C.c_int, [P]),
@@ -221,3 +224,18 @@ def seg_get_profile(h) -> dict:
     out = seg_profile()
     check(lib.seg_get_profile(h, C.byref(out)), "seg_get_profile")
     return out.as_dict()
+
+
+def seg_export_state(h, stream: int):
+    import numpy as np
+    n = C.c_size_t()
+    check(lib.seg_state_bytes(h, C.byref(n)), "seg_state_bytes")
+    buf = np.empty(n.value, np.uint8)
+    check(lib.seg_export_state(h, buf.ctypes.data_as(C.c_void_p), n.value, C.c_void_p(stream)),
+          "seg_export_state")
+    return buf
+
+
+def seg_import_state(h, buf, stream: int) -> None:
+    check(lib.seg_import_state(h, buf.ctypes.data_as(C.c_void_p), buf.nbytes, C.c_void_p(stream)),
+          "seg_import_state")

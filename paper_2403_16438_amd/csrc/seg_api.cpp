@@ -652,6 +652,105 @@ int seg_destroy(seg_session* s) {
   return SEG_OK;
 }
 
+// ---- checkpoint / resume: header, carried frames, per-segment planes
+namespace {
+
+struct StateHeader {
+  char magic[8];
+  uint32_t version;
+  uint32_t planes;        // FP32 [K][M] planes that follow the carried frames
+  uint64_t frames;
+  uint32_t K, tail_n;
+  seg_config cfg;
+};
+constexpr char kStateMagic[8] = {'S', 'E', 'G', 'S', 'T', 'A', 'T', 'E'};
+
+// T, S, D, U, the five co-moment planes, and the probability maps of the
+// surrogate detector
+uint32_t state_planes(const seg_session* s) { return s->cfg.detector == SEG_DET_SURROGATE ? 10u : 9u; }
+
+float* state_plane(seg_session* s, uint32_t j) {
+  const Layout& l = s->lay;
+  const size_t KM = (size_t)s->Kmax * s->M;
+  switch (j) {
+    case 0: return at<float>(s, l.T);
+    case 1: return at<float>(s, l.S);
+    case 2: return at<float>(s, l.D);
+    case 3: return at<float>(s, l.U);
+    case 9: return at<float>(s, l.p);
+    default: return at<float>(s, l.P) + (size_t)(j - 4) * KM;   // co-moment planes 0..4
+  }
+}
+
+size_t state_size(const seg_session* s) {
+  return sizeof(StateHeader) + (size_t)s->tail_n * s->M * 2 +
+         (size_t)state_planes(s) * s->K * s->M * 4;
+}
+
+}  // namespace
+
+int seg_state_bytes(const seg_session* s, size_t* bytes) {
+  if (!s || !bytes) return SEG_E_INVAL;
+  *bytes = state_size(s);
+  return SEG_OK;
+}
+
+int seg_export_state(seg_session* s, void* host, size_t bytes, void* stream) {
+  int e = enter(s);
+  if (e) return e;
+  if (!host) return SEG_E_INVAL;
+  if (s->state != State::Open) return SEG_E_STATE;
+  if (bytes < state_size(s)) return SEG_E_CAPACITY;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StateHeader h{};
+  std::memcpy(h.magic, kStateMagic, 8);
+  h.version = 1;
+  h.planes = state_planes(s);
+  h.frames = s->frames;
+  h.K = s->K;
+  h.tail_n = s->tail_n;
+  h.cfg = s->cfg;
+  char* out = static_cast<char*>(host);
+  std::memcpy(out, &h, sizeof h);
+  out += sizeof h;
+  const size_t tb = (size_t)s->tail_n * s->M * 2;
+  if (tb && (e = fail(s, hipMemcpyAsync(out, s->ws + s->lay.tail, tb, hipMemcpyDeviceToHost, st)))) return e;
+  out += tb;
+  const size_t pb = (size_t)s->K * s->M * 4;
+  for (uint32_t j = 0; j < h.planes && pb; ++j, out += pb)
+    if ((e = fail(s, hipMemcpyAsync(out, state_plane(s, j), pb, hipMemcpyDeviceToHost, st)))) return e;
+  return fail(s, hipStreamSynchronize(st));
+}
+
+int seg_import_state(seg_session* s, const void* host, size_t bytes, void* stream) {
+  int e = enter(s);
+  if (e) return e;
+  if (!host || bytes < sizeof(StateHeader)) return host ? SEG_E_CAPACITY : SEG_E_INVAL;
+  if (s->state != State::Open || s->frames != 0 || s->K != 0 || s->tail_n != 0) return SEG_E_STATE;
+  StateHeader h;
+  std::memcpy(&h, host, sizeof h);
+  if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1) return SEG_E_INVAL;
+  if (std::memcmp(&h.cfg, &s->cfg, sizeof(seg_config)) != 0 || h.planes != state_planes(s)) return SEG_E_INVAL;
+  if (h.K > s->Kmax || h.tail_n >= (uint32_t)seg::kSegLen ||
+      h.frames != (uint64_t)h.K * seg::kSegLen + h.tail_n)
+    return SEG_E_INVAL;
+  const size_t need = sizeof h + (size_t)h.tail_n * s->M * 2 + (size_t)h.planes * h.K * s->M * 4;
+  if (bytes < need) return SEG_E_CAPACITY;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const char* in = static_cast<const char*>(host) + sizeof h;
+  const size_t tb = (size_t)h.tail_n * s->M * 2;
+  if (tb && (e = fail(s, hipMemcpyAsync(s->ws + s->lay.tail, in, tb, hipMemcpyHostToDevice, st)))) return e;
+  in += tb;
+  const size_t pb = (size_t)h.K * s->M * 4;
+  for (uint32_t j = 0; j < h.planes && pb; ++j, in += pb)
+    if ((e = fail(s, hipMemcpyAsync(state_plane(s, j), in, pb, hipMemcpyHostToDevice, st)))) return e;
+  if ((e = fail(s, hipStreamSynchronize(st)))) return e;
+  s->frames = h.frames;
+  s->K = h.K;
+  s->tail_n = h.tail_n;
+  return SEG_OK;
+}
+
 int seg_get_profile(const seg_session* s, seg_profile* out) {
   if (!s || !out) return SEG_E_INVAL;
   if (s->state != State::Finalized) return SEG_E_STATE;

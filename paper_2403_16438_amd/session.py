@@ -76,6 +76,16 @@ class Session:
         abi.seg_get_footprints(self.handle, n, w, m, a, c)
         return dict(weights=w, masks=m.astype(bool), activity=a, component=c)
 
+    def export_state(self, stream: torch.cuda.Stream | None = None) -> np.ndarray:
+        """Checkpoint of an open session (host bytes, seg_export_state)."""
+        st = (stream or torch.cuda.current_stream(self.device)).cuda_stream
+        return abi.seg_export_state(self.handle, st)
+
+    def import_state(self, state: np.ndarray, stream: torch.cuda.Stream | None = None) -> None:
+        """Resume from a checkpoint (fresh session, same configuration)."""
+        st = (stream or torch.cuda.current_stream(self.device)).cuda_stream
+        abi.seg_import_state(self.handle, np.ascontiguousarray(state, np.uint8), st)
+
     def profile(self) -> dict:
         """Device times (HIP events) and NMF work of the last finalize."""
         return abi.seg_get_profile(self.handle)
