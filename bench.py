@@ -74,9 +74,19 @@ def cpu_baseline(video, sample_frames):
         cores = max([d.get("num_threads", 1) for d in info] + [1])
     except Exception:
         cores = os.cpu_count()
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return dict(value=sample_frames / dt, unit="frames/s", cores=int(cores), kind="oracle",
                 sample=f"first {sample_frames} frames ({sample_frames // SEG_LEN} segments) of the "
-                       f"256x256 video, whole oracle pipeline, {dt:.1f} s")
+                       f"256x256 video, whole oracle pipeline, {dt:.1f} s, on {os.cpu_count()} host "
+                       f"CPUs ({cpu})")
 
 
 def source_hash(kernel):
@@ -168,9 +178,23 @@ def main():
     video, truth = make_video(args.frames, args.seed)
     T, H, W = video.shape
     dev = torch.device("cuda:0")
-    vdev = to_device_frames(video, dev)
     torch.cuda.synchronize()
+    t_h2d = time.perf_counter()
+    vdev = to_device_frames(video, dev)     # pageable host memory to HBM (PCIe)
+    torch.cuda.synchronize()
+    t_h2d = time.perf_counter() - t_h2d
     log("video resident in HBM")
+    # measured copy roof: one device-to-device copy of the resident video
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    copy_s = []
+    for _ in range(3):
+        e0.record()
+        vcopy = vdev.clone()
+        e1.record()
+        e1.synchronize()
+        copy_s.append(e0.elapsed_time(e1) * 1e-3)
+        del vcopy
+    copy_GBps = 2 * vdev.numel() * 2 / min(copy_s) / 1e9
 
     sess0 = Session(H, W, T, dev)
     ws = sess0.workspace
@@ -268,6 +292,13 @@ def main():
         "streaming_frames_per_s": T / k_time,
         "finalize_ms": 1e3 * float(np.mean(tf)),
         "finalize_maps_ms": 1e3 * float(np.mean(tm)),
+        "copy_roof_GBps": copy_GBps,
+        "streaming_frac_of_copy_roof": stream_roof["hbm_algorithmic_GBps"] / copy_GBps,
+        "h2d": {"ms": 1e3 * t_h2d, "GBps": video.nbytes / t_h2d / 1e9,
+                "note": "pageable host buffer to HBM, outside the timed steps"},
+        "paper_context": {"segmentation_s_for_10000_frames": 6.9, "frames_per_s": 1449,
+                          "note": "the paper's segmentation stage on a 450x138 recording, Threadripper "
+                                  "3960X with 2x RTX 2080 Ti (Table I); context only"},
         "nmf": {"path": "split" if prof["nmf_path"] == abi.SEG_NMF_SPLIT else "single",
                 "workgroups": prof["nmf_workgroups"], "components": prof["components"],
                 "max_rank": prof["max_rank"], "component_pixels": comp_px},
