@@ -11,7 +11,9 @@ Prints one JSON line (rank 0): frames/s over the timed steps; the roofline of
 the dominant kernel, i.e. the longer of the streaming summary kernel (timed
 with HIP events recorded on the stream it runs on) and the per-component NMF
 (timed by the library with HIP events on the same stream), with the other
-one beside it; and the CPU oracle timed on a bounded sample.
+one beside it; the voltage traces of the same video (the stage after
+segmentation, outside the step) with their own HBM roofline; and the CPU
+oracle timed on a bounded sample.
 
 `traffic` is the HBM bytes per launch measured by hardware counters
 (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), read from the
@@ -43,6 +45,7 @@ CSRC = os.path.join(ROOT, "paper_2403_16438_amd", "csrc")
 KERNEL_SOURCES = {
     "k_block_stats": ["k_stream.hip", "gen_selnet.py", "seg_kernels.h"],
     "k_nmf_split": ["k_nmf_split.hip", "seg_kernels.h"],
+    "k_traces": ["k_traces.hip", "seg_traces.h"],
 }
 WORKLOAD = "256x256x10000"
 
@@ -262,6 +265,34 @@ def main():
                "hbm_frac": bytes_alg / seconds / HBM_PEAK}
         return out
 
+    # voltage traces (the stage after segmentation) of the resident video,
+    # timed with events on torch's current stream, which the call uses
+    s = step()
+    masks = s.footprints()["masks"]
+    n_tr = masks.shape[0]
+    tr_out = torch.empty((n_tr, T), dtype=torch.float32, device=dev)
+    s.traces(vdev, out=tr_out)          # the first call uploads the mask tables
+    tt = []
+    for _ in range(reps):
+        ev0.record()
+        s.traces(vdev, out=tr_out)
+        ev1.record()
+        ev1.synchronize()
+        tt.append(ev0.elapsed_time(ev1) * 1e-3)
+    s.close()
+    union = masks.any(0).reshape(-1)
+    union_px = int(union.sum())
+    lines = len(np.unique(np.flatnonzero(union) // 64)) if (H * W) % 64 == 0 else None
+    tr_time = float(np.mean(tt))
+    tr_bytes = 2.0 * union_px * T + 4.0 * n_tr * T
+    traces = {"ms": tr_time * 1e3, "frames_per_s": T / tr_time, "footprints": n_tr,
+              "masked_pixels": union_px,
+              "roofline": {"bound": "hbm", "achieved": tr_bytes / tr_time / 1e9, "peak": HBM_PEAK / 1e9,
+                           "unit": "GB/s", "frac": tr_bytes / tr_time / HBM_PEAK,
+                           "traffic": counted_traffic("k_traces"), "kernel": "k_traces",
+                           "algorithmic_bytes_per_launch": tr_bytes,
+                           "line_bytes_per_launch": None if lines is None else 128.0 * lines * T + 4.0 * n_tr * T}}
+
     stream_roof = roof("k_block_stats", k_time, FLOPS_PER_PXF * pxf, BYTES_PER_PXF * pxf)
     # NMF: reads the detection maps of the component pixels (FP32 per
     # segment), writes F (FP64, rank columns) and A (FP64, rank x segments)
@@ -303,6 +334,7 @@ def main():
                 "workgroups": prof["nmf_workgroups"], "components": prof["components"],
                 "max_rank": prof["max_rank"], "component_pixels": comp_px},
         "footprints": n_fp,
+        "traces": traces,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -151,6 +151,29 @@ int seg_get_footprints(seg_session* s, uint32_t capacity, uint32_t* n_out,
                        float* weights, uint8_t* masks, float* activity,
                        int32_t* component);
 
+/* Voltage traces (Sec. II, the stage after segmentation): for every
+ * footprint j of a finalized session and every frame t of dev_frames, the
+ * mean intensity over the footprint's mask (the pixels seg_get_footprints
+ * reports in `masks`):
+ *     trace_j(t) = sum_{x in mask_j} V_t(x) / |mask_j|
+ * The sum is exact (integers); the mean is one FP64 division rounded to FP32.
+ *   dev_frames device uint16 [n_frames][height][width]; any frames of the
+ *              session's size (the segmented recording or later ones)
+ *   dev_out    device float, footprint j's trace at dev_out[j * ld + t],
+ *              t < n_frames; ld >= n_frames. A recording pushed in blocks
+ *              fills one [N][T] array by offsetting dev_out by the block's
+ *              first frame and keeping ld = T.
+ * Work is ordered on `stream`; the call does not synchronise, except for the
+ * first call on a session, which uploads the mask tables (a few bytes per
+ * masked pixel) into the workspace. Nothing is written when N = 0 or
+ * n_frames = 0. The caller owns both buffers.
+ * Errors: SEG_E_INVAL (NULL pointer with n_frames > 0, ld < n_frames),
+ * SEG_E_STATE (not finalized), SEG_E_CAPACITY (the mask tables do not fit
+ * the workspace's NMF factor region; only for frames of a few pixels),
+ * SEG_E_DEVICE. */
+int seg_extract_traces(seg_session* s, const uint16_t* dev_frames, uint64_t n_frames,
+                       float* dev_out, uint64_t ld, void* stream);
+
 /* Copy one SEG_IMG_* image ([height][width], float or int32) to host_out.
  * Every kind needs a finalized session. Errors: SEG_E_INVAL, SEG_E_STATE. */
 int seg_get_image(seg_session* s, int kind, void* host_out);

@@ -81,6 +81,7 @@ def _load():
         "seg_num_segments": (C.c_int, [P, C.POINTER(u32)]),
         "seg_get_footprints": (C.c_int, [P, u32, C.POINTER(u32), P, P, P, P]),
         "seg_get_image": (C.c_int, [P, C.c_int, P]),
+        "seg_extract_traces": (C.c_int, [P, P, C.c_uint64, P, C.c_uint64, P]),
         "seg_get_profile": (C.c_int, [P, C.POINTER(seg_profile)]),
         "seg_state_bytes": (C.c_int, [P, C.POINTER(C.c_size_t)]),
         "seg_export_state": (C.c_int, [P, P, C.c_size_t, P]),
@@ -176,6 +177,11 @@ def seg_get_footprints(h, capacity: int, weights, masks, activity, component) ->
 
 def seg_get_image(h, kind: int, out) -> None:
     check(lib.seg_get_image(h, kind, out.ctypes.data_as(C.c_void_p)), "seg_get_image")
+
+
+def seg_extract_traces(h, dev_frames: int, n_frames: int, dev_out: int, ld: int, stream: int) -> None:
+    check(lib.seg_extract_traces(h, C.c_void_p(dev_frames), n_frames, C.c_void_p(dev_out), ld,
+                                 C.c_void_p(stream)), "seg_extract_traces")
 
 
 def seg_get_segment_maps(h, kind: int, first: int, count: int, dev_out: int, stream: int) -> None:

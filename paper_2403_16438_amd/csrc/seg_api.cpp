@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "seg_internal.h"
+#include "seg_traces.h"
 #include "seg_nn.h"
 
 using seg::Layout;
@@ -546,6 +547,28 @@ int seg_finalize(seg_session* s, void* stream) {
                        [](const seg::Footprint& x, const seg::Footprint& y) { return x.peak < y.peak; });
       for (auto& it : items) s->fps.push_back(std::move(it));
     }
+    // trace tables: per component with footprints, the pixels in at least
+    // one mask and their mask bits (footprints of a component are adjacent)
+    for (size_t j = 0; j < s->fps.size();) {
+      const int k = s->fps[j].component - 1, off = coff[k], Mc = coff[k + 1] - coff[k];
+      size_t e = j;
+      while (e < s->fps.size() && s->fps[e].component == k + 1) ++e;
+      const int begin = (int)s->tr_pix.size();
+      for (int m = 0; m < Mc; ++m) {
+        uint32_t b = 0;
+        for (size_t q = j; q < e; ++q) b |= (uint32_t)s->fps[q].on[m] << (q - j);
+        if (!b) continue;
+        s->tr_pix.push_back(pix[off + m]);
+        s->tr_bits.push_back((uint8_t)b);
+      }
+      s->tr_comp.insert(s->tr_comp.end(), {begin, (int)s->tr_pix.size(), (int)j, (int)(e - j)});
+      for (size_t q = j; q < e; ++q) {
+        uint32_t area = 0;
+        for (uint8_t o : s->fps[q].on) area += o;
+        s->tr_count.push_back(area);
+      }
+      j = e;
+    }
     s->comp_pix = std::move(pix);
     s->comp_off = std::move(coff);
   }
@@ -585,6 +608,47 @@ int seg_get_footprints(seg_session* s, uint32_t capacity, uint32_t* n_out, float
     if (component) component[j] = f.component;
   }
   return SEG_OK;
+}
+
+int seg_extract_traces(seg_session* s, const uint16_t* dev_frames, uint64_t n_frames, float* dev_out,
+                       uint64_t ld, void* stream) {
+  int e = enter(s);
+  if (e) return e;
+  if (s->state != State::Finalized) return SEG_E_STATE;
+  if (ld < n_frames || n_frames > (uint64_t)INT64_MAX / 2) return SEG_E_INVAL;
+  if (n_frames == 0 || s->fps.empty()) return SEG_OK;
+  if (!dev_frames || !dev_out) return SEG_E_INVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!s->tr_ready) {
+    // the NMF factor region is free once the footprints are on the host
+    const size_t n = s->tr_pix.size(), nc = s->tr_comp.size() / 4, base = s->lay.nmf_F;
+    s->tr_at[0] = base;
+    s->tr_at[1] = s->tr_at[0] + seg::align_up(n * 4);
+    s->tr_at[2] = s->tr_at[1] + seg::align_up(n);
+    s->tr_at[3] = s->tr_at[2] + seg::align_up(nc * 16);
+    if (s->tr_at[3] + s->tr_count.size() * 4 > base + (size_t)s->M * seg::kMaxRank * 8) return SEG_E_CAPACITY;
+    const void* src[4] = {s->tr_pix.data(), s->tr_bits.data(), s->tr_comp.data(), s->tr_count.data()};
+    const size_t len[4] = {n * 4, n, nc * 16, s->tr_count.size() * 4};
+    for (int i = 0; i < 4; ++i)
+      if (len[i] && (e = fail(s, hipMemcpyAsync(s->ws + s->tr_at[i], src[i], len[i], hipMemcpyHostToDevice, st))))
+        return e;
+    if ((e = fail(s, hipStreamSynchronize(st)))) return e;
+    s->tr_ready = true;
+  }
+  seg::TraceArgs a{};
+  a.frames = dev_frames;
+  a.n_frames = (long long)n_frames;
+  a.M = (int)s->M;
+  a.ncomp = (int)(s->tr_comp.size() / 4);
+  a.max_fp = 1;
+  for (int k = 0; k < a.ncomp; ++k) a.max_fp = std::max(a.max_fp, s->tr_comp[4 * k + 3]);
+  a.pix = at<int>(s, s->tr_at[0]);
+  a.bits = at<uint8_t>(s, s->tr_at[1]);
+  a.comp = at<int4>(s, s->tr_at[2]);
+  a.count = at<uint32_t>(s, s->tr_at[3]);
+  a.out = dev_out;
+  a.ld = (long long)ld;
+  return fail(s, seg::launch_traces(a, st));
 }
 
 int seg_get_image(seg_session* s, int kind, void* host_out) {

@@ -86,6 +86,14 @@ struct seg_session {
   uint32_t n_comp;
   std::vector<seg::Footprint> fps;
   std::vector<int> comp_pix, comp_off;   // component pixel lists (CSR, raster order)
+  // trace extraction tables (built at finalize, uploaded by the first
+  // seg_extract_traces into the NMF factor region, unused after finalize)
+  std::vector<int> tr_pix;          // masked pixels of every component, raster order
+  std::vector<uint8_t> tr_bits;     // bit r: in the mask of the component's footprint r
+  std::vector<int> tr_comp;         // [4 per component] entry begin, end, first footprint, footprints
+  std::vector<uint32_t> tr_count;   // [N] mask sizes
+  bool tr_ready;
+  size_t tr_at[4];                  // workspace offsets of the four tables
   hipEvent_t ev[4];    // finalize timing: maps start/end, NMF start/end
   bool have_ev;
   seg_profile prof;

@@ -76,6 +76,28 @@ class Session:
         abi.seg_get_footprints(self.handle, n, w, m, a, c)
         return dict(weights=w, masks=m.astype(bool), activity=a, component=c)
 
+    def traces(self, frames: torch.Tensor, out: torch.Tensor | None = None,
+               stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        """Mean intensity of every footprint's mask in each frame (seg_extract_traces).
+
+        frames: contiguous 16-bit [n, H, W] on the session's device. `out`, if
+        given, is a float32 [N, n] view whose rows may be strided (a column
+        slice of a [N, T] array); else a new [N, n] tensor is returned."""
+        if frames.device != self.device or not frames.is_contiguous():
+            raise ValueError("frames must be a contiguous tensor on the session's device")
+        if frames.dtype not in (torch.int16, torch.uint16) or tuple(frames.shape[1:]) != (self.H, self.W):
+            raise ValueError("frames must be 16-bit [n, H, W]")
+        n = abi.seg_get_footprints(self.handle, 0, None, None, None, None)
+        if out is None:
+            out = torch.empty((n, frames.shape[0]), dtype=torch.float32, device=self.device)
+        if (out.dtype != torch.float32 or out.device != self.device or tuple(out.shape) != (n, frames.shape[0])
+                or (out.numel() and out.stride(1) != 1)):
+            raise ValueError("out must be float32 [N, n] on the session's device, unit column stride")
+        st = (stream or torch.cuda.current_stream(self.device)).cuda_stream
+        ld = out.stride(0) if n > 1 else frames.shape[0]
+        abi.seg_extract_traces(self.handle, frames.data_ptr(), frames.shape[0], out.data_ptr(), ld, st)
+        return out
+
     def export_state(self, stream: torch.cuda.Stream | None = None) -> np.ndarray:
         """Checkpoint of an open session (host bytes, seg_export_state)."""
         st = (stream or torch.cuda.current_stream(self.device)).cuda_stream

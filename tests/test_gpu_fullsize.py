@@ -15,6 +15,7 @@ import pytest
 import torch
 
 import oracle
+import oracle.traces as otr
 from paper_2403_16438_amd import abi, Session, to_device_frames
 from synth import preset, simulate
 from synth.gpu import GpuScene
@@ -69,6 +70,16 @@ def test_benchmark_video_footprints(bench_video):
     assert oracle.match_f1(fp["masks"], truth.masks())["f1"] >= 0.9
 
 
+def test_benchmark_video_traces(bench_video):
+    """Traces of every footprint over all 10,000 frames, bit-exact (exact
+    integer sums, one FP64 division on both sides)."""
+    video, truth, sess, prm, ref = bench_video
+    masks = sess.footprints()["masks"]
+    got = sess.traces(to_device_frames(video, torch.device("cuda:0")))
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), otr.extract_traces(video, masks).astype(np.float32))
+
+
 @pytest.fixture(scope="module")
 def large_field():
     cfg = preset(3)
@@ -107,6 +118,19 @@ def test_large_field_blocks_equal_whole(large_field):
     a, b = blocks.footprints(), whole.footprints()
     assert np.array_equal(a["weights"], b["weights"])
     assert np.array_equal(a["activity"], b["activity"])
+
+
+def test_large_field_traces_sampled_frames(large_field):
+    """All 20,000 frames in one call; the oracle on sampled frames."""
+    cfg, scene, video, blocks, whole = large_field
+    masks = blocks.footprints()["masks"]
+    got = blocks.traces(video)
+    torch.cuda.synchronize()
+    assert got.shape == (masks.shape[0], cfg.frames)
+    for t in (0, 1, 4999, 12345, 19984, 19999):
+        frame = video[t:t + 1].cpu().numpy().view(np.uint16)
+        ref = otr.extract_traces(frame, masks).astype(np.float32)[:, 0]
+        assert np.array_equal(got[:, t].cpu().numpy(), ref), t
 
 
 def test_large_field_truth(large_field, record_property):

@@ -1,0 +1,168 @@
+"""Voltage traces (seg_extract_traces) against the FP64 oracle, through the C ABI.
+
+The trace of a footprint is the mean intensity of its mask in each frame
+(Sec. II). Both sides sum the mask's pixels exactly and divide once in FP64,
+so the FP32 traces must be bit-identical to the oracle rounded to FP32. The
+masks are the session's own (seg_get_footprints), so the comparison covers
+the extraction only.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle.traces as otr
+from paper_2403_16438_amd import abi, segment_video, Session, to_device_frames
+from synth import preset, simulate
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _ref(video, masks):
+    return otr.extract_traces(video, masks).astype(np.float32)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    video, truth = simulate(preset(1), 0)
+    sess = segment_video(video)
+    fp = sess.footprints()
+    assert fp["masks"].shape[0] >= 3
+    return video, sess, fp["masks"]
+
+
+def test_recording_traces_bit_exact(c1):
+    video, sess, masks = c1
+    frames = to_device_frames(video, DEV)
+    got = sess.traces(frames)
+    torch.cuda.synchronize()
+    assert got.shape == (masks.shape[0], video.shape[0])
+    assert np.array_equal(got.cpu().numpy(), _ref(video, masks))
+
+
+def test_full_range_frames_and_ragged_frame_counts(c1):
+    """Any frames of the session's size: uniform uint16 up to 65535, frame
+    counts that leave a partial workgroup (1, 15, 17, 1000)."""
+    video, sess, masks = c1
+    rng = np.random.default_rng(11)
+    for n in (1, 15, 17, 1000):
+        v = rng.integers(0, 65536, size=(n,) + video.shape[1:], dtype=np.uint16)
+        got = sess.traces(to_device_frames(v, DEV))
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), _ref(v, masks)), n
+    v = np.full((33,) + video.shape[1:], 65535, np.uint16)
+    got = sess.traces(to_device_frames(v, DEV)).cpu().numpy()
+    assert np.array_equal(got, np.full_like(got, 65535.0))
+
+
+def test_blocks_fill_one_array(c1):
+    """Ragged blocks written into column slices of one [N, T] array (ld = T)
+    equal one call over the whole recording."""
+    video, sess, masks = c1
+    frames = to_device_frames(video, DEV)
+    whole = sess.traces(frames)
+    out = torch.full((masks.shape[0], video.shape[0]), -1.0, device=DEV)
+    t0 = 0
+    for n in (37, 1, 462, 0, 500):
+        sess.traces(frames[t0:t0 + n], out=out[:, t0:t0 + n])
+        t0 += n
+    torch.cuda.synchronize()
+    assert t0 == video.shape[0]
+    assert torch.equal(out, whole)
+
+
+def test_zero_frames_writes_nothing(c1):
+    video, sess, masks = c1
+    out = torch.full((masks.shape[0], 4), 7.0, device=DEV)
+    abi.seg_extract_traces(sess.handle, to_device_frames(video[:1], DEV).data_ptr(), 0, out.data_ptr(), 4,
+                           torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
+
+
+def test_errors(c1):
+    video, sess, masks = c1
+    frames = to_device_frames(video[:10], DEV)
+    out = torch.empty((masks.shape[0], 10), device=DEV)
+    st = torch.cuda.current_stream().cuda_stream
+    with pytest.raises(abi.SegError) as e:
+        abi.seg_extract_traces(sess.handle, frames.data_ptr(), 10, out.data_ptr(), 9, st)
+    assert e.value.code == abi.SEG_E_INVAL
+    with pytest.raises(abi.SegError) as e:
+        abi.seg_extract_traces(sess.handle, 0, 10, out.data_ptr(), 10, st)
+    assert e.value.code == abi.SEG_E_INVAL
+    open_sess = Session(64, 64, 1000)
+    with pytest.raises(abi.SegError) as e:
+        open_sess.traces(frames)
+    assert e.value.code == abi.SEG_E_STATE
+    open_sess.close()
+    # the session is still usable after rejected calls
+    got = sess.traces(frames)
+    assert np.array_equal(got.cpu().numpy(), _ref(video[:10], masks))
+
+
+def test_no_footprints():
+    """A recording without neurons: N = 0, the call succeeds and writes nothing."""
+    cfg = preset(1, n_neurons=0, frames=200)
+    video, _ = simulate(cfg, 5)
+    sess = segment_video(video)
+    assert sess.footprints()["masks"].shape[0] == 0
+    got = sess.traces(to_device_frames(video, DEV))
+    assert got.shape == (0, 200)
+
+
+def test_overlapping_footprints_and_large_mask():
+    """One component with several footprints (mask bits beyond the first) and
+    masks larger than the workgroup's LDS stage (read from HBM directly)."""
+    cfg = preset(1, height=160, width=160, frames=500, n_neurons=1, sigma_range=(27.0, 27.0),
+                 edge_margin=70.0, n_blobs=0, amp_range=(0.2, 0.2), dff_range=(0.3, 0.3),
+                 rate_range=(20.0, 20.0))
+    video, _ = simulate(cfg, 7)
+    sess = segment_video(video, area_max=65536)
+    masks = sess.footprints()["masks"]
+    assert masks.sum(axis=(1, 2)).max() > 4096
+    got = sess.traces(to_device_frames(video, DEV))
+    assert np.array_equal(got.cpu().numpy(), _ref(video, masks))
+
+    # seed 7: the oracle finds three footprints in one component, their
+    # masks sharing about a hundred pixels
+    video, _ = simulate(preset(4, n_overlap=2, n_neurons=4, frames=1000), 7)
+    sess = segment_video(video)
+    fp = sess.footprints()
+    assert np.bincount(fp["component"]).max() >= 2
+    assert (fp["masks"].sum(0) >= 2).any()
+    got = sess.traces(to_device_frames(video, DEV))
+    assert np.array_equal(got.cpu().numpy(), _ref(video, fp["masks"]))
+
+
+def _ring_video(n_cells=6, radius=7.0, sigma=3.0, frames=1000, seed=0):
+    """Hand-built scene: n_cells Gaussian cells on a ring, neighbours
+    overlapping, cell j firing (two frames, +40% of its footprint) in
+    segments j, j + n_cells, ... Poisson-Gaussian noise around 1000."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:64, 0:64].astype(np.float64)
+    cells = []
+    for j in range(n_cells):
+        ang = 2 * np.pi * j / n_cells
+        cx, cy = 32 + radius * np.cos(ang), 32 + radius * np.sin(ang)
+        cells.append(np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / (2 * sigma ** 2)))
+    cells = np.array(cells)
+    act = np.zeros((frames, n_cells))
+    for j in range(n_cells):
+        for seg in range(j, frames // 50, n_cells):
+            act[seg * 50 + 20 + j, j] = 1.0
+            act[seg * 50 + 21 + j, j] = 0.5
+    mean = 1000.0 * (1.0 + 0.4 * np.tensordot(act, cells, axes=1))
+    v = rng.poisson(mean) + rng.normal(0.0, 5.0, mean.shape)
+    return np.clip(np.rint(v), 0, 65535).astype(np.uint16)
+
+
+def test_component_with_many_footprints():
+    """Six overlapping cells in one component (the oracle finds six
+    footprints): mask bits up to the fifth and beyond."""
+    video = _ring_video()
+    sess = segment_video(video)
+    fp = sess.footprints()
+    assert np.bincount(fp["component"]).max() >= 5
+    got = sess.traces(to_device_frames(video, DEV))
+    assert np.array_equal(got.cpu().numpy(), _ref(video, fp["masks"]))
