@@ -156,7 +156,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=10000)
     ap.add_argument("--seed", type=int, default=2000)
-    ap.add_argument("--cpu-sample", type=int, default=500)
+    ap.add_argument("--cpu-sample", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="the 16-session streaming benchmark")
     ap.add_argument("--sessions", type=int, default=16)
