@@ -8,6 +8,7 @@ method's code.
 """
 from .simulate import (SimConfig, Truth, draw, preset, simulate, simulate_frames,
                        session_mix)
+from .motion import draw_motion, move_frames, plant_motion
 
 __all__ = ["SimConfig", "Truth", "draw", "preset", "simulate", "simulate_frames",
-           "session_mix"]
+           "session_mix", "draw_motion", "move_frames", "plant_motion"]
