@@ -1,7 +1,9 @@
 """MI355X-native neuron segmentation for voltage imaging (Bando et al., 2023,
-Sec. III): HIP kernels behind the C ABI of include/seg.h, with a thin Python
-binding. PyTorch supplies device memory and streams only."""
+Sec. III), with the motion correction before it and the voltage traces after
+it (Sec. II): HIP kernels behind the C ABI of include/seg.h and
+include/seg_mc.h, with a thin Python binding. PyTorch supplies device memory and streams only."""
 from . import abi
+from .motion import MotionCorrector
 from .session import Session, segment_video, to_device_frames
 
-__all__ = ["abi", "Session", "segment_video", "to_device_frames"]
+__all__ = ["abi", "MotionCorrector", "Session", "segment_video", "to_device_frames"]

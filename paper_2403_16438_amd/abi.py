@@ -46,6 +46,13 @@ class seg_config(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class seg_mc_config(C.Structure):
+    _fields_ = [("height", C.c_uint32), ("width", C.c_uint32), ("radius", C.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class seg_profile(C.Structure):
     _fields_ = [("maps_ms", C.c_float), ("nmf_ms", C.c_float), ("nmf_flops", C.c_double),
                 ("nmf_path", C.c_uint32), ("nmf_workgroups", C.c_uint32),
@@ -107,6 +114,15 @@ def _load():
         "seg_nn_destroy": (C.c_int, [P]),
         "seg_nn_shape": (C.c_int, [P, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]),
         "seg_set_model": (C.c_int, [P, P]),
+        "seg_mc_default_config": (C.c_int, [u32, u32, C.POINTER(seg_mc_config)]),
+        "seg_mc_workspace_bytes": (C.c_int, [C.POINTER(seg_mc_config), C.POINTER(C.c_size_t)]),
+        "seg_mc_create": (C.c_int, [C.POINTER(seg_mc_config), P, C.c_size_t, C.POINTER(P)]),
+        "seg_mc_layout": (C.c_int, [P, C.POINTER(u32), C.POINTER(u32)]),
+        "seg_mc_set_template": (C.c_int, [P, P, u32, P]),
+        "seg_mc_get_template": (C.c_int, [P, P]),
+        "seg_mc_estimate": (C.c_int, [P, P, C.c_uint64, P, P, P]),
+        "seg_mc_apply": (C.c_int, [P, P, C.c_uint64, P, P, P]),
+        "seg_mc_destroy": (C.c_int, [P]),
         "seg_strerror": (C.c_char_p, [C.c_int]),
         "seg_last_error": (C.c_int, [P]),
     }
@@ -121,8 +137,9 @@ lib = _load()
 
 
 def header_functions() -> list:
-    """Names of the functions declared in include/seg.h and include/seg_nn.h."""
-    text = open(HEADER).read() + open(os.path.join(os.path.dirname(HEADER), "seg_nn.h")).read()
+    """Names of the functions declared in include/seg.h, seg_nn.h and seg_mc.h."""
+    inc = os.path.dirname(HEADER)
+    text = "".join(open(os.path.join(inc, f)).read() for f in ("seg.h", "seg_nn.h", "seg_mc.h"))
     return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(seg_\w+)\s*\(", text, re.M)))
 
 
@@ -245,3 +262,48 @@ def seg_export_state(h, stream: int):
 def seg_import_state(h, buf, stream: int) -> None:
     check(lib.seg_import_state(h, buf.ctypes.data_as(C.c_void_p), buf.nbytes, C.c_void_p(stream)),
           "seg_import_state")
+
+
+# ---- motion correction (include/seg_mc.h) ----
+
+def seg_mc_default_config(height: int, width: int) -> seg_mc_config:
+    c = seg_mc_config()
+    check(lib.seg_mc_default_config(height, width, C.byref(c)), "seg_mc_default_config")
+    return c
+
+
+def seg_mc_workspace_bytes(cfg: seg_mc_config) -> int:
+    n = C.c_size_t()
+    check(lib.seg_mc_workspace_bytes(C.byref(cfg), C.byref(n)), "seg_mc_workspace_bytes")
+    return n.value
+
+
+def seg_mc_create(cfg: seg_mc_config, dev_workspace: int, nbytes: int):
+    h = C.c_void_p()
+    check(lib.seg_mc_create(C.byref(cfg), C.c_void_p(dev_workspace), nbytes, C.byref(h)), "seg_mc_create")
+    return h
+
+
+def seg_mc_layout(h) -> tuple:
+    p, v = C.c_uint32(), C.c_uint32()
+    check(lib.seg_mc_layout(h, C.byref(p), C.byref(v)), "seg_mc_layout")
+    return p.value, v.value
+
+
+def seg_mc_set_template(h, dev_frames: int, n: int, stream: int) -> None:
+    check(lib.seg_mc_set_template(h, C.c_void_p(dev_frames), n, C.c_void_p(stream)), "seg_mc_set_template")
+
+
+def seg_mc_get_template(h, out) -> None:
+    check(lib.seg_mc_get_template(h, out.ctypes.data_as(C.c_void_p)), "seg_mc_get_template")
+
+
+def seg_mc_estimate(h, dev_frames: int, n: int, dev_motion: int, dev_scores: int | None, stream: int) -> None:
+    check(lib.seg_mc_estimate(h, C.c_void_p(dev_frames), n, C.c_void_p(dev_motion),
+                              C.c_void_p(dev_scores) if dev_scores else None, C.c_void_p(stream)),
+          "seg_mc_estimate")
+
+
+def seg_mc_apply(h, dev_frames: int, n: int, dev_motion: int, dev_out: int, stream: int) -> None:
+    check(lib.seg_mc_apply(h, C.c_void_p(dev_frames), n, C.c_void_p(dev_motion), C.c_void_p(dev_out),
+                           C.c_void_p(stream)), "seg_mc_apply")

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libseg.so")
-SOURCES = ["seg_api.cpp", "k_stream.hip", "k_finalize.hip", "k_nmf.hip", "k_nmf_split.hip", "k_traces.hip", "nn_api.cpp", "k_nn.hip"]
+SOURCES = ["seg_api.cpp", "k_stream.hip", "k_finalize.hip", "k_nmf.hip", "k_nmf_split.hip", "k_traces.hip", "k_motion.hip", "mc_api.cpp", "nn_api.cpp", "k_nn.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

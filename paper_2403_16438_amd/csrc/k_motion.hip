@@ -1,0 +1,325 @@
+// Rigid motion correction by patch-wise ZNCC (Sec. II).
+//
+// A frame F is compared with an integer template T: for every 21 x 21 tile
+// p of F and every integer vector d with |dy|, |dx| <= R, the zero-mean
+// normalised cross-correlation of F's tile with T's window at p + d. The
+// per-vector sum over tiles picks the motion of the frame.
+//
+// With n = 441 pixels, ZNCC = (n C - sF sT) / sqrt(vF vT), where
+//   C  = sum F T over the tile (the cross term),
+//   sF = sum F, vF = n sum F^2 - sF^2 (per frame and tile),
+//   sT = sum T, vT = n sum T^2 - sT^2 (per tile and vector, from integral
+//        images of T and T^2: the table-based area sums).
+// All of these are integers below 2^53, so FP64 holds them exactly; C is a
+// contraction of the template windows (rows d) with the frame tiles
+// (columns: frames) and runs on FP64 MFMA, whose products and partial sums
+// of integers below 2^53 are exact in any order. Only the final division
+// and square root round.
+#include "seg_motion.h"
+
+namespace seg {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kMaxTW = kPatch + 2 * kMcMaxRadius;
+
+// ---- template -------------------------------------------------------------
+
+__global__ void k_mc_template(const uint16_t* __restrict__ f, int n, long long M, uint16_t* __restrict__ t) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= M) return;
+  uint32_t s = 0;
+  for (int i = 0; i < n; ++i) s += f[(size_t)i * M + x];
+  t[x] = (uint16_t)((s + (uint32_t)n / 2) / (uint32_t)n);
+}
+
+// ---- integral images and window tables --------------------------------------
+
+// ii1, ii2: [H+1][W+1], row 0 and column 0 zero. Pass 1: running sums along
+// each row (one thread per row); pass 2: down each column.
+__global__ void k_mc_rows(const uint16_t* __restrict__ t, int H, int W, unsigned long long* ii1,
+                          unsigned long long* ii2) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y > H) return;
+  const size_t row = (size_t)y * (W + 1);
+  unsigned long long a = 0, b = 0;
+  ii1[row] = 0;
+  ii2[row] = 0;
+  for (int x = 0; x < W; ++x) {
+    if (y > 0) {
+      const unsigned long long v = t[(size_t)(y - 1) * W + x];
+      a += v;
+      b += v * v;
+    }
+    ii1[row + x + 1] = a;
+    ii2[row + x + 1] = b;
+  }
+}
+
+__global__ void k_mc_cols(int H, int W, unsigned long long* ii1, unsigned long long* ii2) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x > W) return;
+  unsigned long long a = 0, b = 0;
+  for (int y = 0; y <= H; ++y) {
+    const size_t i = (size_t)y * (W + 1) + x;
+    a += ii1[i];
+    b += ii2[i];
+    ii1[i] = a;
+    ii2[i] = b;
+  }
+}
+
+__global__ void k_mc_windows(McGeom g, const unsigned long long* __restrict__ ii1,
+                             const unsigned long long* __restrict__ ii2, double* sT, double* vT) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.P * g.Vp) return;
+  const int p = i / g.Vp, v = i % g.Vp;
+  if (v >= g.V) {
+    sT[i] = 0.0;
+    vT[i] = 0.0;
+    return;
+  }
+  const int side = 2 * g.R + 1;
+  const int y0 = g.oy + (p / g.nx) * kPatch + v / side - g.R;
+  const int x0 = g.ox + (p % g.nx) * kPatch + v % side - g.R;
+  const size_t w1 = (size_t)g.W + 1;
+  auto box = [&](const unsigned long long* ii) {
+    return ii[(size_t)(y0 + kPatch) * w1 + x0 + kPatch] - ii[(size_t)y0 * w1 + x0 + kPatch] -
+           ii[(size_t)(y0 + kPatch) * w1 + x0] + ii[(size_t)y0 * w1 + x0];
+  };
+  const long long s1 = (long long)box(ii1), s2 = (long long)box(ii2);
+  sT[i] = (double)s1;
+  vT[i] = (double)(kPatchPix * s2 - s1 * s1);
+}
+
+// ---- scores -------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One workgroup: kMcFrames frames x one slice of tiles. Wave w owns the
+// 16-vector tiles w, w + 4, ... (TPW of them). FP64 MFMA 16x16x4: lane l
+// supplies A(l % 16, l / 16) and B(l / 16, l % 16) and holds
+// D(4 j + l / 16, l % 16) in element j; here A rows are vectors, the depth is
+// the tile's pixels, and B columns are frames.
+template <int TPW>
+__global__ __launch_bounds__(kThreads) void k_mc_scores(McScoreArgs a) {
+  const McGeom g = a.g;
+  __shared__ uint16_t s_t[(kMaxTW + 1) * kMaxTW];     // template window, one extra zero row
+  __shared__ uint16_t s_f[kMcFrames * kPatchK];       // frame tiles, zero padded
+  __shared__ double s_sf[kMcFrames], s_vf[kMcFrames];
+  const int slice = blockIdx.x % g.S, grp = blockIdx.x / g.S;
+  const int f0 = grp * kMcFrames;
+  const int nf = min(kMcFrames, a.n - f0);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int col = lane & 15, q = lane >> 4;
+  const int MT = g.Vp / 16, side = 2 * g.R + 1, TW = g.TW;
+  const long long M = (long long)g.H * g.W;
+
+  int dbase[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int d = (wave + 4 * i) * 16 + col;
+    dbase[i] = (wave + 4 * i < MT && d < g.V) ? (d / side) * TW + d % side : 0;
+  }
+  double score[TPW][4];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) score[i][j] = 0.0;
+
+  const int p0 = slice * g.pps, p1 = min(g.P, p0 + g.pps);
+  for (int p = p0; p < p1; ++p) {
+    const int py = g.oy + (p / g.nx) * kPatch, px = g.ox + (p % g.nx) * kPatch;
+    __syncthreads();
+    for (int i = tid; i < (TW + 1) * TW; i += kThreads) {
+      const int r = i / TW, c = i % TW;
+      s_t[i] = r < TW ? a.tmpl[(size_t)(py - g.R + r) * g.W + px - g.R + c] : (uint16_t)0;
+    }
+    for (int i = tid; i < kMcFrames * kPatchK; i += kThreads) {
+      const int f = i / kPatchK, k = i % kPatchK;
+      uint16_t v = 0;
+      if (f < nf && k < kPatchPix)
+        v = a.frames[(size_t)(f0 + f) * M + (size_t)(py + k / kPatch) * g.W + px + k % kPatch];
+      s_f[i] = v;
+    }
+    __syncthreads();
+    // exact per-frame moments of the tile
+#pragma unroll
+    for (int j = 0; j < kMcFrames / 4; ++j) {
+      const int f = wave * (kMcFrames / 4) + j;
+      unsigned long long s = 0, s2 = 0;
+      for (int k = lane; k < kPatchPix; k += 64) {
+        const unsigned long long v = s_f[f * kPatchK + k];
+        s += v;
+        s2 += v * v;
+      }
+      s = wave_sum_u64(s);
+      s2 = wave_sum_u64(s2);
+      if (lane == 0) {
+        s_sf[f] = (double)s;
+        s_vf[f] = (double)((long long)(kPatchPix * s2) - (long long)(s * s));
+      }
+    }
+    __syncthreads();
+
+    d4 acc[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+    int x = q, off = q;                       // pixel k = 4 kk + q at (k / 21, k % 21)
+    const uint16_t* fb = s_f + col * kPatchK + q;
+    for (int kk = 0; kk < kPatchK / 4; ++kk) {
+      const double b = (double)fb[4 * kk];
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        if (wave + 4 * i < MT) {
+          const double av = (double)s_t[dbase[i] + off];
+          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[i], 0, 0, 0);
+        }
+      }
+      x += 4;
+      off += 4;
+      if (x >= kPatch) {
+        x -= kPatch;
+        off += TW - kPatch;
+      }
+    }
+    const double vf = s_vf[col], sf = s_sf[col];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int t = wave + 4 * i;
+      if (t >= MT) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int d = t * 16 + 4 * j + q;
+        const double st = a.sT[(size_t)p * g.Vp + d], vt = a.vT[(size_t)p * g.Vp + d];
+        double z = 0.0;
+        if (vf > 0.0 && vt > 0.0) z = ((double)kPatchPix * acc[i][j] - sf * st) / sqrt(vf * vt);
+        score[i][j] += z;
+      }
+    }
+  }
+  if (col < nf) {
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int t = wave + 4 * i;
+      if (t >= MT) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int d = t * 16 + 4 * j + q;
+        a.part[((size_t)slice * kMcChunk + f0 + col) * g.Vp + d] = score[i][j];
+      }
+    }
+  }
+}
+
+// ---- pick and apply -----------------------------------------------------------
+
+// One wave per frame: lanes take vectors d = lane, lane + 64, ...; the slice
+// sums are added in slice order; the first maximum wins.
+__global__ __launch_bounds__(kThreads) void k_mc_pick(McGeom g, const double* __restrict__ part, int n,
+                                                      int32_t* motion, double* scores) {
+  const int f = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (f >= n) return;
+  double best = -1.0e300;
+  int arg = 0x7fffffff;
+  for (int d = lane; d < g.V; d += 64) {
+    double s = 0.0;
+    for (int sl = 0; sl < g.S; ++sl) s += part[((size_t)sl * kMcChunk + f) * g.Vp + d];
+    if (scores) scores[(size_t)f * g.V + d] = s;
+    if (s > best) {
+      best = s;
+      arg = d;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int oa = __shfl_xor(arg, o, 64);
+    if (ob > best || (ob == best && oa < arg)) {
+      best = ob;
+      arg = oa;
+    }
+  }
+  if (lane == 0) {
+    const int side = 2 * g.R + 1;
+    motion[2 * (size_t)f] = -(arg / side - g.R);
+    motion[2 * (size_t)f + 1] = -(arg % side - g.R);
+  }
+}
+
+// C(y, x) = F(clamp(y + my), clamp(x + mx)); one thread per output pixel.
+__global__ void k_mc_apply(const uint16_t* __restrict__ in, long long n, int H, int W,
+                           const int32_t* __restrict__ motion, uint16_t* __restrict__ out) {
+  const long long M = (long long)H * W;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * M) return;
+  const long long f = i / M;
+  const int r = (int)(i - f * M), y = r / W, x = r % W;
+  const int sy = min(max(y + motion[2 * f], 0), H - 1);
+  const int sx = min(max(x + motion[2 * f + 1], 0), W - 1);
+  out[i] = in[(size_t)f * M + (size_t)sy * W + sx];
+}
+
+}  // namespace
+
+hipError_t launch_mc_template(const uint16_t* frames, int n, long long M, uint16_t* tmpl, hipStream_t st) {
+  hipLaunchKernelGGL(k_mc_template, dim3((unsigned)((M + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                     frames, n, M, tmpl);
+  return hipGetLastError();
+}
+
+hipError_t launch_mc_tables(const McGeom& g, const uint16_t* tmpl, unsigned long long* ii, double* sT,
+                            double* vT, hipStream_t st) {
+  unsigned long long* ii2 = ii + (size_t)(g.H + 1) * (g.W + 1);
+  hipLaunchKernelGGL(k_mc_rows, dim3((g.H + 1 + 63) / 64), dim3(64), 0, st, tmpl, g.H, g.W, ii, ii2);
+  hipLaunchKernelGGL(k_mc_cols, dim3((g.W + 1 + 63) / 64), dim3(64), 0, st, g.H, g.W, ii, ii2);
+  const int n = g.P * g.Vp;
+  hipLaunchKernelGGL(k_mc_windows, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, st, g, ii, ii2, sT,
+                     vT);
+  return hipGetLastError();
+}
+
+hipError_t launch_mc_scores(const McScoreArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  const int groups = (a.n + kMcFrames - 1) / kMcFrames;
+  const dim3 grid((unsigned)(groups * a.g.S)), block(kThreads);
+  const int tpw = (a.g.Vp / 16 + 3) / 4;
+  switch (tpw) {
+    case 1: hipLaunchKernelGGL(k_mc_scores<1>, grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_mc_scores<2>, grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_mc_scores<3>, grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_mc_scores<4>, grid, block, 0, st, a); break;
+    case 5: hipLaunchKernelGGL(k_mc_scores<5>, grid, block, 0, st, a); break;
+    case 6: hipLaunchKernelGGL(k_mc_scores<6>, grid, block, 0, st, a); break;
+    case 7: hipLaunchKernelGGL(k_mc_scores<7>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mc_pick(const McGeom& g, const double* part, int n, int32_t* motion, double* scores,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int per = kThreads / 64;
+  hipLaunchKernelGGL(k_mc_pick, dim3((unsigned)((n + per - 1) / per)), dim3(kThreads), 0, st, g, part, n, motion,
+                     scores);
+  return hipGetLastError();
+}
+
+hipError_t launch_mc_apply(const uint16_t* in, long long n, int H, int W, const int32_t* motion, uint16_t* out,
+                           hipStream_t st) {
+  const long long total = n * H * W;
+  if (total <= 0) return hipSuccess;
+  const long long blocks = (total + kThreads - 1) / kThreads;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mc_apply, dim3((unsigned)blocks), dim3(kThreads), 0, st, in, n, H, W, motion, out);
+  return hipGetLastError();
+}
+
+}  // namespace seg

@@ -1,0 +1,55 @@
+// Kernel interface of the motion correction (k_motion.hip), shared with the
+// host library (mc_api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace seg {
+
+constexpr int kPatch = 21;                 // tile side (Sec. II)
+constexpr int kPatchPix = kPatch * kPatch; // 441
+constexpr int kPatchK = 444;               // 441 padded to the MFMA depth 4
+constexpr int kMcFrames = 16;              // frames per workgroup (the MFMA's N)
+constexpr int kMcMaxRadius = 10;           // |dy|, |dx| <= R
+constexpr int kMcChunk = 2048;             // frames per scoring launch
+constexpr int kMcSlices = 8;               // patch slices per frame group
+
+// Geometry of one motion corrector: tile grid and candidate vectors.
+struct McGeom {
+  int H, W, R;
+  int TW;          // template window side 21 + 2R
+  int ny, nx;      // tiles per column / row
+  int oy, ox;      // origin of the first tile
+  int P;           // tiles, ny * nx
+  int V;           // vectors (2R + 1)^2, ordered by dy then dx
+  int Vp;          // V rounded up to 16 (the MFMA's M)
+  int S;           // patch slices
+  int pps;         // patches per slice
+};
+
+struct McScoreArgs {
+  McGeom g;
+  const uint16_t* frames;   // [n][H][W]
+  int n;                    // frames of this launch, <= kMcChunk
+  const uint16_t* tmpl;     // [H][W]
+  const double* sT;         // [P][Vp] template window sums
+  const double* vT;         // [P][Vp] 441 sum T^2 - (sum T)^2
+  double* part;             // [S][kMcChunk][Vp] per-slice ZNCC sums
+};
+
+// template = per-pixel sum of n frames, rounded half up after division by n
+hipError_t launch_mc_template(const uint16_t* frames, int n, long long M, uint16_t* tmpl, hipStream_t st);
+// integral images of T and T^2 ([H+1][W+1] each, uint64) and the window tables
+hipError_t launch_mc_tables(const McGeom& g, const uint16_t* tmpl, unsigned long long* ii,
+                            double* sT, double* vT, hipStream_t st);
+hipError_t launch_mc_scores(const McScoreArgs& a, hipStream_t st);
+// per frame: slice sums in order, argmax (first maximum), motion = -d;
+// scores (may be null) [n][V]
+hipError_t launch_mc_pick(const McGeom& g, const double* part, int n, int32_t* motion, double* scores,
+                          hipStream_t st);
+hipError_t launch_mc_apply(const uint16_t* in, long long n, int H, int W, const int32_t* motion, uint16_t* out,
+                           hipStream_t st);
+
+}  // namespace seg
