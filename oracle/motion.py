@@ -23,7 +23,9 @@ Readings where the paper is silent:
     vector with the largest sum wins, ties going to the first in order;
   * the reported motion is m = -d, the displacement of the frame's content
     relative to the template; the corrected frame is
-    C(y, x) = F(y + my, x + mx), with coordinates clamped to the frame.
+    C(y, x) = F(y + my, x + mx) where that pixel lies in the frame, and the
+    template's T(y, x) where it does not (no measurement exists there, and a
+    repeated edge would vary with the motion like activity).
 """
 from __future__ import annotations
 
@@ -105,14 +107,16 @@ def estimate(frames: np.ndarray, tmpl: np.ndarray, R: int):
     return shifts, sc
 
 
-def apply_shifts(frames: np.ndarray, shifts: np.ndarray) -> np.ndarray:
-    """C_t(y, x) = F_t(clamp(y + my), clamp(x + mx))."""
+def apply_shifts(frames: np.ndarray, shifts: np.ndarray, tmpl: np.ndarray) -> np.ndarray:
+    """C_t(y, x) = F_t(y + my, x + mx) inside the frame, else T(y, x)."""
     n, H, W = frames.shape
     out = np.empty_like(frames)
+    y, x = np.mgrid[0:H, 0:W]
     for t in range(n):
-        iy = np.clip(np.arange(H) + int(shifts[t, 0]), 0, H - 1)
-        ix = np.clip(np.arange(W) + int(shifts[t, 1]), 0, W - 1)
-        out[t] = frames[t][iy][:, ix]
+        sy, sx = y + int(shifts[t, 0]), x + int(shifts[t, 1])
+        inside = (sy >= 0) & (sy < H) & (sx >= 0) & (sx < W)
+        src = frames[t][np.clip(sy, 0, H - 1), np.clip(sx, 0, W - 1)]
+        out[t] = np.where(inside, src, tmpl)
     return out
 
 
@@ -121,4 +125,4 @@ def correct(frames: np.ndarray, R: int = 8, tmpl: np.ndarray | None = None):
     if tmpl is None:
         tmpl = make_template(frames[:TEMPLATE_FRAMES])
     shifts, sc = estimate(frames, tmpl, R)
-    return apply_shifts(frames, shifts), shifts, tmpl
+    return apply_shifts(frames, shifts, tmpl), shifts, tmpl

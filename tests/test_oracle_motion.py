@@ -92,21 +92,31 @@ def test_planted_shift_recovered_exactly_on_a_texture():
     # the best vector reaches the patch count (every patch correlates to 1)
     P = len(om.patch_grid(80, 96, R))
     assert np.allclose(sc.max(axis=1), P, rtol=0, atol=1e-9)
-    corr = om.apply_shifts(frames, got)
+    corr = om.apply_shifts(frames, got, tmpl)
     assert np.array_equal(corr[:, R:-R, R:-R], np.repeat(tmpl[None], len(shifts), 0)[:, R:-R, R:-R])
 
 
 def test_apply_shifts_closed_forms():
     rng = np.random.default_rng(5)
     f = rng.integers(0, 65536, size=(3, 9, 11), dtype=np.uint16)
-    assert np.array_equal(om.apply_shifts(f, np.zeros((3, 2), np.int32)), f)
+    tm = rng.integers(0, 65536, size=(9, 11), dtype=np.uint16)
+    assert np.array_equal(om.apply_shifts(f, np.zeros((3, 2), np.int32), tm), f)
     s = np.array([[1, 0], [0, -2], [3, 3]], np.int32)
-    out = om.apply_shifts(f, s)
-    assert np.array_equal(out[0, :-1], f[0, 1:]) and np.array_equal(out[0, -1], f[0, -1])
-    assert np.array_equal(out[1, :, 2:], f[1, :, :-2]) and np.array_equal(out[1, :, 0], f[1, :, 0])
-    assert out[2, 0, 0] == f[2, 3, 3] and out[2, -1, -1] == f[2, -1, -1]
+    out = om.apply_shifts(f, s, tm)
+    assert np.array_equal(out[0, :-1], f[0, 1:]) and np.array_equal(out[0, -1], tm[-1])
+    assert np.array_equal(out[1, :, 2:], f[1, :, :-2]) and np.array_equal(out[1, :, :2], tm[:, :2])
+    assert out[2, 0, 0] == f[2, 3, 3] and out[2, -1, -1] == tm[-1, -1]
+    assert np.array_equal(out[2, :6, :8], f[2, 3:, 3:])
+    assert np.array_equal(out[2, 6:], tm[6:]) and np.array_equal(out[2, :, 8:], tm[:, 8:])
+    # brute force
+    for t in range(3):
+        for y in range(9):
+            for x in range(11):
+                sy, sx = y + s[t, 0], x + s[t, 1]
+                want = f[t, sy, sx] if 0 <= sy < 9 and 0 <= sx < 11 else tm[y, x]
+                assert out[t, y, x] == want
     # undoes planted motion away from the borders
-    back = om.apply_shifts(move_frames(f, s), s)
+    back = om.apply_shifts(move_frames(f, s), s, tm)
     assert np.array_equal(back[:, 3:-3, 3:-3], f[:, 3:-3, 3:-3])
 
 
