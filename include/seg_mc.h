@@ -19,7 +19,8 @@
  *     score wins, ties going to the lowest index;
  *   - the motion of the frame is m = -d (the displacement of its content
  *     relative to the template), and the corrected frame is
- *     C(y, x) = F(y + my, x + mx) with coordinates clamped to the frame.
+ *     C(y, x) = F(y + my, x + mx) where that pixel lies in the frame and the
+ *     template's T(y, x) where it does not.
  *
  * Conventions are those of seg.h: int status (SEG_OK or SEG_E_*), frames
  * uint16 [n][height][width], "dev" pointers are HIP device memory, the
@@ -84,9 +85,10 @@ int seg_mc_get_template(seg_mc* mc, uint16_t* host_out);
 int seg_mc_estimate(seg_mc* mc, const uint16_t* dev_frames, uint64_t n_frames,
                     int32_t* dev_motion, double* dev_scores, void* stream);
 
-/* Corrected frames: dev_out[t](y, x) = dev_frames[t](clamp(y + my), clamp(x + mx))
- * with (my, mx) = dev_motion[t]. dev_out must not overlap dev_frames.
- * Errors: SEG_E_INVAL, SEG_E_DEVICE. */
+/* Corrected frames: dev_out[t](y, x) = dev_frames[t](y + my, x + mx) with
+ * (my, mx) = dev_motion[t] where that pixel lies in the frame, else the
+ * template's value at (y, x). dev_out must not overlap dev_frames.
+ * Errors: SEG_E_INVAL, SEG_E_STATE (no template), SEG_E_DEVICE. */
 int seg_mc_apply(seg_mc* mc, const uint16_t* dev_frames, uint64_t n_frames,
                  const int32_t* dev_motion, uint16_t* dev_out, void* stream);
 

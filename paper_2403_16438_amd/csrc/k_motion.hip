@@ -253,17 +253,51 @@ __global__ __launch_bounds__(kThreads) void k_mc_pick(McGeom g, const double* __
   }
 }
 
-// C(y, x) = F(clamp(y + my), clamp(x + mx)); one thread per output pixel.
-__global__ void k_mc_apply(const uint16_t* __restrict__ in, long long n, int H, int W,
-                           const int32_t* __restrict__ motion, uint16_t* __restrict__ out) {
-  const long long M = (long long)H * W;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * M) return;
-  const long long f = i / M;
-  const int r = (int)(i - f * M), y = r / W, x = r % W;
-  const int sy = min(max(y + motion[2 * f], 0), H - 1);
-  const int sx = min(max(x + motion[2 * f + 1], 0), W - 1);
-  out[i] = in[(size_t)f * M + (size_t)sy * W + sx];
+// C(y, x) = F(y + my, x + mx) where that pixel is in the frame, else the
+// template's T(y, x). Grid: x runs over the 8-pixel runs of a frame, y over
+// frames (uniform motion per workgroup); each thread gathers one run and
+// writes it with one 16-byte store. Frame widths that are not a multiple of
+// 8 take the per-pixel kernel.
+__global__ void k_mc_apply8(const uint16_t* __restrict__ in, int H, int W, const int32_t* __restrict__ motion,
+                            const uint16_t* __restrict__ tmpl, uint16_t* __restrict__ out) {
+  const int runs = W >> 3;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= H * runs) return;
+  const size_t f = blockIdx.y;
+  const int y = i / runs, x0 = (i - y * runs) << 3;
+  const int my = motion[2 * f], mx = motion[2 * f + 1];
+  const size_t M = (size_t)H * W;
+  const int sy = y + my;
+  const uint16_t* trow = tmpl + (size_t)y * W + x0;
+  uint16_t v[8];
+  if (sy < 0 || sy >= H) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = trow[k];
+  } else {
+    const uint16_t* srow = in + f * M + (size_t)sy * W;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int sx = x0 + k + mx;
+      v[k] = (sx >= 0 && sx < W) ? srow[sx] : trow[k];
+    }
+  }
+  uint4 pk;
+  pk.x = v[0] | ((uint32_t)v[1] << 16);
+  pk.y = v[2] | ((uint32_t)v[3] << 16);
+  pk.z = v[4] | ((uint32_t)v[5] << 16);
+  pk.w = v[6] | ((uint32_t)v[7] << 16);
+  *reinterpret_cast<uint4*>(out + f * M + (size_t)y * W + x0) = pk;
+}
+
+__global__ void k_mc_apply1(const uint16_t* __restrict__ in, int H, int W, const int32_t* __restrict__ motion,
+                            const uint16_t* __restrict__ tmpl, uint16_t* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= H * W) return;
+  const size_t f = blockIdx.y, M = (size_t)H * W;
+  const int y = r / W, x = r % W;
+  const int sy = y + motion[2 * f], sx = x + motion[2 * f + 1];
+  const bool inside = sy >= 0 && sy < H && sx >= 0 && sx < W;
+  out[f * M + r] = inside ? in[f * M + (size_t)sy * W + sx] : tmpl[r];
 }
 
 }  // namespace
@@ -312,14 +346,24 @@ hipError_t launch_mc_pick(const McGeom& g, const double* part, int n, int32_t* m
   return hipGetLastError();
 }
 
-hipError_t launch_mc_apply(const uint16_t* in, long long n, int H, int W, const int32_t* motion, uint16_t* out,
-                           hipStream_t st) {
-  const long long total = n * H * W;
-  if (total <= 0) return hipSuccess;
-  const long long blocks = (total + kThreads - 1) / kThreads;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_mc_apply, dim3((unsigned)blocks), dim3(kThreads), 0, st, in, n, H, W, motion, out);
-  return hipGetLastError();
+hipError_t launch_mc_apply(const uint16_t* in, long long n, int H, int W, const int32_t* motion,
+                           const uint16_t* tmpl, uint16_t* out, hipStream_t st) {
+  const bool vec = W % 8 == 0 && ((uintptr_t)out & 15) == 0;
+  const long long per = vec ? (long long)H * (W / 8) : (long long)H * W;
+  const unsigned bx = (unsigned)((per + kThreads - 1) / kThreads);
+  for (long long f0 = 0; f0 < n; f0 += 65535) {
+    const unsigned nf = (unsigned)(n - f0 < 65535 ? n - f0 : 65535);
+    const size_t o = (size_t)f0 * H * W;
+    if (vec)
+      hipLaunchKernelGGL(k_mc_apply8, dim3(bx, nf), dim3(kThreads), 0, st, in + o, H, W, motion + 2 * f0, tmpl,
+                         out + o);
+    else
+      hipLaunchKernelGGL(k_mc_apply1, dim3(bx, nf), dim3(kThreads), 0, st, in + o, H, W, motion + 2 * f0, tmpl,
+                         out + o);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace seg

@@ -191,13 +191,14 @@ int seg_mc_apply(seg_mc* mc, const uint16_t* dev_frames, uint64_t n_frames, cons
                  uint16_t* dev_out, void* stream) {
   int e = enter(mc);
   if (e) return e;
+  if (!mc->have_template) return SEG_E_STATE;
   if (n_frames == 0) return SEG_OK;
   if (!dev_frames || !dev_motion || !dev_out) return SEG_E_INVAL;
   const size_t bytes = n_frames * (size_t)mc->g.H * mc->g.W * 2;
   const char *a = reinterpret_cast<const char*>(dev_frames), *b = reinterpret_cast<const char*>(dev_out);
   if (a < b + bytes && b < a + bytes) return SEG_E_INVAL;
-  return fail(mc, seg::launch_mc_apply(dev_frames, (long long)n_frames, mc->g.H, mc->g.W, dev_motion, dev_out,
-                                       static_cast<hipStream_t>(stream)));
+  return fail(mc, seg::launch_mc_apply(dev_frames, (long long)n_frames, mc->g.H, mc->g.W, dev_motion,
+                                       at<uint16_t>(mc, mc->at_tmpl), dev_out, static_cast<hipStream_t>(stream)));
 }
 
 int seg_mc_destroy(seg_mc* mc) {

@@ -49,7 +49,8 @@ hipError_t launch_mc_scores(const McScoreArgs& a, hipStream_t st);
 // scores (may be null) [n][V]
 hipError_t launch_mc_pick(const McGeom& g, const double* part, int n, int32_t* motion, double* scores,
                           hipStream_t st);
-hipError_t launch_mc_apply(const uint16_t* in, long long n, int H, int W, const int32_t* motion, uint16_t* out,
-                           hipStream_t st);
+// out(y, x) = in(y + my, x + mx) inside the frame, else tmpl(y, x)
+hipError_t launch_mc_apply(const uint16_t* in, long long n, int H, int W, const int32_t* motion,
+                           const uint16_t* tmpl, uint16_t* out, hipStream_t st);
 
 }  // namespace seg

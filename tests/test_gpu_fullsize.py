@@ -70,6 +70,30 @@ def test_benchmark_video_footprints(bench_video):
     assert oracle.match_f1(fp["masks"], truth.masks())["f1"] >= 0.9
 
 
+def test_benchmark_video_after_motion_correction(bench_video):
+    """The paper's order of stages: the video with planted drift (up to
+    6 px), corrected on the GPU, then segmented; the footprints match those
+    of the still video."""
+    from paper_2403_16438_amd import MotionCorrector
+    from synth import plant_motion
+    video, truth, sess, prm, ref = bench_video
+    moved, planted = plant_motion(video, 6, 2001)
+    d = to_device_frames(moved, torch.device("cuda:0"))
+    mc = MotionCorrector(256, 256, torch.device("cuda:0"), radius=8)
+    mc.set_template(d[:50])
+    corrected, motion = mc.correct(d)
+    del d
+    s2 = Session(256, 256, 10000)
+    s2.push(corrected)
+    s2.finalize()
+    torch.cuda.synchronize()
+    assert np.array_equal(motion.cpu().numpy(), planted)
+    a, b = s2.footprints()["masks"], sess.footprints()["masks"]
+    m = oracle.match_f1(a, b)
+    print("footprints after correction", a.shape[0], "still", b.shape[0], m)
+    assert m["f1"] >= 0.95
+
+
 def test_benchmark_video_traces(bench_video):
     """Traces of every footprint over all 10,000 frames, bit-exact (exact
     integer sums, one FP64 division on both sides)."""

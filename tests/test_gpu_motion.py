@@ -6,7 +6,7 @@ integer moments, the oracle from centred values, so they differ by rounding
 only); motion equal to the oracle's wherever the oracle's best score leads
 the runner-up by more than 1e-9, and otherwise a vector whose oracle score is
 within 1e-9 of the best; corrected frames bit-exact against the oracle's
-shift of the same frames.
+shift of the same frames (template values where the shift leaves the frame).
 """
 import numpy as np
 import pytest
@@ -65,7 +65,7 @@ def _check_against_oracle(frames, R, motion, sc, corrected, tmpl, frames_idx=Non
             assert pick == order[0], (t, pick, order[0])
         else:
             assert ref[pick] >= best - GAP, t
-        assert np.array_equal(corrected[t], om.apply_shifts(frames[t:t + 1], motion[t:t + 1])[0]), t
+        assert np.array_equal(corrected[t], om.apply_shifts(frames[t:t + 1], motion[t:t + 1], tmpl)[0]), t
 
 
 def test_small_recording_against_oracle():
@@ -170,3 +170,27 @@ def test_errors_and_empty():
     m = mc.estimate(d)
     torch.cuda.synchronize()
     assert m.shape == (3, 2)
+
+
+def test_benchmark_recording_full_size():
+    """256 x 256 x 10,000 with drift up to 6 px, in the launch configuration
+    bench.py times: every planted displacement recovered; the oracle on
+    sampled frames; corrected frames equal the still video inside the
+    R-pixel border."""
+    video, _ = simulate(preset(2), 2000)
+    moved, planted = plant_motion(video, 6, 2001)
+    mc = MotionCorrector(256, 256, DEV, radius=8)
+    d = to_device_frames(moved, DEV)
+    mc.set_template(d[:50])
+    motion, sc = mc.estimate(d, scores=True)
+    out = mc.apply(d, motion)
+    torch.cuda.synchronize()
+    got = motion.cpu().numpy()
+    assert np.array_equal(got, planted)
+    tmpl = om.make_template(moved[:50])
+    sample = [0, 49, 50, 2047, 2048, 5000, 7777, 9999]
+    sc_s = sc[sample].cpu().numpy()
+    out_s = out[sample].cpu().numpy().view(np.uint16)
+    _check_against_oracle(moved[sample], 8, got[sample], sc_s, out_s, tmpl)
+    still = to_device_frames(video, DEV)
+    assert torch.equal(out[:, 8:-8, 8:-8], still[:, 8:-8, 8:-8])
