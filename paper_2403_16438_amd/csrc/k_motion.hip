@@ -5,7 +5,7 @@
 // normalised cross-correlation of F's tile with T's window at p + d. The
 // per-vector sum over tiles picks the motion of the frame.
 //
-// With n = 441 pixels, ZNCC = (n C - sF sT) / sqrt(vF vT), where
+// With n = 441 pixels, ZNCC = (n C - sF sT) / (sqrt(vF) sqrt(vT)), where
 //   C  = sum F T over the tile (the cross term),
 //   sF = sum F, vF = n sum F^2 - sF^2 (per frame and tile),
 //   sT = sum T, vT = n sum T^2 - sT^2 (per tile and vector, from integral
@@ -13,8 +13,9 @@
 // All of these are integers below 2^53, so FP64 holds them exactly; C is a
 // contraction of the template windows (rows d) with the frame tiles
 // (columns: frames) and runs on FP64 MFMA, whose products and partial sums
-// of integers below 2^53 are exact in any order. Only the final division
-// and square root round.
+// of integers below 2^53 are exact in any order. Only the reciprocal square
+// roots (one per frame and tile, one per tile and vector, from tables) and
+// the final products round.
 #include "seg_motion.h"
 
 namespace seg {
@@ -24,6 +25,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 constexpr int kMaxTW = kPatch + 2 * kMcMaxRadius;
+constexpr int kSThreads = 512;               // scoring workgroup: 8 waves
+constexpr int kSWaves = kSThreads / 64;
 
 // ---- template -------------------------------------------------------------
 
@@ -90,8 +93,9 @@ __global__ void k_mc_windows(McGeom g, const unsigned long long* __restrict__ ii
            ii[(size_t)(y0 + kPatch) * w1 + x0] + ii[(size_t)y0 * w1 + x0];
   };
   const long long s1 = (long long)box(ii1), s2 = (long long)box(ii2);
+  const long long var = kPatchPix * s2 - s1 * s1;
   sT[i] = (double)s1;
-  vT[i] = (double)(kPatchPix * s2 - s1 * s1);
+  vT[i] = var > 0 ? 1.0 / sqrt((double)var) : 0.0;   // 0: zero variance, ZNCC 0
 }
 
 // ---- scores -------------------------------------------------------------------
@@ -102,30 +106,58 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
+// The cross terms of one tile for the NT vector tiles a wave owns: per step
+// of depth 4, one frame value and NT template values from LDS (held as FP64,
+// converted once when staged), then NT independent MFMAs. NT is a compile-time count, so the loads of a step are
+// issued together and no lane mask guards the MFMAs.
+template <int NT, int TPW>
+__device__ __forceinline__ void corr_tiles(d4 (&acc)[TPW], const double* s_t, const double* fb,
+                                           const int (&dbase)[TPW], int q, int TW) {
+  int x = q, off = q;                       // pixel k = 4 kk + q at (k / 21, k % 21)
+#pragma unroll 1
+  for (int kk = 0; kk < kPatchK / 4; ++kk) {
+    const double b = fb[4 * kk];
+    double av[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) av[i] = s_t[dbase[i] + off];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], b, acc[i], 0, 0, 0);
+    x += 4;
+    off += 4;
+    if (x >= kPatch) {
+      x -= kPatch;
+      off += TW - kPatch;
+    }
+  }
+}
+
 // One workgroup: kMcFrames frames x one slice of tiles. Wave w owns the
-// 16-vector tiles w, w + 4, ... (TPW of them). FP64 MFMA 16x16x4: lane l
+// 16-vector tiles w, w + 8, ... (TPW of them). FP64 MFMA 16x16x4: lane l
 // supplies A(l % 16, l / 16) and B(l / 16, l % 16) and holds
 // D(4 j + l / 16, l % 16) in element j; here A rows are vectors, the depth is
 // the tile's pixels, and B columns are frames.
 template <int TPW>
-__global__ __launch_bounds__(kThreads) void k_mc_scores(McScoreArgs a) {
+__global__ __launch_bounds__(kSThreads) void k_mc_scores(McScoreArgs a) {
   const McGeom g = a.g;
-  __shared__ uint16_t s_t[(kMaxTW + 1) * kMaxTW];     // template window, one extra zero row
-  __shared__ uint16_t s_f[kMcFrames * kPatchK];       // frame tiles, zero padded
-  __shared__ double s_sf[kMcFrames], s_vf[kMcFrames];
+  __shared__ double s_t[(kMaxTW + 1) * kMaxTW];     // template window, one extra zero row
+  __shared__ double s_f[kMcFrames * kPatchK];       // frame tiles, zero padded
+  __shared__ double s_sf[kMcFrames], s_rf[kMcFrames];
   const int slice = blockIdx.x % g.S, grp = blockIdx.x / g.S;
   const int f0 = grp * kMcFrames;
   const int nf = min(kMcFrames, a.n - f0);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col = lane & 15, q = lane >> 4;
   const int MT = g.Vp / 16, side = 2 * g.R + 1, TW = g.TW;
+  // vector tiles of this wave: wave, wave + 8, ... below MT (wave-uniform)
+  const int nt = min(TPW, max(0, (MT - wave + kSWaves - 1) / kSWaves));
   const long long M = (long long)g.H * g.W;
 
   int dbase[TPW];
 #pragma unroll
   for (int i = 0; i < TPW; ++i) {
-    const int d = (wave + 4 * i) * 16 + col;
-    dbase[i] = (wave + 4 * i < MT && d < g.V) ? (d / side) * TW + d % side : 0;
+    const int d = (wave + kSWaves * i) * 16 + col;
+    dbase[i] = (wave + kSWaves * i < MT && d < g.V) ? (d / side) * TW + d % side : 0;
   }
   double score[TPW][4];
 #pragma unroll
@@ -137,33 +169,34 @@ __global__ __launch_bounds__(kThreads) void k_mc_scores(McScoreArgs a) {
   for (int p = p0; p < p1; ++p) {
     const int py = g.oy + (p / g.nx) * kPatch, px = g.ox + (p % g.nx) * kPatch;
     __syncthreads();
-    for (int i = tid; i < (TW + 1) * TW; i += kThreads) {
+    for (int i = tid; i < (TW + 1) * TW; i += kSThreads) {
       const int r = i / TW, c = i % TW;
-      s_t[i] = r < TW ? a.tmpl[(size_t)(py - g.R + r) * g.W + px - g.R + c] : (uint16_t)0;
+      s_t[i] = r < TW ? (double)a.tmpl[(size_t)(py - g.R + r) * g.W + px - g.R + c] : 0.0;
     }
-    for (int i = tid; i < kMcFrames * kPatchK; i += kThreads) {
+    for (int i = tid; i < kMcFrames * kPatchK; i += kSThreads) {
       const int f = i / kPatchK, k = i % kPatchK;
-      uint16_t v = 0;
+      double v = 0.0;
       if (f < nf && k < kPatchPix)
-        v = a.frames[(size_t)(f0 + f) * M + (size_t)(py + k / kPatch) * g.W + px + k % kPatch];
+        v = (double)a.frames[(size_t)(f0 + f) * M + (size_t)(py + k / kPatch) * g.W + px + k % kPatch];
       s_f[i] = v;
     }
     __syncthreads();
     // exact per-frame moments of the tile
 #pragma unroll
-    for (int j = 0; j < kMcFrames / 4; ++j) {
-      const int f = wave * (kMcFrames / 4) + j;
+    for (int j = 0; j < kMcFrames / kSWaves; ++j) {
+      const int f = wave * (kMcFrames / kSWaves) + j;
       unsigned long long s = 0, s2 = 0;
       for (int k = lane; k < kPatchPix; k += 64) {
-        const unsigned long long v = s_f[f * kPatchK + k];
+        const unsigned long long v = (unsigned long long)s_f[f * kPatchK + k];
         s += v;
         s2 += v * v;
       }
       s = wave_sum_u64(s);
       s2 = wave_sum_u64(s2);
       if (lane == 0) {
+        const long long v = (long long)(kPatchPix * s2) - (long long)(s * s);
         s_sf[f] = (double)s;
-        s_vf[f] = (double)((long long)(kPatchPix * s2) - (long long)(s * s));
+        s_rf[f] = v > 0 ? 1.0 / sqrt((double)v) : 0.0;
       }
     }
     __syncthreads();
@@ -171,44 +204,32 @@ __global__ __launch_bounds__(kThreads) void k_mc_scores(McScoreArgs a) {
     d4 acc[TPW];
 #pragma unroll
     for (int i = 0; i < TPW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
-    int x = q, off = q;                       // pixel k = 4 kk + q at (k / 21, k % 21)
-    const uint16_t* fb = s_f + col * kPatchK + q;
-    for (int kk = 0; kk < kPatchK / 4; ++kk) {
-      const double b = (double)fb[4 * kk];
-#pragma unroll
-      for (int i = 0; i < TPW; ++i) {
-        if (wave + 4 * i < MT) {
-          const double av = (double)s_t[dbase[i] + off];
-          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[i], 0, 0, 0);
-        }
-      }
-      x += 4;
-      off += 4;
-      if (x >= kPatch) {
-        x -= kPatch;
-        off += TW - kPatch;
-      }
+    const double* fb = s_f + col * kPatchK + q;
+    switch (nt) {
+      case 1: corr_tiles<1>(acc, s_t, fb, dbase, q, TW); break;
+      case 2: if constexpr (TPW >= 2) corr_tiles<2>(acc, s_t, fb, dbase, q, TW); break;
+      case 3: if constexpr (TPW >= 3) corr_tiles<3>(acc, s_t, fb, dbase, q, TW); break;
+      case 4: if constexpr (TPW >= 4) corr_tiles<4>(acc, s_t, fb, dbase, q, TW); break;
+      default: break;
     }
-    const double vf = s_vf[col], sf = s_sf[col];
+    const double rf = s_rf[col], sf = s_sf[col];
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
-      const int t = wave + 4 * i;
-      if (t >= MT) continue;
+      if (i >= nt) break;
+      const int t = wave + kSWaves * i;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int d = t * 16 + 4 * j + q;
-        const double st = a.sT[(size_t)p * g.Vp + d], vt = a.vT[(size_t)p * g.Vp + d];
-        double z = 0.0;
-        if (vf > 0.0 && vt > 0.0) z = ((double)kPatchPix * acc[i][j] - sf * st) / sqrt(vf * vt);
-        score[i][j] += z;
+        const double st = a.sT[(size_t)p * g.Vp + d], rt = a.vT[(size_t)p * g.Vp + d];
+        score[i][j] += ((double)kPatchPix * acc[i][j] - sf * st) * rf * rt;
       }
     }
   }
   if (col < nf) {
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
-      const int t = wave + 4 * i;
-      if (t >= MT) continue;
+      if (i >= nt) break;
+      const int t = wave + kSWaves * i;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int d = t * 16 + 4 * j + q;
@@ -322,16 +343,13 @@ hipError_t launch_mc_tables(const McGeom& g, const uint16_t* tmpl, unsigned long
 hipError_t launch_mc_scores(const McScoreArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   const int groups = (a.n + kMcFrames - 1) / kMcFrames;
-  const dim3 grid((unsigned)(groups * a.g.S)), block(kThreads);
-  const int tpw = (a.g.Vp / 16 + 3) / 4;
+  const dim3 grid((unsigned)(groups * a.g.S)), block(kSThreads);
+  const int tpw = (a.g.Vp / 16 + kSWaves - 1) / kSWaves;
   switch (tpw) {
     case 1: hipLaunchKernelGGL(k_mc_scores<1>, grid, block, 0, st, a); break;
     case 2: hipLaunchKernelGGL(k_mc_scores<2>, grid, block, 0, st, a); break;
     case 3: hipLaunchKernelGGL(k_mc_scores<3>, grid, block, 0, st, a); break;
     case 4: hipLaunchKernelGGL(k_mc_scores<4>, grid, block, 0, st, a); break;
-    case 5: hipLaunchKernelGGL(k_mc_scores<5>, grid, block, 0, st, a); break;
-    case 6: hipLaunchKernelGGL(k_mc_scores<6>, grid, block, 0, st, a); break;
-    case 7: hipLaunchKernelGGL(k_mc_scores<7>, grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

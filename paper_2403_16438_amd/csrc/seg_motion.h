@@ -35,13 +35,14 @@ struct McScoreArgs {
   int n;                    // frames of this launch, <= kMcChunk
   const uint16_t* tmpl;     // [H][W]
   const double* sT;         // [P][Vp] template window sums
-  const double* vT;         // [P][Vp] 441 sum T^2 - (sum T)^2
+  const double* vT;         // [P][Vp] 1 / sqrt(441 sum T^2 - (sum T)^2), 0 if that is 0
   double* part;             // [S][kMcChunk][Vp] per-slice ZNCC sums
 };
 
 // template = per-pixel sum of n frames, rounded half up after division by n
 hipError_t launch_mc_template(const uint16_t* frames, int n, long long M, uint16_t* tmpl, hipStream_t st);
-// integral images of T and T^2 ([H+1][W+1] each, uint64) and the window tables
+// integral images of T and T^2 ([H+1][W+1] each, uint64) and the window
+// tables: sum T and the reciprocal root of 441 sum T^2 - (sum T)^2
 hipError_t launch_mc_tables(const McGeom& g, const uint16_t* tmpl, unsigned long long* ii,
                             double* sT, double* vT, hipStream_t st);
 hipError_t launch_mc_scores(const McScoreArgs& a, hipStream_t st);
