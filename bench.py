@@ -12,8 +12,9 @@ the dominant kernel, i.e. the longer of the streaming summary kernel (timed
 with HIP events recorded on the stream it runs on) and the per-component NMF
 (timed by the library with HIP events on the same stream), with the other
 one beside it; the voltage traces of the same video (the stage after
-segmentation, outside the step) with their own HBM roofline; and the CPU
-oracle timed on a bounded sample.
+segmentation, outside the step) with their own HBM roofline; the motion
+correction of the video with planted drift; the paper's summary U-Net
+detector's network time; and the CPU oracle timed on a bounded sample.
 
 `traffic` is the HBM bytes per launch measured by hardware counters
 (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), read from the
@@ -172,6 +173,50 @@ def motion_bench(video, vdev, reps, dev, seed):
                               "note": "Table I, the paper's GPU motion correction; context only"}}
 
 
+# resolution (pixels of a 64 x 64 patch) at which each layer of the summary
+# U-Net runs: full, half and quarter resolution
+UNET_RES = {"e1a": 4096, "e1b": 4096, "e2a": 1024, "e2b": 1024, "e3a": 256, "e3b": 256, "u2": 256,
+            "d2a": 1024, "d2b": 1024, "u1": 1024, "d1a": 4096, "d1b": 4096, "out": 4096}
+BF16_PEAK = 2.5e15          # FLOP/s, dense BF16 MFMA
+
+
+def unet_bench(vdev, k_time, reps, dev):
+    """The paper's detector input: the summary U-Net on every segment of the
+    video (49 patches of 64 x 64 per 256 x 256 segment), timed as the extra
+    push time of a SEG_DET_UNET session over the plain push (k_time). The
+    weights are He-initialised: the network's work does not depend on them."""
+    import torch
+    from paper_2403_16438_amd import Session, abi
+    from paper_2403_16438_amd.unet import SummaryUNet, he_init, param_layout, patch_count
+    T, H, W = vdev.shape
+    net = SummaryUNet(64, 64, 64, he_init(0), dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tu = []
+    for r in range(reps + 1):
+        s = Session(H, W, T, dev, detector=abi.SEG_DET_UNET, event_z=0.5, min_event_segs=2)
+        s.set_model(net)
+        ev0.record()
+        s.push(vdev)
+        ev1.record()
+        ev1.synchronize()
+        if r:
+            tu.append(ev0.elapsed_time(ev1) * 1e-3)
+        s.close()
+    net.close()
+    t_push = float(np.mean(tu))
+    t_net = max(t_push - k_time, 1e-9)
+    mac = sum(r * c * UNET_RES[n] for n, r, c, _, _ in param_layout())
+    npatch = patch_count(H, W)
+    flops = 2.0 * mac * npatch * (T // SEG_LEN)
+    return {"push_ms": 1e3 * t_push, "network_ms": 1e3 * t_net, "patches_per_segment": npatch,
+            "segments": T // SEG_LEN, "segments_per_s": (T // SEG_LEN) / t_net,
+            "mac_per_patch": mac,
+            "roofline": {"bound": "mfma", "achieved": flops / t_net / 1e12, "peak": BF16_PEAK / 1e12,
+                         "unit": "TFLOP/s", "frac": flops / t_net / BF16_PEAK,
+                         "note": "patches, normalisation, im2col, BF16 MFMA products, merge: the push "
+                                 "time of a SEG_DET_UNET session minus the plain push"}}
+
+
 def serve_bench(args):
     """16 concurrent sessions (frame sizes 128^2, 256^2, 512x128, 512^2 at
     500-1,000 fps, Poisson arrivals 0.5 s apart on average, 20 blocks of 500
@@ -214,13 +259,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=10000)
     ap.add_argument("--seed", type=int, default=2000)
-    ap.add_argument("--cpu-sample", type=int, default=4000)
+    ap.add_argument("--cpu-sample", type=int, default=6000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="the 16-session streaming benchmark")
     ap.add_argument("--sessions", type=int, default=16)
     ap.add_argument("--blocks", type=int, default=20)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--no-motion", action="store_true", help="skip the motion-correction measurement")
+    ap.add_argument("--no-unet", action="store_true", help="skip the summary U-Net measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also copy the resident video once (a plain copy kernel of known size, "
                          "to calibrate hardware byte counters)")
@@ -353,6 +399,7 @@ def main():
                            "line_bytes_per_launch": None if lines is None else 128.0 * lines * T + 4.0 * n_tr * T}}
 
     motion = motion_bench(video, vdev, reps, dev, args.seed) if not args.no_motion else None
+    unet = unet_bench(vdev, float(np.mean(ts)), 2, dev) if not args.no_unet else None
 
     stream_roof = roof("k_block_stats", k_time, FLOPS_PER_PXF * pxf, BYTES_PER_PXF * pxf)
     # NMF: reads the detection maps of the component pixels (FP32 per
@@ -397,6 +444,7 @@ def main():
         "footprints": n_fp,
         "traces": traces,
         "motion": motion,
+        "unet": unet,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -53,6 +53,10 @@ extern "C" {
 #define SEG_DET_SURROGATE 1  /* learned spiking-pixel maps (seg_nn.h, Sec. III-C);
                                 events where the probability >= event_z, NMF on the
                                 probabilities; height and width multiples of 4     */
+#define SEG_DET_UNET      2  /* the paper's U-Net on 64 x 64 patches of each
+                                segment's (S_i, T_i), merged by weighted averaging
+                                (seg_nn_st_*, Sec. III-C); events and NMF as for the
+                                surrogate; height and width at least 64           */
 
 /* execution of the per-component NMF (Eq. 3); every path computes the same
  * factorisation, they differ in the order of sums over pixels only */
@@ -195,7 +199,11 @@ int seg_get_segment_maps(seg_session* s, int kind, uint32_t first,
  *            (V(x) - R_i(x)) (V(y) - R_i(y)) for y = x, x + (0,1), x + (1,0),
  *            x + (1,1), x + (1,-1), with R_i any per-pixel integer reference
  * U and P may be NULL (the correlation image is then 0). The session must be
- * fresh (nothing pushed). Errors: SEG_E_INVAL, SEG_E_STATE, SEG_E_CAPACITY. */
+ * fresh (nothing pushed). A SEG_DET_UNET session runs its network on the
+ * loaded S and T here (its model must be set: SEG_E_NOMODEL); a
+ * SEG_DET_SURROGATE session cannot load summaries (SEG_E_STATE), since its
+ * maps come from the frames. Errors: SEG_E_INVAL, SEG_E_STATE,
+ * SEG_E_CAPACITY, SEG_E_NOMODEL, SEG_E_DEVICE. */
 int seg_load_summaries(seg_session* s, uint32_t k, const float* T,
                        const float* S, const float* D, const float* U,
                        const float* P);
@@ -231,10 +239,14 @@ int seg_push_batch(seg_batch* b, seg_session* const* sessions,
 /* Release the batch object (not the caller's device table). */
 int seg_batch_destroy(seg_batch* b);
 
-/* Attach the surrogate network used by a SEG_DET_SURROGATE session (before
- * the first push). The network must have been created for the session's
- * height and width; it is used on the push stream, one segment at a time,
- * and must outlive the session's pushes. Errors: SEG_E_INVAL, SEG_E_STATE. */
+/* Attach the network of a learned detector (before the first push). For
+ * SEG_DET_SURROGATE a frame network (seg_nn_create) of the session's height
+ * and width; for SEG_DET_UNET a summary network (seg_nn_st_create) of
+ * 64 x 64 patches, run on each segment's patches as the push completes it
+ * (and on every segment given to seg_load_summaries). The network is used on
+ * the push stream and must outlive the session's pushes.
+ * Errors: SEG_E_INVAL, SEG_E_STATE, SEG_E_SHAPE (wrong network shape or
+ * input). */
 int seg_set_model(seg_session* s, struct seg_nn* net);
 
 /* Release the session (not the caller's workspace). NULL is a no-op. */

@@ -90,6 +90,48 @@ int seg_nn_shape(const seg_nn* n, uint32_t* batch, uint32_t* height, uint32_t* w
 
 int seg_nn_destroy(seg_nn* n);
 
+/* ---- the paper's input: summary-image patches (Sec. III-C) -----------------
+ *
+ * The same U-Net without the temporal layers: its first convolution reads a
+ * 2-channel patch (S_i, T_i) of a segment's summary images, normalised inside
+ * as channel 0 = (S - mean over the patch) / max(sd over the patch, 1e-3)
+ * and channel 1 = T / sqrt(S + 25). Over a frame it runs on 64 x 64 patches
+ * at origins every 32 pixels (the last one flush with the far edge, frames
+ * of at least 64 x 64), and a frame pixel's probability is the mean of the
+ * patches' probabilities weighted by w(u) w(v), w(u) = 1 - |u - 31.5| / 32
+ * (u, v: the pixel's position in the patch). A network made by
+ * seg_nn_st_create takes these calls in place of the frame calls (which
+ * return SEG_E_STATE on it, and the other way round); seg_nn_sync_weights,
+ * seg_nn_step, seg_nn_logits, seg_nn_shape and seg_nn_destroy are shared.
+ * The parameter table is that of seg_nn_param_layout with layers t1, t2, t3
+ * empty (0 x 0) and e1a of 32 x 18.
+ *   dev_st  device float [batch][2][height][width]: raw S then raw T. */
+#define SEG_NN_INPUT_FRAMES    0
+#define SEG_NN_INPUT_SUMMARIES 1
+int seg_nn_st_param_count(size_t* n);
+int seg_nn_st_param_layout(uint32_t index, uint32_t* rows, uint32_t* cols,
+                           size_t* w_offset, size_t* b_offset);
+int seg_nn_st_workspace_bytes(uint32_t batch, uint32_t height, uint32_t width,
+                              size_t* bytes);
+int seg_nn_st_create(uint32_t batch, uint32_t height, uint32_t width,
+                     float* dev_params, void* dev_workspace, size_t bytes,
+                     seg_nn** out);
+int seg_nn_st_forward(seg_nn* n, const float* dev_st, uint32_t batch,
+                      float* dev_prob, void* stream);
+int seg_nn_st_backward(seg_nn* n, const float* dev_st, const float* dev_labels,
+                       uint32_t batch, float* dev_grad, float* host_loss,
+                       void* stream);
+/* SEG_NN_INPUT_FRAMES or SEG_NN_INPUT_SUMMARIES. Errors: SEG_E_INVAL. */
+int seg_nn_input(const seg_nn* n, uint32_t* input);
+/* Patches of a height x width frame (both >= 64). Errors: SEG_E_INVAL. */
+int seg_nn_st_patch_count(uint32_t height, uint32_t width, uint32_t* n);
+/* dev_out [n_patch][2][64][64] from device S and T ([height][width] float). */
+int seg_nn_st_patches(const float* dev_S, const float* dev_T, uint32_t height,
+                      uint32_t width, float* dev_out, void* stream);
+/* dev_out [height][width] from patch probabilities [n_patch][64][64]. */
+int seg_nn_st_merge(const float* dev_prob, uint32_t height, uint32_t width,
+                    float* dev_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

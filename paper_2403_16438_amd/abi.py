@@ -23,6 +23,8 @@ SEG_E_NOMODEL = -6
 
 SEG_DET_PLAIN = 0
 SEG_DET_SURROGATE = 1
+SEG_DET_UNET = 2
+SEG_NN_INPUT_FRAMES, SEG_NN_INPUT_SUMMARIES = 0, 1
 SEG_NMF_AUTO, SEG_NMF_SINGLE, SEG_NMF_SPLIT = 0, 1, 2
 
 SEG_IMG_MEAN, SEG_IMG_CORR, SEG_IMG_NOISE = 0, 1, 2
@@ -113,6 +115,17 @@ def _load():
         "seg_nn_gemm_test": (C.c_int, [P, C.c_int, P, C.c_int, P, C.c_int, C.c_int, C.c_int, C.c_int, P, P]),
         "seg_nn_destroy": (C.c_int, [P]),
         "seg_nn_shape": (C.c_int, [P, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]),
+        "seg_nn_st_param_count": (C.c_int, [C.POINTER(C.c_size_t)]),
+        "seg_nn_st_param_layout": (C.c_int, [u32, C.POINTER(u32), C.POINTER(u32), C.POINTER(C.c_size_t),
+                                             C.POINTER(C.c_size_t)]),
+        "seg_nn_st_workspace_bytes": (C.c_int, [u32, u32, u32, C.POINTER(C.c_size_t)]),
+        "seg_nn_st_create": (C.c_int, [u32, u32, u32, P, P, C.c_size_t, C.POINTER(P)]),
+        "seg_nn_st_forward": (C.c_int, [P, P, u32, P, P]),
+        "seg_nn_st_backward": (C.c_int, [P, P, P, u32, P, C.POINTER(C.c_float), P]),
+        "seg_nn_input": (C.c_int, [P, C.POINTER(u32)]),
+        "seg_nn_st_patch_count": (C.c_int, [u32, u32, C.POINTER(u32)]),
+        "seg_nn_st_patches": (C.c_int, [P, P, u32, u32, P, P]),
+        "seg_nn_st_merge": (C.c_int, [P, u32, u32, P, P]),
         "seg_set_model": (C.c_int, [P, P]),
         "seg_mc_default_config": (C.c_int, [u32, u32, C.POINTER(seg_mc_config)]),
         "seg_mc_workspace_bytes": (C.c_int, [C.POINTER(seg_mc_config), C.POINTER(C.c_size_t)]),

@@ -353,6 +353,77 @@ __global__ void k_to_bf16(const float* __restrict__ w, uint16_t* __restrict__ wb
   if (i < n) wb[i] = to_bf16(w[i]);
 }
 
+// ---- summary-image input (S, T) -------------------------------------------
+
+// One block per patch: exact-enough FP64 mean and population deviation of
+// S, then channel 0 = (S - mean) / max(sd, 1e-3), channel 1 = T / sqrt(S + 25).
+__global__ __launch_bounds__(256) void k_st_norm(const float* __restrict__ stin, float* __restrict__ x, int Bn,
+                                                 long long HW) {
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const float* S = stin + (size_t)b * 2 * HW;
+  const float* T = S + HW;
+  double s = 0.0, s2 = 0.0;
+  for (long long i = tid; i < HW; i += 256) {
+    const double v = S[i];
+    s += v;
+    s2 += v * v;
+  }
+  __shared__ double r1[256], r2[256];
+  r1[tid] = s;
+  r2[tid] = s2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      r1[tid] += r1[tid + o];
+      r2[tid] += r2[tid + o];
+    }
+    __syncthreads();
+  }
+  const double m = r1[0] / (double)HW;
+  const double sd = fmax(sqrt(fmax(r2[0] / (double)HW - m * m, 0.0)), 1e-3);
+  for (long long i = tid; i < HW; i += 256) {
+    x[(size_t)b * HW + i] = (float)(((double)S[i] - m) / sd);
+    x[((size_t)Bn + b) * HW + i] = (float)((double)T[i] / sqrt(fmax((double)S[i], 0.0) + 25.0));
+  }
+}
+
+__device__ __forceinline__ int st_count(int n) { return (n - 64 + 31) / 32 + 1; }
+__device__ __forceinline__ int st_origin(int k, int n) { return min(32 * k, n - 64); }
+
+// out [n_patch][2][64][64], patches in raster order of their origins
+__global__ void k_st_patches(const float* __restrict__ S, const float* __restrict__ T, int H, int W,
+                             float* __restrict__ out) {
+  const int nx = st_count(W);
+  const long long total = (long long)st_count(H) * nx * 2 * 4096;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int k = (int)(i / 8192), r = (int)(i % 8192), c = r / 4096, y = (r % 4096) / 64, x = r % 64;
+  const int oy = st_origin(k / nx, H), ox = st_origin(k % nx, W);
+  out[i] = (c ? T : S)[(size_t)(oy + y) * W + ox + x];
+}
+
+// out(y, x) = sum_k w w prob_k / sum_k w w over the patches that hold the pixel
+__global__ void k_st_merge(const float* __restrict__ prob, int H, int W, float* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)H * W) return;
+  const int y = (int)(i / W), x = (int)(i % W);
+  const int ny = st_count(H), nx = st_count(W);
+  double num = 0.0, den = 0.0;
+  for (int ky = 0; ky < ny; ++ky) {
+    const int oy = st_origin(ky, H);
+    if (y < oy || y >= oy + 64) continue;
+    const double wy = 1.0 - fabs((double)(y - oy) - 31.5) / 32.0;
+    for (int kx = 0; kx < nx; ++kx) {
+      const int ox = st_origin(kx, W);
+      if (x < ox || x >= ox + 64) continue;
+      const double w = wy * (1.0 - fabs((double)(x - ox) - 31.5) / 32.0);
+      num += w * (double)prob[(size_t)(ky * nx + kx) * 4096 + (y - oy) * 64 + (x - ox)];
+      den += w;
+    }
+  }
+  out[i] = (float)(num / den);
+}
+
 inline dim3 grid1(long long n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
 }  // namespace
@@ -435,6 +506,17 @@ void rmsprop(float* w, const float* g, float* v, uint16_t* wb, long long n, floa
   L1(k_rmsprop, n, w, g, v, wb, n, lr, rho, eps);
 }
 void to_bf16_copy(const float* w, uint16_t* wb, long long n, hipStream_t st) { L1(k_to_bf16, n, w, wb, n); }
+
+void st_norm(const float* stin, float* x, int Bn, long long HW, hipStream_t stream) {
+  hipLaunchKernelGGL(k_st_norm, dim3((unsigned)Bn), dim3(256), 0, stream, stin, x, Bn, HW);
+}
+int st_origins(int n) { return (n - 64 + 31) / 32 + 1; }
+void st_patches(const float* S, const float* T, int H, int W, float* out, hipStream_t st) {
+  L1(k_st_patches, (long long)st_origins(H) * st_origins(W) * 2 * 4096, S, T, H, W, out);
+}
+void st_merge(const float* prob, int H, int W, float* out, hipStream_t st) {
+  L1(k_st_merge, (long long)H * W, prob, H, W, out);
+}
 
 }  // namespace nn
 }  // namespace seg

@@ -38,19 +38,27 @@ const PDef kP[NPAR] = {
     {32, 32 * 9},     // d1b
     {1, 32},          // output 1x1
 };
-int bias_len(int id) { return (id == U2 || id == U1) ? kP[id].rows / 4 : kP[id].rows; }
+// The summary-image network (paper's input, Sec. III-C): no temporal
+// layers, and the first convolution reads the two channels (S, T).
+const PDef kPst[NPAR] = {
+    {0, 0}, {0, 0}, {0, 0},
+    {32, 2 * 9},      // e1a: (S, T) -> 32
+    {32, 32 * 9}, {64, 32 * 9}, {64, 64 * 9}, {128, 64 * 9}, {128, 128 * 9}, {64 * 4, 128},
+    {64, 128 * 9}, {64, 64 * 9}, {32 * 4, 64}, {32, 64 * 9}, {32, 32 * 9}, {1, 32},
+};
+int bias_len(const PDef* P, int id) { return (id == U2 || id == U1) ? P[id].rows / 4 : P[id].rows; }
 
 struct POff {
   size_t w[NPAR], b[NPAR], total;
 };
-POff param_offsets() {
+POff param_offsets(const PDef* P) {
   POff o{};
   size_t at = 0;
   for (int i = 0; i < NPAR; ++i) {
     o.w[i] = at;
-    at += (size_t)kP[i].rows * kP[i].cols;
+    at += (size_t)P[i].rows * P[i].cols;
     o.b[i] = at;
-    at += bias_len(i);
+    at += bias_len(P, i);
   }
   o.total = at;
   return o;
@@ -76,7 +84,7 @@ struct Plan {
   size_t total;
 };
 
-Plan make_plan(int B, int H, int W) {
+Plan make_plan(int B, int H, int W, bool st) {
   Plan p{};
   p.B = B;
   p.H = H;
@@ -92,10 +100,11 @@ Plan make_plan(int B, int H, int W) {
   };
   const size_t f = 4;
   const long long N = p.N, N2 = p.N2, N4 = p.N4;
-  p.x0 = take(f * L * N);
-  p.a1 = take(f * 32 * 10 * N);
-  p.a2 = take(f * 32 * 5 * N);
-  p.a3 = take(f * 32 * N);
+  const long long tn = st ? 0 : 1;   // temporal activations (frames input only)
+  p.x0 = take(f * (st ? 2 : L) * N);
+  p.a1 = take(f * 32 * 10 * N * tn);
+  p.a2 = take(f * 32 * 5 * N * tn);
+  p.a3 = take(f * 32 * N * tn);
   p.e1a = take(f * 32 * N);
   p.cat1 = take(f * 64 * N);
   p.p1 = take(f * 32 * N2);
@@ -114,9 +123,9 @@ Plan make_plan(int B, int H, int W) {
   p.prob = take(f * N);
   p.arg1 = take(32 * N2);
   p.arg2 = take(64 * N4);
-  p.ga1 = take(f * 32 * 10 * N);
-  p.ga2 = take(f * 32 * 5 * N);
-  p.ga3 = take(f * 32 * N);
+  p.ga1 = take(f * 32 * 10 * N * tn);
+  p.ga2 = take(f * 32 * 5 * N * tn);
+  p.ga3 = take(f * 32 * N * tn);
   p.ge1a = take(f * 32 * N);
   p.gcat1 = take(f * 64 * N);
   p.gp1 = take(f * 32 * N2);
@@ -142,7 +151,7 @@ Plan make_plan(int B, int H, int W) {
   p.dcol = take(f * colmax);
   p.splitk = take(f * (size_t)SPLITS * 256 * 1152);
   p.lossp = take(f * ((N + 255) / 256 + 1));
-  const POff po = param_offsets();
+  const POff po = param_offsets(st ? kPst : kP);
   p.wb = take(2 * po.total);
   p.grad = take(f * po.total);
   p.vel = take(f * po.total);
@@ -155,6 +164,8 @@ Plan make_plan(int B, int H, int W) {
 struct seg_nn {
   Plan plan;
   POff po;
+  const PDef* P;   // parameter table of the input mode
+  bool st;         // input: summary-image patches (S, T) instead of frames
   char* ws;
   float* params;   // caller's FP32 master weights
   int device;
@@ -176,7 +187,7 @@ hipError_t gemm_wx(seg_nn* n, int id, const void* X, bool x_bf16, long long ncol
   // Y [rows][ncols] = W [rows][cols] X [cols][ncols]
   GemmOp g{};
   g.A = wbf(n, id);
-  g.sam = kP[id].cols;
+  g.sam = n->P[id].cols;
   g.sak = 1;
   g.a_bf16 = true;
   g.B = X;
@@ -184,9 +195,9 @@ hipError_t gemm_wx(seg_nn* n, int id, const void* X, bool x_bf16, long long ncol
   g.sbn = 1;
   g.b_bf16 = x_bf16;
   g.C = Y;
-  g.M = kP[id].rows;
+  g.M = n->P[id].rows;
   g.N = (int)ncols;
-  g.K = kP[id].cols;
+  g.K = n->P[id].cols;
   g.splits = 1;
   return gemm(g, st);
 }
@@ -196,16 +207,16 @@ hipError_t gemm_wtdy(seg_nn* n, int id, const float* dY, long long ncols, float*
   GemmOp g{};
   g.A = wbf(n, id);
   g.sam = 1;
-  g.sak = kP[id].cols;
+  g.sak = n->P[id].cols;
   g.a_bf16 = true;
   g.B = dY;
   g.sbk = ncols;
   g.sbn = 1;
   g.b_bf16 = false;
   g.C = dX;
-  g.M = kP[id].cols;
+  g.M = n->P[id].cols;
   g.N = (int)ncols;
-  g.K = kP[id].rows;
+  g.K = n->P[id].rows;
   g.splits = 1;
   return gemm(g, st);
 }
@@ -222,8 +233,8 @@ hipError_t gemm_dw(seg_nn* n, int id, const float* dY, const void* X, bool x_bf1
   g.sbn = ncols;
   g.b_bf16 = x_bf16;
   g.C = gw(n, id);
-  g.M = kP[id].rows;
-  g.N = kP[id].cols;
+  g.M = n->P[id].rows;
+  g.N = n->P[id].cols;
   g.K = (int)ncols;
   g.splits = SPLITS;
   g.scratch = at<float>(n, n->plan.splitk);
@@ -232,12 +243,12 @@ hipError_t gemm_dw(seg_nn* n, int id, const float* dY, const void* X, bool x_bf1
 
 // 3x3 convolution + bias (+ ReLU): X [Ci][Bn H W] -> Y [Co][Bn H W]
 hipError_t conv3(seg_nn* n, int id, const float* X, int Bn, int H, int W, float* Y, bool relu, hipStream_t st) {
-  const int Ci = kP[id].cols / 9;
+  const int Ci = n->P[id].cols / 9;
   const long long N = (long long)Bn * H * W;
   uint16_t* col = at<uint16_t>(n, n->plan.col);
   im2col3(X, col, Ci, Bn, H, W, st);
   hipError_t e = gemm_wx(n, id, col, true, N, Y, st);
-  bias_act(Y, bias(n, id), kP[id].rows, N, relu, st);
+  bias_act(Y, bias(n, id), n->P[id].rows, N, relu, st);
   return e;
 }
 
@@ -245,7 +256,7 @@ hipError_t conv3(seg_nn* n, int id, const float* X, int Bn, int H, int W, float*
 // gradients, input gradient into dX (accumulated when acc)
 hipError_t conv3_bwd(seg_nn* n, int id, const float* X, const float* Y, float* dY, int Bn, int H, int W,
                      float* dX, bool acc, bool relu, hipStream_t st) {
-  const int Ci = kP[id].cols / 9, Co = kP[id].rows;
+  const int Ci = n->P[id].cols / 9, Co = n->P[id].rows;
   const long long N = (long long)Bn * H * W;
   if (relu) relu_bwd(dY, Y, (long long)Co * N, st);
   bias_grad(dY, gb(n, id), Co, N, st);
@@ -260,7 +271,7 @@ hipError_t conv3_bwd(seg_nn* n, int id, const float* X, const float* Y, float* d
   return e;
 }
 
-hipError_t forward(seg_nn* n, const uint16_t* frames, int Bn, hipStream_t st) {
+hipError_t forward(seg_nn* n, const uint16_t* frames, const float* stin, int Bn, hipStream_t st) {
   const Plan& p = n->plan;
   const int H = p.H, W = p.W;
   const long long HW = (long long)H * W;
@@ -270,25 +281,32 @@ hipError_t forward(seg_nn* n, const uint16_t* frames, int Bn, hipStream_t st) {
     if (x != hipSuccess && e == hipSuccess) e = x;
   };
   float* x0 = at<float>(n, p.x0);
-  tnorm(frames, x0, Bn, L, HW, st);
   uint16_t* col = at<uint16_t>(n, p.col);
-  // temporal convolutions
-  float* a1 = at<float>(n, p.a1);
-  im2col1(x0, col, 1, L, 10, 5, 5, 0, N, st);
-  chk(gemm_wx(n, T1, col, true, 10 * N, a1, st));
-  bias_act(a1, bias(n, T1), 32, 10 * N, true, st);
-  float* a2 = at<float>(n, p.a2);
-  im2col1(a1, col, 32, 10, 5, 5, 2, 2, N, st);
-  chk(gemm_wx(n, T2, col, true, 5 * N, a2, st));
-  bias_act(a2, bias(n, T2), 32, 5 * N, true, st);
-  float* a3 = at<float>(n, p.a3);
-  chk(gemm_wx(n, T3, a2, false, N, a3, st));     // a2 viewed as [160][N]
-  bias_act(a3, bias(n, T3), 32, N, true, st);
+  const float* unet_in = nullptr;   // input of the first 3x3 convolution
+  if (n->st) {
+    st_norm(stin, x0, Bn, HW, st);
+    unet_in = x0;
+  } else {
+    tnorm(frames, x0, Bn, L, HW, st);
+    // temporal convolutions
+    float* a1 = at<float>(n, p.a1);
+    im2col1(x0, col, 1, L, 10, 5, 5, 0, N, st);
+    chk(gemm_wx(n, T1, col, true, 10 * N, a1, st));
+    bias_act(a1, bias(n, T1), 32, 10 * N, true, st);
+    float* a2 = at<float>(n, p.a2);
+    im2col1(a1, col, 32, 10, 5, 5, 2, 2, N, st);
+    chk(gemm_wx(n, T2, col, true, 5 * N, a2, st));
+    bias_act(a2, bias(n, T2), 32, 5 * N, true, st);
+    float* a3 = at<float>(n, p.a3);
+    chk(gemm_wx(n, T3, a2, false, N, a3, st));     // a2 viewed as [160][N]
+    bias_act(a3, bias(n, T3), 32, N, true, st);
+    unet_in = a3;
+  }
   // U-Net encoder
   float* e1a = at<float>(n, p.e1a);
   float* cat1 = at<float>(n, p.cat1);
   float* s1 = cat1 + 32 * N;
-  chk(conv3(n, E1A, a3, Bn, H, W, e1a, true, st));
+  chk(conv3(n, E1A, unet_in, Bn, H, W, e1a, true, st));
   chk(conv3(n, E1B, e1a, Bn, H, W, s1, true, st));
   float* p1 = at<float>(n, p.p1);
   pool(s1, p1, at<uint8_t>(n, p.arg1), 32 * Bn, H, W, st);
@@ -393,6 +411,11 @@ hipError_t backward(seg_nn* n, int Bn, hipStream_t st) {
   float* a3 = at<float>(n, p.a3);
   float* ga3 = at<float>(n, p.ga3);
   chk(conv3_bwd(n, E1B, e1a, cat1 + 32 * N, gs1, Bn, H, W, ge1a, false, true, st));
+  if (n->st) {   // the input needs no gradient
+    chk(conv3_bwd(n, E1A, at<float>(n, p.x0), e1a, ge1a, Bn, H, W, nullptr, false, true, st));
+    chk(hipGetLastError());
+    return e;
+  }
   chk(conv3_bwd(n, E1A, a3, e1a, ge1a, Bn, H, W, ga3, false, true, st));
   // temporal convolutions
   float* a2 = at<float>(n, p.a2);
@@ -430,40 +453,65 @@ extern "C" {
 
 int seg_nn_param_count(size_t* n) {
   if (!n) return SEG_E_INVAL;
-  *n = param_offsets().total;
+  *n = param_offsets(kP).total;
   return SEG_OK;
 }
 
-int seg_nn_param_layout(uint32_t index, uint32_t* rows, uint32_t* cols, size_t* w_offset, size_t* b_offset) {
+int seg_nn_st_param_count(size_t* n) {
+  if (!n) return SEG_E_INVAL;
+  *n = param_offsets(kPst).total;
+  return SEG_OK;
+}
+
+static int layout_of(const PDef* P, uint32_t index, uint32_t* rows, uint32_t* cols, size_t* w_offset,
+                     size_t* b_offset) {
   if (index >= (uint32_t)NPAR) return SEG_E_INVAL;
-  const POff o = param_offsets();
-  if (rows) *rows = (uint32_t)kP[index].rows;
-  if (cols) *cols = (uint32_t)kP[index].cols;
+  const POff o = param_offsets(P);
+  if (rows) *rows = (uint32_t)P[index].rows;
+  if (cols) *cols = (uint32_t)P[index].cols;
   if (w_offset) *w_offset = o.w[index];
   if (b_offset) *b_offset = o.b[index];
   return SEG_OK;
 }
 
-int seg_nn_workspace_bytes(uint32_t batch, uint32_t height, uint32_t width, size_t* bytes) {
+int seg_nn_param_layout(uint32_t index, uint32_t* rows, uint32_t* cols, size_t* w_offset, size_t* b_offset) {
+  return layout_of(kP, index, rows, cols, w_offset, b_offset);
+}
+
+int seg_nn_st_param_layout(uint32_t index, uint32_t* rows, uint32_t* cols, size_t* w_offset, size_t* b_offset) {
+  return layout_of(kPst, index, rows, cols, w_offset, b_offset);
+}
+
+static int ws_bytes(uint32_t batch, uint32_t height, uint32_t width, bool st, size_t* bytes) {
   if (!bytes || batch < 1 || height < 4 || width < 4 || height % 4 || width % 4) return SEG_E_INVAL;
   if ((long long)batch * height * width * 576 >= (1LL << 31)) return SEG_E_INVAL;
-  *bytes = make_plan((int)batch, (int)height, (int)width).total;
+  *bytes = make_plan((int)batch, (int)height, (int)width, st).total;
   return SEG_OK;
 }
 
-int seg_nn_create(uint32_t batch, uint32_t height, uint32_t width, float* dev_params, void* dev_workspace,
+int seg_nn_workspace_bytes(uint32_t batch, uint32_t height, uint32_t width, size_t* bytes) {
+  return ws_bytes(batch, height, width, false, bytes);
+}
+
+int seg_nn_st_workspace_bytes(uint32_t batch, uint32_t height, uint32_t width, size_t* bytes) {
+  return ws_bytes(batch, height, width, true, bytes);
+}
+
+static int create(uint32_t batch, uint32_t height, uint32_t width, bool st, float* dev_params, void* dev_workspace,
                   size_t bytes, seg_nn** out) {
   if (!out || !dev_params || !dev_workspace) return SEG_E_INVAL;
   *out = nullptr;
   size_t need = 0;
-  int e = seg_nn_workspace_bytes(batch, height, width, &need);
+  int e = ws_bytes(batch, height, width, st, &need);
   if (e) return e;
   if (bytes < need) return SEG_E_CAPACITY;
   if (reinterpret_cast<uintptr_t>(dev_workspace) & 255) return SEG_E_INVAL;
   seg_nn* n = new (std::nothrow) seg_nn();
   if (!n) return SEG_E_INVAL;
-  n->plan = make_plan((int)batch, (int)height, (int)width);
-  n->po = param_offsets();
+  n->plan = make_plan((int)batch, (int)height, (int)width, st);
+  n->P = st ? kPst : kP;
+  n->st = st;
+  n->po = param_offsets(n->P);
   n->ws = static_cast<char*>(dev_workspace);
   n->params = dev_params;
   n->batch = 0;
@@ -475,6 +523,16 @@ int seg_nn_create(uint32_t batch, uint32_t height, uint32_t width, float* dev_pa
   return SEG_OK;
 }
 
+int seg_nn_create(uint32_t batch, uint32_t height, uint32_t width, float* dev_params, void* dev_workspace,
+                  size_t bytes, seg_nn** out) {
+  return create(batch, height, width, false, dev_params, dev_workspace, bytes, out);
+}
+
+int seg_nn_st_create(uint32_t batch, uint32_t height, uint32_t width, float* dev_params, void* dev_workspace,
+                     size_t bytes, seg_nn** out) {
+  return create(batch, height, width, true, dev_params, dev_workspace, bytes, out);
+}
+
 int seg_nn_sync_weights(seg_nn* n, void* stream) {
   int e = enter(n);
   if (e) return e;
@@ -484,12 +542,14 @@ int seg_nn_sync_weights(seg_nn* n, void* stream) {
   return hipGetLastError() == hipSuccess ? SEG_OK : SEG_E_DEVICE;
 }
 
-int seg_nn_forward(seg_nn* n, const uint16_t* dev_frames, uint32_t batch, float* dev_prob, void* stream) {
+static int run_forward(seg_nn* n, const uint16_t* frames, const float* stin, uint32_t batch, float* dev_prob,
+                       void* stream) {
   int e = enter(n);
   if (e) return e;
-  if (!dev_frames || batch < 1 || (int)batch > n->plan.B) return SEG_E_INVAL;
+  if ((n->st ? (const void*)stin : (const void*)frames) == nullptr || batch < 1 || (int)batch > n->plan.B)
+    return SEG_E_INVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (forward(n, dev_frames, (int)batch, st) != hipSuccess) return SEG_E_DEVICE;
+  if (forward(n, frames, stin, (int)batch, st) != hipSuccess) return SEG_E_DEVICE;
   const long long N = (long long)batch * n->plan.H * n->plan.W;
   bce(at<float>(n, n->plan.logit), nullptr, nullptr, dev_prob ? dev_prob : at<float>(n, n->plan.prob), nullptr, N,
       st);
@@ -497,13 +557,15 @@ int seg_nn_forward(seg_nn* n, const uint16_t* dev_frames, uint32_t batch, float*
   return hipGetLastError() == hipSuccess ? SEG_OK : SEG_E_DEVICE;
 }
 
-int seg_nn_backward(seg_nn* n, const uint16_t* dev_frames, const float* dev_labels, uint32_t batch,
-                    float* dev_grad, float* host_loss, void* stream) {
+static int run_backward(seg_nn* n, const uint16_t* frames, const float* stin, const float* dev_labels,
+                        uint32_t batch, float* dev_grad, float* host_loss, void* stream) {
   int e = enter(n);
   if (e) return e;
-  if (!dev_frames || !dev_labels || batch < 1 || (int)batch > n->plan.B) return SEG_E_INVAL;
+  if ((n->st ? (const void*)stin : (const void*)frames) == nullptr || !dev_labels || batch < 1 ||
+      (int)batch > n->plan.B)
+    return SEG_E_INVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (forward(n, dev_frames, (int)batch, st) != hipSuccess) return SEG_E_DEVICE;
+  if (forward(n, frames, stin, (int)batch, st) != hipSuccess) return SEG_E_DEVICE;
   const long long N = (long long)batch * n->plan.H * n->plan.W;
   float* part = at<float>(n, n->plan.lossp);
   bce(at<float>(n, n->plan.logit), dev_labels, at<float>(n, n->plan.glogit), at<float>(n, n->plan.prob), part, N,
@@ -525,6 +587,53 @@ int seg_nn_backward(seg_nn* n, const uint16_t* dev_frames, const float* dev_labe
     *host_loss = (float)(s / (double)N);
   }
   return hipGetLastError() == hipSuccess ? SEG_OK : SEG_E_DEVICE;
+}
+
+int seg_nn_forward(seg_nn* n, const uint16_t* dev_frames, uint32_t batch, float* dev_prob, void* stream) {
+  if (n && n->st) return SEG_E_STATE;
+  return run_forward(n, dev_frames, nullptr, batch, dev_prob, stream);
+}
+
+int seg_nn_backward(seg_nn* n, const uint16_t* dev_frames, const float* dev_labels, uint32_t batch,
+                    float* dev_grad, float* host_loss, void* stream) {
+  if (n && n->st) return SEG_E_STATE;
+  return run_backward(n, dev_frames, nullptr, dev_labels, batch, dev_grad, host_loss, stream);
+}
+
+int seg_nn_st_forward(seg_nn* n, const float* dev_st, uint32_t batch, float* dev_prob, void* stream) {
+  if (n && !n->st) return SEG_E_STATE;
+  return run_forward(n, nullptr, dev_st, batch, dev_prob, stream);
+}
+
+int seg_nn_st_backward(seg_nn* n, const float* dev_st, const float* dev_labels, uint32_t batch, float* dev_grad,
+                       float* host_loss, void* stream) {
+  if (n && !n->st) return SEG_E_STATE;
+  return run_backward(n, nullptr, dev_st, dev_labels, batch, dev_grad, host_loss, stream);
+}
+
+int seg_nn_st_patch_count(uint32_t height, uint32_t width, uint32_t* n) {
+  if (!n || height < 64 || width < 64) return SEG_E_INVAL;
+  *n = (uint32_t)(st_origins((int)height) * st_origins((int)width));
+  return SEG_OK;
+}
+
+int seg_nn_st_patches(const float* dev_S, const float* dev_T, uint32_t height, uint32_t width, float* dev_out,
+                      void* stream) {
+  if (!dev_S || !dev_T || !dev_out || height < 64 || width < 64) return SEG_E_INVAL;
+  st_patches(dev_S, dev_T, (int)height, (int)width, dev_out, static_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? SEG_OK : SEG_E_DEVICE;
+}
+
+int seg_nn_st_merge(const float* dev_prob, uint32_t height, uint32_t width, float* dev_out, void* stream) {
+  if (!dev_prob || !dev_out || height < 64 || width < 64) return SEG_E_INVAL;
+  st_merge(dev_prob, (int)height, (int)width, dev_out, static_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? SEG_OK : SEG_E_DEVICE;
+}
+
+int seg_nn_input(const seg_nn* n, uint32_t* input) {
+  if (!n || !input) return SEG_E_INVAL;
+  *input = n->st ? SEG_NN_INPUT_SUMMARIES : SEG_NN_INPUT_FRAMES;
+  return SEG_OK;
 }
 
 int seg_nn_step(seg_nn* n, float lr, float rho, float eps, void* stream) {

@@ -47,5 +47,14 @@ void rmsprop(float* w, const float* g, float* v, uint16_t* wb, long long n, floa
              hipStream_t st);
 void to_bf16_copy(const float* w, uint16_t* wb, long long n, hipStream_t st);
 
+// summary-image input (S, T): st [Bn][2][HW] -> x [2][Bn HW] with channel 0
+// the patch-standardised S and channel 1 T / sqrt(S + 25)
+void st_norm(const float* st, float* x, int Bn, long long HW, hipStream_t stream);
+// 64 x 64 patches at origins every 32 pixels, the last one flush with the edge
+int st_origins(int n);
+void st_patches(const float* S, const float* T, int H, int W, float* out, hipStream_t stream);
+// tent-weighted mean of patch probabilities [n_patch][64][64] over the frame
+void st_merge(const float* prob, int H, int W, float* out, hipStream_t stream);
+
 }  // namespace nn
 }  // namespace seg

@@ -41,8 +41,10 @@ int check_config(const seg_config* c) {
   if (!(c->spa_delta >= 0.f) || !(c->footprint_level > 0.f && c->footprint_level <= 1.f))
     return SEG_E_INVAL;
   if (!(c->sigma_floor >= 0.f)) return SEG_E_INVAL;
-  if (c->detector != SEG_DET_PLAIN && c->detector != SEG_DET_SURROGATE) return SEG_E_INVAL;
+  if (c->detector != SEG_DET_PLAIN && c->detector != SEG_DET_SURROGATE && c->detector != SEG_DET_UNET)
+    return SEG_E_INVAL;
   if (c->detector == SEG_DET_SURROGATE && (c->height % 4 || c->width % 4)) return SEG_E_INVAL;
+  if (c->detector == SEG_DET_UNET && (c->height < 64 || c->width < 64)) return SEG_E_INVAL;
   if (c->nmf_path > SEG_NMF_SPLIT) return SEG_E_INVAL;
   return SEG_OK;
 }
@@ -102,7 +104,14 @@ Layout make_layout(const seg_config& c) {
   l.nmf_W = take(l.Ccap * 2 * K * 8);
   l.nmf_N = take(l.Ccap * 4);
   l.cmom = take(5 * M * 8);
-  l.stage = take(c.detector == SEG_DET_SURROGATE ? (size_t)kSegLen * M * 2 : 0);
+  size_t stage = 0;
+  if (c.detector == SEG_DET_SURROGATE) stage = (size_t)kSegLen * M * 2;
+  if (c.detector == SEG_DET_UNET) {
+    uint32_t np = 0;
+    seg_nn_st_patch_count(c.height, c.width, &np);
+    stage = (size_t)np * 3 * 4096 * 4;   // patches (S, T) and their probabilities
+  }
+  l.stage = take(stage);
   l.total = o;
   return l;
 }
@@ -140,6 +149,30 @@ int surrogate_maps(seg_session* s, const uint16_t* dev_frames, uint32_t nseg, hi
     if (fail(s, he)) return SEG_E_DEVICE;
     const int r = seg_nn_forward(s->net, stage, 1, p + (size_t)(s->K + j) * M, st);
     if (r) return fail(s, hipErrorUnknown);
+  }
+  return SEG_OK;
+}
+
+// Summary-image U-Net: for segments first .. first + nseg - 1 (whose S and T
+// are written), cut the patches, run the network in batches and merge the
+// patch probabilities into p[k].
+int unet_maps(seg_session* s, uint32_t first, uint32_t nseg, hipStream_t st) {
+  const size_t M = s->M;
+  const uint32_t H = s->cfg.height, W = s->cfg.width;
+  uint32_t np = 0, B = 0;
+  if (seg_nn_st_patch_count(H, W, &np) || seg_nn_shape(s->net, &B, nullptr, nullptr)) return fail(s, hipErrorUnknown);
+  float* in = at<float>(s, s->lay.stage);
+  float* prob = in + (size_t)np * 2 * 4096;
+  for (uint32_t j = 0; j < nseg; ++j) {
+    const size_t k = first + j;
+    if (seg_nn_st_patches(at<float>(s, s->lay.S) + k * M, at<float>(s, s->lay.T) + k * M, H, W, in, st))
+      return fail(s, hipErrorUnknown);
+    for (uint32_t a = 0; a < np; a += B) {
+      const uint32_t b = std::min(B, np - a);
+      if (seg_nn_st_forward(s->net, in + (size_t)a * 2 * 4096, b, prob + (size_t)a * 4096, st))
+        return fail(s, hipErrorUnknown);
+    }
+    if (seg_nn_st_merge(prob, H, W, at<float>(s, s->lay.p) + k * M, st)) return fail(s, hipErrorUnknown);
   }
   return SEG_OK;
 }
@@ -249,7 +282,7 @@ int seg_push_frames(seg_session* s, const uint16_t* dev_frames, uint32_t n, void
   if (s->state != State::Open) return SEG_E_STATE;
   if (n == 0) return SEG_OK;
   if (!dev_frames) return SEG_E_INVAL;
-  if (s->cfg.detector == SEG_DET_SURROGATE && !s->net) return SEG_E_NOMODEL;
+  if (s->cfg.detector != SEG_DET_PLAIN && !s->net) return SEG_E_NOMODEL;
   if (s->frames + n > s->cfg.max_frames) return SEG_E_CAPACITY;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long M = s->M;
@@ -275,6 +308,7 @@ int seg_push_frames(seg_session* s, const uint16_t* dev_frames, uint32_t n, void
     a.w = s->w;
     if ((e = fail(s, seg::launch_block_stats(a, st)))) return e;
     if (s->cfg.detector == SEG_DET_SURROGATE && (e = surrogate_maps(s, dev_frames, nseg, st))) return e;
+    if (s->cfg.detector == SEG_DET_UNET && (e = unet_maps(s, s->K, nseg, st))) return e;
     if (rem) {
       const uint16_t* from = dev_frames + (size_t)(n - rem) * M;
       if ((e = fail(s, hipMemcpyAsync(tail, from, (size_t)rem * M * 2, hipMemcpyDeviceToDevice, st))))
@@ -298,6 +332,8 @@ int seg_load_summaries(seg_session* s, uint32_t k, const float* T, const float* 
   if (s->state != State::Open || s->frames != 0 || s->K != 0) return SEG_E_STATE;
   if (!T || !S || !D || k == 0) return SEG_E_INVAL;
   if (k > s->Kmax) return SEG_E_CAPACITY;
+  if (s->cfg.detector == SEG_DET_SURROGATE) return SEG_E_STATE;   // its maps need the frames
+  if (s->cfg.detector == SEG_DET_UNET && !s->net) return SEG_E_NOMODEL;
   const size_t n = (size_t)k * s->M * 4;
   if ((e = fail(s, hipMemcpy(at<float>(s, s->lay.T), T, n, hipMemcpyHostToDevice)))) return e;
   if ((e = fail(s, hipMemcpy(at<float>(s, s->lay.S), S, n, hipMemcpyHostToDevice)))) return e;
@@ -314,6 +350,10 @@ int seg_load_summaries(seg_session* s, uint32_t k, const float* T, const float* 
     if ((e = fail(s, hipMemset(at<float>(s, s->lay.U), 0, n)))) return e;
     for (int o = 0; o < 5; ++o)
       if ((e = fail(s, hipMemset(at<float>(s, s->lay.P) + (size_t)o * s->Kmax * s->M, 0, n)))) return e;
+  }
+  if (s->cfg.detector == SEG_DET_UNET) {
+    if ((e = unet_maps(s, 0, k, nullptr))) return e;
+    if ((e = fail(s, hipStreamSynchronize(nullptr)))) return e;
   }
   s->K = k;
   s->frames = (uint64_t)k * seg::kSegLen;
@@ -378,7 +418,7 @@ int seg_finalize(seg_session* s, void* stream) {
   a.area_max = (int)c.area_max;
   a.min_event_segs = (int)c.min_event_segs;
   a.have_moments = true;
-  a.prob_mode = c.detector == SEG_DET_SURROGATE;
+  a.prob_mode = c.detector != SEG_DET_PLAIN;
   s->prof = seg_profile{};
   bool nmf_timed = false;
   if ((e = fail(s, hipEventRecord(s->ev[0], st)))) return e;
@@ -731,7 +771,7 @@ constexpr char kStateMagic[8] = {'S', 'E', 'G', 'S', 'T', 'A', 'T', 'E'};
 
 // T, S, D, U, the five co-moment planes, and the probability maps of the
 // surrogate detector
-uint32_t state_planes(const seg_session* s) { return s->cfg.detector == SEG_DET_SURROGATE ? 10u : 9u; }
+uint32_t state_planes(const seg_session* s) { return s->cfg.detector != SEG_DET_PLAIN ? 10u : 9u; }
 
 float* state_plane(seg_session* s, uint32_t j) {
   const Layout& l = s->lay;
@@ -823,10 +863,15 @@ int seg_get_profile(const seg_session* s, seg_profile* out) {
 }
 
 int seg_set_model(seg_session* s, struct seg_nn* net) {
-  if (!s || !net || s->cfg.detector != SEG_DET_SURROGATE) return SEG_E_INVAL;
-  if (s->state != State::Open || s->frames != 0) return SEG_E_STATE;
-  uint32_t b = 0, h = 0, w = 0;
-  if (seg_nn_shape(net, &b, &h, &w) != SEG_OK || h != s->cfg.height || w != s->cfg.width) return SEG_E_SHAPE;
+  if (!s || !net || s->cfg.detector == SEG_DET_PLAIN) return SEG_E_INVAL;
+  if (s->state != State::Open || s->frames != 0 || s->K != 0) return SEG_E_STATE;
+  uint32_t b = 0, h = 0, w = 0, input = 0;
+  if (seg_nn_shape(net, &b, &h, &w) != SEG_OK || seg_nn_input(net, &input) != SEG_OK) return SEG_E_INVAL;
+  if (s->cfg.detector == SEG_DET_SURROGATE &&
+      (input != SEG_NN_INPUT_FRAMES || h != s->cfg.height || w != s->cfg.width))
+    return SEG_E_SHAPE;
+  if (s->cfg.detector == SEG_DET_UNET && (input != SEG_NN_INPUT_SUMMARIES || h != 64 || w != 64))
+    return SEG_E_SHAPE;
   s->net = net;
   return SEG_OK;
 }

@@ -44,7 +44,8 @@ class Session:
         self.H, self.W = height, width
 
     def set_model(self, net) -> None:
-        """Attach a Surrogate (SEG_DET_SURROGATE sessions, before the first push)."""
+        """Attach a Surrogate (SEG_DET_SURROGATE) or a SummaryUNet of 64 x 64
+        patches (SEG_DET_UNET), before the first push."""
         abi.check(abi.lib.seg_set_model(self.handle, net.handle), "seg_set_model")
         self.net = net   # keep it alive while the session pushes
 
@@ -145,10 +146,13 @@ class Session:
 def segment_video(video: np.ndarray, block: int | None = None, net=None, **overrides) -> Session:
     """Push a host uint16 video [T, H, W] (in blocks of `block` frames) and
     finalize. Returns the finalized session. With `net` (a Surrogate) the
-    learned detector is used (events at probability >= 0.5, c_min = 2)."""
+    learned detector is used (events at probability >= 0.5, c_min = 2): a
+    Surrogate reads the frames, a SummaryUNet the summary patches."""
     T, H, W = video.shape
     if net is not None:
-        overrides = dict(dict(detector=abi.SEG_DET_SURROGATE, event_z=0.5, min_event_segs=2), **overrides)
+        from .unet import SummaryUNet
+        det = abi.SEG_DET_UNET if isinstance(net, SummaryUNet) else abi.SEG_DET_SURROGATE
+        overrides = dict(dict(detector=det, event_z=0.5, min_event_segs=2), **overrides)
     s = Session(H, W, max(T, 50), **overrides)
     if net is not None:
         s.set_model(net)

@@ -74,3 +74,67 @@ def train(steps: int = 400, batch: int = 16, lr: float = 1e-3, n_videos: int = 2
 def for_frames(net: Surrogate, height: int, width: int, device="cuda") -> Surrogate:
     """A batch-1 network for other frame sizes with the same weights."""
     return Surrogate(1, height, width, net.theta(), device)
+
+
+# ---- the paper's input: summary-image patches --------------------------------
+
+class SummaryBank:
+    """Summary pairs (S_i, T_i) of n simulated 128 x 128 x 1,000 videos (the
+    training videos of Sec. III-C: 20 pairs each), computed on the GPU by a
+    plain session, with the mask of the neurons spiking in each segment as
+    the label. Training patches are random 64 x 64 crops of the pairs."""
+
+    def __init__(self, n: int, seed0: int = 60000, device="cuda", **overrides):
+        from synth import preset
+        from synth.gpu import GpuScene
+        from . import abi
+        from .session import Session
+        self.device = torch.device(device)
+        cfg0 = preset(4, **dict(dict(height=128, width=128, frames=1000, n_neurons=8, n_overlap=2,
+                                     edge_margin=10.0), **overrides))
+        self.H, self.W = cfg0.height, cfg0.width
+        K = cfg0.frames // SEG
+        self.S = torch.empty((n * K, self.H, self.W), dtype=torch.float32, device=self.device)
+        self.T = torch.empty_like(self.S)
+        self.Y = torch.empty_like(self.S)
+        for k in range(n):
+            cfg = preset(4, **dict(dict(height=128, width=128, frames=1000, n_neurons=8, n_overlap=2,
+                                        edge_margin=10.0,
+                                        dff_reference="neuron" if k % 2 else "total"), **overrides))
+            sc = GpuScene(cfg, seed0 + k, self.device)
+            sess = Session(self.H, self.W, cfg.frames, self.device)
+            sess.push(sc.render(0, cfg.frames))
+            self.S[k * K:(k + 1) * K] = sess.segment_maps(abi.SEG_MAP_S)
+            self.T[k * K:(k + 1) * K] = sess.segment_maps(abi.SEG_MAP_T)
+            self.Y[k * K:(k + 1) * K] = torch.from_numpy(sc.truth.segment_masks(SEG).astype(np.float32))
+            sess.close()
+
+    def batch(self, rng, B):
+        st = torch.empty((B, 2, 64, 64), dtype=torch.float32, device=self.device)
+        y = torch.empty((B, 64, 64), dtype=torch.float32, device=self.device)
+        for b in range(B):
+            i = int(rng.integers(self.S.shape[0]))
+            oy, ox = int(rng.integers(self.H - 63)), int(rng.integers(self.W - 63))
+            st[b, 0] = self.S[i, oy:oy + 64, ox:ox + 64]
+            st[b, 1] = self.T[i, oy:oy + 64, ox:ox + 64]
+            y[b] = self.Y[i, oy:oy + 64, ox:ox + 64]
+        return st, y
+
+
+def train_unet(steps: int = 2000, batch: int = 32, lr: float = 1e-3, n_videos: int = 100, seed: int = 0,
+               device="cuda", log=None, bank: SummaryBank | None = None):
+    """Train a fresh summary-image U-Net; returns (SummaryUNet, losses)."""
+    from .unet import SummaryUNet, he_init as st_init
+    bank = bank or SummaryBank(n_videos, device=device)
+    net = SummaryUNet(batch, 64, 64, st_init(seed), device)
+    rng = np.random.default_rng(seed)
+    losses = []
+    t0 = time.time()
+    for s in range(steps):
+        st, y = bank.batch(rng, batch)
+        loss, _ = net.backward(st, y)
+        net.step(lr=lr)
+        losses.append(loss)
+        if log and (s % 100 == 0 or s == steps - 1):
+            log(f"step {s} loss {loss:.4f} ({time.time() - t0:.1f}s)")
+    return net, losses
