@@ -110,6 +110,108 @@ __global__ __launch_bounds__(256) void k_gemm(const TA* __restrict__ A, long lon
     }
 }
 
+// Contiguous BF16 operands (A [M][K] with K fastest, B [K][N] with N
+// fastest, rows 16-byte aligned): each thread moves 16-byte groups of 8, and
+// the next K step is loaded into registers while the current one runs on
+// MFMA. Tile MT x NT (64 x 64, or 32 x 128 for M <= 32), 4 waves of 32 x 32.
+// IMP: B is the 3 x 3 im2col matrix of the FP32 activations X [Ci][Bn][H][W]
+// (row k = c 9 + ky 3 + kx, column n = pixel), gathered from X as it is
+// loaded (W a multiple of 8, so a group of 8 pixels lies in one row).
+struct Im2col {
+  const float* X;
+  int Bn, H, W;
+};
+template <int MT, bool IMP>
+__global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, long long sam,
+                                                const uint16_t* __restrict__ B, long long sbk, Im2col ic,
+                                                float* __restrict__ C, long long ldc, int M, int N, int K,
+                                                int accumulate) {
+  constexpr int NT = 4096 / MT;
+  constexpr int NB = NT / 64;                   // 16-byte B groups per thread per K step
+  __shared__ uint16_t As[MT][GK + 8];
+  __shared__ uint16_t Bs[NT][GK + 8];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = MT == 64 ? wv >> 1 : 0, wn = MT == 64 ? wv & 1 : wv;
+  const int m0 = blockIdx.y * MT, n0 = blockIdx.x * NT;
+  // A: thread -> (row am, k group ak); B: thread -> (k row bk, n group bn + 64 j)
+  const int am = tid >> 2, ak = (tid & 3) * 8;
+  const bool a_on = am < MT;
+  const int bk = tid >> 3, bn = (tid & 7) * 8;
+  uint4 ra = make_uint4(0, 0, 0, 0), rb[NB];
+  auto load = [&](int k0) {
+    const int gm = m0 + am, gk = k0 + ak;
+    ra = (a_on && gm < M && gk < K) ? *reinterpret_cast<const uint4*>(A + gm * sam + gk) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int gkb = k0 + bk, gn = n0 + bn + 64 * j;
+      if constexpr (!IMP) {
+        rb[j] = (gkb < K && gn < N) ? *reinterpret_cast<const uint4*>(B + gkb * sbk + gn) : make_uint4(0, 0, 0, 0);
+      } else {
+        uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (gkb < K && gn < N) {
+          const int c = gkb / 9, kk = gkb - 9 * c, ky = kk / 3, kx = kk - 3 * ky;
+          const int HW = ic.H * ic.W, b = gn / HW, yx = gn - b * HW, y = yx / ic.W, x0 = yx - y * ic.W;
+          const int yy = y + ky - 1;
+          if (yy >= 0 && yy < ic.H) {
+            const float* src = ic.X + ((long long)c * ic.Bn + b) * HW + (long long)yy * ic.W;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int xx = x0 + q + kx - 1;
+              v[q] = (xx >= 0 && xx < ic.W) ? to_bf16(src[xx]) : (uint16_t)0;
+            }
+          }
+        }
+        rb[j] = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
+                           v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16));
+      }
+    }
+  };
+  f32x16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    if (a_on) *reinterpret_cast<uint4*>(&As[am][ak]) = ra;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const uint32_t w[4] = {rb[j].x, rb[j].y, rb[j].z, rb[j].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Bs[bn + 64 * j + 2 * q][bk] = (uint16_t)(w[q] & 0xffffu);
+        Bs[bn + 64 * j + 2 * q + 1][bk] = (uint16_t)(w[q] >> 16);
+      }
+    }
+    __syncthreads();
+    if (k0 + GK < K) load(k0 + GK);
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 16) {
+      const int kk = ks + (lane >> 5) * 8;
+      bf16x8 a, b;
+      const uint16_t* ap = &As[wm * 32 + (lane & 31)][kk];
+      const uint16_t* bp = &Bs[wn * 32 + (lane & 31)][kk];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        a[q] = __builtin_bit_cast(__bf16, ap[q]);
+        b[q] = __builtin_bit_cast(__bf16, bp[q]);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int col = n0 + wn * 32 + (lane & 31);
+  if (col >= N) return;
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = m0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
+      if (row < M) {
+        float* c = C + (long long)row * ldc + col;
+        *c = accumulate ? *c + acc[4 * g + r] : acc[4 * g + r];
+      }
+    }
+}
+
 // sum the split-K partials in order: C[m][n] (+)= sum_z P[z][m][n]
 __global__ void k_splitk_reduce(const float* __restrict__ P, float* __restrict__ C, long long MN, int Z,
                                 int accumulate) {
@@ -133,6 +235,33 @@ __global__ void k_im2col3(const float* __restrict__ X, uint16_t* __restrict__ co
   const int yy = y + ky - 1, xx = x + kx - 1;
   const float v = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? X[((long long)c * Bn + b) * H * W + yy * W + xx] : 0.f;
   col[i] = to_bf16(v);
+}
+
+// The same, 8 consecutive pixels of one row per thread and one 16-byte
+// store (W a multiple of 8).
+__global__ void k_im2col3_v(const float* __restrict__ X, uint16_t* __restrict__ col, int C, int Bn, int H, int W) {
+  const long long N = (long long)Bn * H * W, N8 = N / 8;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N8 * C * 9) return;
+  const long long p = (i % N8) * 8;
+  const int r = (int)(i / N8);
+  const int c = r / 9, kk = r % 9, ky = kk / 3, kx = kk % 3;
+  const int b = (int)(p / (H * W)), yx = (int)(p % (H * W)), y = yx / W, x0 = yx % W;
+  const int yy = y + ky - 1;
+  uint16_t v[8];
+  const bool row_in = yy >= 0 && yy < H;
+  const float* src = X + ((long long)c * Bn + b) * H * W + (long long)yy * W;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int xx = x0 + j + kx - 1;
+    v[j] = to_bf16(row_in && xx >= 0 && xx < W ? src[xx] : 0.f);
+  }
+  uint4 pk;
+  pk.x = v[0] | ((uint32_t)v[1] << 16);
+  pk.y = v[2] | ((uint32_t)v[3] << 16);
+  pk.z = v[4] | ((uint32_t)v[5] << 16);
+  pk.w = v[6] | ((uint32_t)v[7] << 16);
+  *reinterpret_cast<uint4*>(col + (long long)r * N + p) = pk;
 }
 
 // dX[c][b][y][x] (+)= sum_{ky,kx} dcol[c*9 + ky*3 + kx][b, y - ky + 1, x - kx + 1]
@@ -439,7 +568,19 @@ hipError_t gemm(const GemmOp& g, hipStream_t st) {
   dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT, z > 0 ? z : 1);
   float* out = z > 1 ? g.scratch : g.C;
   const int acc = z > 1 ? 0 : g.accumulate;
-  if (g.a_bf16 && g.b_bf16)
+  const bool vec = z == 1 && g.a_bf16 && g.b_bf16 && g.sak == 1 && g.sbn == 1 && g.K % 8 == 0 && g.sam % 8 == 0 &&
+                   g.sbk % 8 == 0 && g.N % 8 == 0 && ((uintptr_t)g.A & 15) == 0 && ((uintptr_t)g.B & 15) == 0;
+  if (vec) {
+    const Im2col none{nullptr, 0, 0, 0};
+    if (g.M <= 32)
+      hipLaunchKernelGGL((k_gemm_v<32, false>), dim3((g.N + 127) / 128, (g.M + 31) / 32), dim3(256), 0, st,
+                         (const uint16_t*)g.A, g.sam, (const uint16_t*)g.B, g.sbk, none, out, (long long)g.N, g.M,
+                         g.N, g.K, acc);
+    else
+      hipLaunchKernelGGL((k_gemm_v<64, false>), dim3((g.N + 63) / 64, (g.M + 63) / 64), dim3(256), 0, st,
+                         (const uint16_t*)g.A, g.sam, (const uint16_t*)g.B, g.sbk, none, out, (long long)g.N, g.M,
+                         g.N, g.K, acc);
+  } else if (g.a_bf16 && g.b_bf16)
     hipLaunchKernelGGL((k_gemm<uint16_t, uint16_t>), grid, dim3(256), 0, st, (const uint16_t*)g.A, g.sam, g.sak,
                        (const uint16_t*)g.B, g.sbk, g.sbn, out, (long long)g.N, g.M, g.N, g.K, kchunk, acc);
   else if (g.a_bf16)
@@ -460,8 +601,26 @@ hipError_t gemm(const GemmOp& g, hipStream_t st) {
 
 #define L1(kernel, n, ...) hipLaunchKernelGGL(kernel, grid1(n), dim3(256), 0, st, __VA_ARGS__)
 
+bool conv3_implicit(const uint16_t* Wb, const float* X, float* Y, int Co, int Ci, int Bn, int H, int W,
+                    hipStream_t st) {
+  const int K = Ci * 9;
+  const long long N = (long long)Bn * H * W;
+  if (W % 8 || K % 8 || ((uintptr_t)Wb & 15) || N > 0x7fffffffLL) return false;
+  const Im2col ic{X, Bn, H, W};
+  if (Co <= 32)
+    hipLaunchKernelGGL((k_gemm_v<32, true>), dim3((unsigned)((N + 127) / 128), (Co + 31) / 32), dim3(256), 0, st,
+                       Wb, (long long)K, nullptr, 0LL, ic, Y, N, Co, (int)N, K, 0);
+  else
+    hipLaunchKernelGGL((k_gemm_v<64, true>), dim3((unsigned)((N + 63) / 64), (Co + 63) / 64), dim3(256), 0, st,
+                       Wb, (long long)K, nullptr, 0LL, ic, Y, N, Co, (int)N, K, 0);
+  return true;
+}
+
 void im2col3(const float* X, uint16_t* col, int C, int Bn, int H, int W, hipStream_t st) {
-  L1(k_im2col3, (long long)C * 9 * Bn * H * W, X, col, C, Bn, H, W);
+  if (W % 8 == 0 && ((uintptr_t)col & 15) == 0)
+    L1(k_im2col3_v, (long long)C * 9 * Bn * H * W / 8, X, col, C, Bn, H, W);
+  else
+    L1(k_im2col3, (long long)C * 9 * Bn * H * W, X, col, C, Bn, H, W);
 }
 void col2im3(const float* dcol, float* dX, int C, int Bn, int H, int W, bool acc, hipStream_t st) {
   L1(k_col2im3, (long long)C * Bn * H * W, dcol, dX, C, Bn, H, W, (int)acc);
