@@ -138,6 +138,21 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
   const bool a_on = am < MT;
   const int bk = tid >> 3, bn = (tid & 7) * 8;
   uint4 ra = make_uint4(0, 0, 0, 0), rb[NB];
+  // IMP: a thread's pixel groups are fixed, so their image, row and column
+  // are found once
+  int py[NB], px[NB];
+  long long poff[NB];
+  if constexpr (IMP) {
+    const int HW = ic.H * ic.W;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int gn = n0 + bn + 64 * j;
+      const int b = gn / HW, yx = gn - b * HW;
+      py[j] = gn < N ? yx / ic.W : -(1 << 20);      // off-range groups load nothing
+      px[j] = yx - (yx / ic.W) * ic.W;
+      poff[j] = (long long)b * HW;
+    }
+  }
   auto load = [&](int k0) {
     const int gm = m0 + am, gk = k0 + ak;
     ra = (a_on && gm < M && gk < K) ? *reinterpret_cast<const uint4*>(A + gm * sam + gk) : make_uint4(0, 0, 0, 0);
@@ -148,12 +163,12 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
         rb[j] = (gkb < K && gn < N) ? *reinterpret_cast<const uint4*>(B + gkb * sbk + gn) : make_uint4(0, 0, 0, 0);
       } else {
         uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (gkb < K && gn < N) {
+        (void)gn;
+        if (gkb < K) {
           const int c = gkb / 9, kk = gkb - 9 * c, ky = kk / 3, kx = kk - 3 * ky;
-          const int HW = ic.H * ic.W, b = gn / HW, yx = gn - b * HW, y = yx / ic.W, x0 = yx - y * ic.W;
-          const int yy = y + ky - 1;
+          const int x0 = px[j], yy = py[j] + ky - 1;
           if (yy >= 0 && yy < ic.H) {
-            const float* src = ic.X + ((long long)c * ic.Bn + b) * HW + (long long)yy * ic.W;
+            const float* src = ic.X + (long long)c * ic.Bn * ic.H * ic.W + poff[j] + (long long)yy * ic.W;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
               const int xx = x0 + q + kx - 1;
