@@ -121,11 +121,13 @@ struct Im2col {
   const float* X;
   int Bn, H, W;
 };
+// bias (may be null) and relu are applied to the stored values (not with
+// accumulate), as bias_act does after an unfused product.
 template <int MT, bool IMP>
 __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, long long sam,
                                                 const uint16_t* __restrict__ B, long long sbk, Im2col ic,
                                                 float* __restrict__ C, long long ldc, int M, int N, int K,
-                                                int accumulate) {
+                                                int accumulate, const float* __restrict__ bias, int relu) {
   constexpr int NT = 4096 / MT;
   constexpr int NB = NT / 64;                   // 16-byte B groups per thread per K step
   __shared__ uint16_t As[MT][GK + 8];
@@ -222,7 +224,12 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
       const int row = m0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
       if (row < M) {
         float* c = C + (long long)row * ldc + col;
-        *c = accumulate ? *c + acc[4 * g + r] : acc[4 * g + r];
+        float v = accumulate ? *c + acc[4 * g + r] : acc[4 * g + r];
+        if (bias) {
+          v += bias[row];
+          if (relu) v = fmaxf(v, 0.f);
+        }
+        *c = v;
       }
     }
 }
@@ -590,11 +597,11 @@ hipError_t gemm(const GemmOp& g, hipStream_t st) {
     if (g.M <= 32)
       hipLaunchKernelGGL((k_gemm_v<32, false>), dim3((g.N + 127) / 128, (g.M + 31) / 32), dim3(256), 0, st,
                          (const uint16_t*)g.A, g.sam, (const uint16_t*)g.B, g.sbk, none, out, (long long)g.N, g.M,
-                         g.N, g.K, acc);
+                         g.N, g.K, acc, nullptr, 0);
     else
       hipLaunchKernelGGL((k_gemm_v<64, false>), dim3((g.N + 63) / 64, (g.M + 63) / 64), dim3(256), 0, st,
                          (const uint16_t*)g.A, g.sam, (const uint16_t*)g.B, g.sbk, none, out, (long long)g.N, g.M,
-                         g.N, g.K, acc);
+                         g.N, g.K, acc, nullptr, 0);
   } else if (g.a_bf16 && g.b_bf16)
     hipLaunchKernelGGL((k_gemm<uint16_t, uint16_t>), grid, dim3(256), 0, st, (const uint16_t*)g.A, g.sam, g.sak,
                        (const uint16_t*)g.B, g.sbk, g.sbn, out, (long long)g.N, g.M, g.N, g.K, kchunk, acc);
@@ -617,17 +624,17 @@ hipError_t gemm(const GemmOp& g, hipStream_t st) {
 #define L1(kernel, n, ...) hipLaunchKernelGGL(kernel, grid1(n), dim3(256), 0, st, __VA_ARGS__)
 
 bool conv3_implicit(const uint16_t* Wb, const float* X, float* Y, int Co, int Ci, int Bn, int H, int W,
-                    hipStream_t st) {
+                    const float* bias, bool relu, hipStream_t st) {
   const int K = Ci * 9;
   const long long N = (long long)Bn * H * W;
   if (W % 8 || K % 8 || ((uintptr_t)Wb & 15) || N > 0x7fffffffLL) return false;
   const Im2col ic{X, Bn, H, W};
   if (Co <= 32)
     hipLaunchKernelGGL((k_gemm_v<32, true>), dim3((unsigned)((N + 127) / 128), (Co + 31) / 32), dim3(256), 0, st,
-                       Wb, (long long)K, nullptr, 0LL, ic, Y, N, Co, (int)N, K, 0);
+                       Wb, (long long)K, nullptr, 0LL, ic, Y, N, Co, (int)N, K, 0, bias, (int)relu);
   else
     hipLaunchKernelGGL((k_gemm_v<64, true>), dim3((unsigned)((N + 63) / 64), (Co + 63) / 64), dim3(256), 0, st,
-                       Wb, (long long)K, nullptr, 0LL, ic, Y, N, Co, (int)N, K, 0);
+                       Wb, (long long)K, nullptr, 0LL, ic, Y, N, Co, (int)N, K, 0, bias, (int)relu);
   return true;
 }
 

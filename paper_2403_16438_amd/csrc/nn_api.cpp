@@ -246,12 +246,12 @@ hipError_t conv3(seg_nn* n, int id, const float* X, int Bn, int H, int W, float*
   const int Ci = n->P[id].cols / 9;
   const long long N = (long long)Bn * H * W;
   hipError_t e = hipSuccess;
-  if (!conv3_implicit(wbf(n, id), X, Y, n->P[id].rows, Ci, Bn, H, W, st)) {
+  if (!conv3_implicit(wbf(n, id), X, Y, n->P[id].rows, Ci, Bn, H, W, bias(n, id), relu, st)) {
     uint16_t* col = at<uint16_t>(n, n->plan.col);
     im2col3(X, col, Ci, Bn, H, W, st);
     e = gemm_wx(n, id, col, true, N, Y, st);
+    bias_act(Y, bias(n, id), n->P[id].rows, N, relu, st);
   }
-  bias_act(Y, bias(n, id), n->P[id].rows, N, relu, st);
   return e;
 }
 
