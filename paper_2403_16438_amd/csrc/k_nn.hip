@@ -234,6 +234,111 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
     }
 }
 
+// Direct 3 x 3 convolution (stride 1, zero padding 1) on MFMA, forward:
+// Y[co][b][y][x] = bias[co] + sum_{c, ky, kx} W[co][9 c + 3 ky + kx] X[c][b][y + ky - 1][x + kx - 1],
+// then ReLU when asked. A workgroup computes MT output channels x NT = 4096 / MT
+// pixels, a block of BR rows x BC columns of one image (BC = min(W, 64)).
+// Per chunk of 16 input channels it stages, as BF16 with the channel fastest,
+// the input rows y0 - 1 .. y0 + BR and columns x0 - 1 .. x0 + BC (zero outside
+// the image) and the chunk's weights, (ky, kx) then channel, copied with
+// 16-byte loads from a reordered copy kept beside the BF16 weights. A depth
+// step of 16 is then one (ky, kx) and 16 channels, and each lane's 8
+// consecutive depth values are 16 contiguous bytes in both arrays: every input
+// value is loaded and converted once per chunk instead of once per (ky, kx),
+// and the nine offsets read it from LDS.
+constexpr int HC = 16;                          // input channels per chunk
+constexpr int HX = 4224;                        // largest halo tile: 4 x 66 x 16
+// Convolution weights reordered for k_conv3_halo: Wr[chunk][co][ky 3 + kx][cl]
+// = W[co][9 (16 chunk + cl) + ky 3 + kx] (0 past Ci), so that a chunk's
+// weights of one output channel are 144 contiguous values.
+__global__ void k_conv3_reorder(const uint16_t* __restrict__ Wb, uint16_t* __restrict__ Wr, int Co, int Ci) {
+  const int nch = (Ci + HC - 1) / HC;
+  const long long total = (long long)nch * Co * 9 * HC;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int cl = (int)(i % HC), kyx = (int)((i / HC) % 9), co = (int)((i / (9 * HC)) % Co),
+            ch = (int)(i / ((long long)9 * HC * Co));
+  const int c = ch * HC + cl;
+  Wr[i] = c < Ci ? Wb[(long long)co * Ci * 9 + c * 9 + kyx] : (uint16_t)0;
+}
+
+template <int MT>
+__global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__ Wr, const float* __restrict__ X,
+                                                    const float* __restrict__ bias, int relu,
+                                                    float* __restrict__ Y, int Co, int Ci, int Bn, int H, int W,
+                                                    int BC) {
+  constexpr int NT = 4096 / MT;
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[HX];
+  __shared__ __attribute__((aligned(16))) uint16_t Ws[MT][9 * HC + 8];
+  const int BR = NT / BC, TC = BC + 2, TR = BR + 2;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = MT == 64 ? wv >> 1 : 0, wn = MT == 64 ? wv & 1 : wv;
+  const int bx = (W + BC - 1) / BC, by = (H + BR - 1) / BR;
+  const int blk = blockIdx.x, b = blk / (bx * by), rem = blk - b * bx * by;
+  const int y0 = (rem / bx) * BR, x0 = (rem % bx) * BC;
+  const int co0 = blockIdx.y * MT;
+  const long long HW = (long long)H * W;
+  // this lane's pixel and its place in the halo tile
+  const int pl = wn * 32 + (lane & 31), pr = pl / BC, pc = pl - pr * BC;
+  const int kg = (lane >> 5) * 8;
+  f32x16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  for (int c0 = 0; c0 < Ci; c0 += HC) {
+    __syncthreads();
+    // input: a thread takes 8 channels of one tile position (8 loads, each
+    // coalesced over the positions) and writes them with one 16-byte store
+    const int np = TR * TC;
+    for (int e = tid; e < 2 * np; e += 256) {
+      const int g = e / np, pos = e - g * np, r = pos / TC, cc = pos - r * TC;
+      const int y = y0 + r - 1, x = x0 + cc - 1;
+      const bool in = y >= 0 && y < H && x >= 0 && x < W;
+      const float* src = X + ((long long)(c0 + 8 * g) * Bn + b) * HW + (long long)y * W + x;
+      uint16_t v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = (in && c0 + 8 * g + q < Ci) ? to_bf16(src[(long long)q * Bn * HW]) : (uint16_t)0;
+      *reinterpret_cast<uint4*>(&Xs[pos * HC + 8 * g]) =
+          make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
+                     v[6] | ((uint32_t)v[7] << 16));
+    }
+    // weights: contiguous 144 values per output channel in the reordered copy
+    const uint16_t* wsrc = Wr + (long long)(c0 / HC) * Co * 9 * HC;
+    for (int e = tid; e < MT * 18; e += 256) {
+      const int m = e / 18, q = e - m * 18, co = co0 + m;
+      *reinterpret_cast<uint4*>(&Ws[m][8 * q]) =
+          co < Co ? *reinterpret_cast<const uint4*>(wsrc + (long long)co * 9 * HC + 8 * q) : make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kyx = 0; kyx < 9; ++kyx) {
+      const int ky = kyx / 3, kx = kyx - 3 * ky;
+      bf16x8 a, bb;
+      const uint16_t* ap = &Ws[wm * 32 + (lane & 31)][kyx * HC + kg];
+      const uint16_t* bp = &Xs[((pr + ky) * TC + pc + kx) * HC + kg];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        a[q] = __builtin_bit_cast(__bf16, ap[q]);
+        bb[q] = __builtin_bit_cast(__bf16, bp[q]);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
+    }
+  }
+  const int y = y0 + pr, x = x0 + pc;
+  if (y >= H || x >= W) return;
+  float* yp = Y + (long long)b * HW + (long long)y * W + x;
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int co = co0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
+      if (co < Co) {
+        float v = acc[4 * g + r] + bias[co];
+        if (relu) v = fmaxf(v, 0.f);
+        yp[(long long)co * Bn * HW] = v;
+      }
+    }
+}
+
 // sum the split-K partials in order: C[m][n] (+)= sum_z P[z][m][n]
 __global__ void k_splitk_reduce(const float* __restrict__ P, float* __restrict__ C, long long MN, int Z,
                                 int accumulate) {
@@ -623,8 +728,29 @@ hipError_t gemm(const GemmOp& g, hipStream_t st) {
 
 #define L1(kernel, n, ...) hipLaunchKernelGGL(kernel, grid1(n), dim3(256), 0, st, __VA_ARGS__)
 
-bool conv3_implicit(const uint16_t* Wb, const float* X, float* Y, int Co, int Ci, int Bn, int H, int W,
-                    const float* bias, bool relu, hipStream_t st) {
+void conv3_reorder(const uint16_t* Wb, uint16_t* Wr, int Co, int Ci, hipStream_t st) {
+  L1(k_conv3_reorder, (long long)((Ci + HC - 1) / HC) * Co * 9 * HC, Wb, Wr, Co, Ci);
+}
+size_t conv3_reordered_size(int Co, int Ci) { return (size_t)((Ci + HC - 1) / HC) * Co * 9 * HC; }
+
+bool conv3_implicit(const uint16_t* Wb, const uint16_t* Wr, const float* X, float* Y, int Co, int Ci, int Bn,
+                    int H, int W, const float* bias, bool relu, hipStream_t st) {
+  // direct convolution over halo tiles where a block of whole 8-aligned
+  // columns fits the tile
+  if (Wr && W % 8 == 0 && bias && (long long)Bn * H * W <= 0x7fffffffLL && ((uintptr_t)Wr & 15) == 0) {
+    const int MT = Co <= 32 ? 32 : 64, NT = 4096 / MT, BC = W < 64 ? W : 64;
+    if (NT % BC == 0 && (NT / BC + 2) * (BC + 2) * HC <= HX) {
+      const int BR = NT / BC;
+      const long long blocks = (long long)Bn * ((H + BR - 1) / BR) * ((W + BC - 1) / BC);
+      if (MT == 32)
+        hipLaunchKernelGGL(k_conv3_halo<32>, dim3((unsigned)blocks, (Co + 31) / 32), dim3(256), 0, st, Wr, X, bias,
+                           (int)relu, Y, Co, Ci, Bn, H, W, BC);
+      else
+        hipLaunchKernelGGL(k_conv3_halo<64>, dim3((unsigned)blocks, (Co + 63) / 64), dim3(256), 0, st, Wr, X, bias,
+                           (int)relu, Y, Co, Ci, Bn, H, W, BC);
+      return true;
+    }
+  }
   const int K = Ci * 9;
   const long long N = (long long)Bn * H * W;
   if (W % 8 || K % 8 || ((uintptr_t)Wb & 15) || N > 0x7fffffffLL) return false;

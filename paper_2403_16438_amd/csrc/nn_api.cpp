@@ -81,6 +81,8 @@ struct Plan {
   Buf ga1, ga2, ga3, ge1a, gcat1, gp1, ge2a, gcat2, gp2, ge3a, gb3, gz2, gd2a, gd2, gz1, gd1a, gd1, glogit;
   Buf col, dcol, splitk, lossp;
   Buf wb, grad, vel;   // BF16 weights, FP32 gradients, RMSProp state
+  Buf wr;              // 3 x 3 convolution weights reordered for the direct kernel
+  size_t wr_off[NPAR]; // element offset of each 3 x 3 layer in wr
   size_t total;
 };
 
@@ -153,6 +155,16 @@ Plan make_plan(int B, int H, int W, bool st) {
   p.lossp = take(f * ((N + 255) / 256 + 1));
   const POff po = param_offsets(st ? kPst : kP);
   p.wb = take(2 * po.total);
+  {
+    const PDef* P = st ? kPst : kP;
+    size_t at_wr = 0;
+    for (int i = 0; i < NPAR; ++i) {
+      p.wr_off[i] = at_wr;
+      if (P[i].rows > 0 && P[i].cols % 9 == 0 && i >= E1A && i != U2 && i != U1 && i != FO)
+        at_wr += (conv3_reordered_size(P[i].rows, P[i].cols / 9) + 7) / 8 * 8;
+    }
+    p.wr = take(2 * at_wr);
+  }
   p.grad = take(f * po.total);
   p.vel = take(f * po.total);
   p.total = at;
@@ -180,6 +192,14 @@ T* at(seg_nn* n, const Buf& b) {
 }
 const uint16_t* wbf(seg_nn* n, int id) { return at<uint16_t>(n, n->plan.wb) + n->po.w[id]; }
 const float* bias(seg_nn* n, int id) { return n->params + n->po.b[id]; }
+
+// refreshes the reordered copy of every 3 x 3 convolution's BF16 weights
+void reorder_conv3(seg_nn* n, hipStream_t st) {
+  for (int id = E1A; id < NPAR; ++id)
+    if (id != U2 && id != U1 && id != FO)
+      conv3_reorder(wbf(n, id), at<uint16_t>(n, n->plan.wr) + n->plan.wr_off[id], n->P[id].rows,
+                    n->P[id].cols / 9, st);
+}
 float* gw(seg_nn* n, int id) { return at<float>(n, n->plan.grad) + n->po.w[id]; }
 float* gb(seg_nn* n, int id) { return at<float>(n, n->plan.grad) + n->po.b[id]; }
 
@@ -246,7 +266,8 @@ hipError_t conv3(seg_nn* n, int id, const float* X, int Bn, int H, int W, float*
   const int Ci = n->P[id].cols / 9;
   const long long N = (long long)Bn * H * W;
   hipError_t e = hipSuccess;
-  if (!conv3_implicit(wbf(n, id), X, Y, n->P[id].rows, Ci, Bn, H, W, bias(n, id), relu, st)) {
+  const uint16_t* wr = at<uint16_t>(n, n->plan.wr) + n->plan.wr_off[id];
+  if (!conv3_implicit(wbf(n, id), wr, X, Y, n->P[id].rows, Ci, Bn, H, W, bias(n, id), relu, st)) {
     uint16_t* col = at<uint16_t>(n, n->plan.col);
     im2col3(X, col, Ci, Bn, H, W, st);
     e = gemm_wx(n, id, col, true, N, Y, st);
@@ -541,6 +562,7 @@ int seg_nn_sync_weights(seg_nn* n, void* stream) {
   if (e) return e;
   hipStream_t st = static_cast<hipStream_t>(stream);
   to_bf16_copy(n->params, at<uint16_t>(n, n->plan.wb), (long long)n->po.total, st);
+  reorder_conv3(n, st);
   if (hipMemsetAsync(at<float>(n, n->plan.vel), 0, n->po.total * 4, st) != hipSuccess) return SEG_E_DEVICE;
   return hipGetLastError() == hipSuccess ? SEG_OK : SEG_E_DEVICE;
 }
@@ -645,6 +667,7 @@ int seg_nn_step(seg_nn* n, float lr, float rho, float eps, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   rmsprop(n->params, at<float>(n, n->plan.grad), at<float>(n, n->plan.vel), at<uint16_t>(n, n->plan.wb),
           (long long)n->po.total, lr, rho, eps, st);
+  reorder_conv3(n, st);
   return hipGetLastError() == hipSuccess ? SEG_OK : SEG_E_DEVICE;
 }
 

@@ -27,11 +27,16 @@ struct GemmOp {
 hipError_t gemm(const GemmOp& g, hipStream_t st);
 
 void im2col3(const float* X, uint16_t* col, int C, int Bn, int H, int W, hipStream_t st);
-// Y [Co][Bn H W] = W [Co][Ci 9] (BF16) times the 3 x 3 im2col of X, gathered
-// from X inside the product, plus bias and ReLU; false (nothing launched) when
-// W % 8 or Ci 9 % 8 is not 0, and the caller takes the im2col + GEMM path.
-bool conv3_implicit(const uint16_t* Wb, const float* X, float* Y, int Co, int Ci, int Bn, int H, int W,
-                    const float* bias, bool relu, hipStream_t st);
+// Y [Co][Bn H W] = W [Co][Ci 9] (BF16) times the 3 x 3 im2col of X, plus bias
+// and ReLU, without an im2col matrix: a direct convolution over LDS halo
+// tiles (Wr: the weights reordered by conv3_reorder), else the product that
+// gathers the im2col inside; false (nothing launched) when neither applies
+// (W % 8 or Ci 9 % 8 not 0), and the caller takes the im2col + GEMM path.
+bool conv3_implicit(const uint16_t* Wb, const uint16_t* Wr, const float* X, float* Y, int Co, int Ci, int Bn,
+                    int H, int W, const float* bias, bool relu, hipStream_t st);
+// Wr [ceil(Ci / 16)][Co][9][16] from W [Co][Ci 9] (zero past Ci)
+void conv3_reorder(const uint16_t* Wb, uint16_t* Wr, int Co, int Ci, hipStream_t st);
+size_t conv3_reordered_size(int Co, int Ci);
 void col2im3(const float* dcol, float* dX, int C, int Bn, int H, int W, bool acc, hipStream_t st);
 void tnorm(const uint16_t* frames, float* out, int Bn, int L, long long HW, hipStream_t st);
 void im2col1(const float* in, uint16_t* col, int C, int Tin, int Tout, int KT, int S, int P, long long N,
