@@ -114,16 +114,25 @@ __global__ __launch_bounds__(256) void k_gemm(const TA* __restrict__ A, long lon
 // fastest, rows 16-byte aligned): each thread moves 16-byte groups of 8, and
 // the next K step is loaded into registers while the current one runs on
 // MFMA. Tile MT x NT (64 x 64, or 32 x 128 for M <= 32), 4 waves of 32 x 32.
-// IMP: B is the 3 x 3 im2col matrix of the FP32 activations X [Ci][Bn][H][W]
-// (row k = c 9 + ky 3 + kx, column n = pixel), gathered from X as it is
-// loaded (W a multiple of 8, so a group of 8 pixels lies in one row).
+// The B operand by MODE:
+//   GV_BF16   B itself;
+//   GV_IM2COL the 3 x 3 im2col matrix of the FP32 activations X [Ci][Bn][H][W]
+//             (row k = c 9 + ky 3 + kx, column n = pixel), gathered from X as
+//             it is loaded (W a multiple of 8, so a group of 8 pixels lies in
+//             one row);
+//   GV_UP     FP32 X [K][N] (row stride sbk) rounded to BF16 as it is loaded,
+//             for the transposed 2 x 2 convolution: row 4 co + 2 a + e of the
+//             product, plus bias[co], is stored to C at channel co, pixel
+//             (2 y + a, 2 x + e) of an image of 2 H x 2 W (X's pixels H x W),
+//             so the product lands directly in the concatenation buffer.
+enum { GV_BF16 = 0, GV_IM2COL = 1, GV_UP = 2 };
 struct Im2col {
   const float* X;
   int Bn, H, W;
 };
 // bias (may be null) and relu are applied to the stored values (not with
 // accumulate), as bias_act does after an unfused product.
-template <int MT, bool IMP>
+template <int MT, int MODE>
 __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, long long sam,
                                                 const uint16_t* __restrict__ B, long long sbk, Im2col ic,
                                                 float* __restrict__ C, long long ldc, int M, int N, int K,
@@ -140,11 +149,11 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
   const bool a_on = am < MT;
   const int bk = tid >> 3, bn = (tid & 7) * 8;
   uint4 ra = make_uint4(0, 0, 0, 0), rb[NB];
-  // IMP: a thread's pixel groups are fixed, so their image, row and column
-  // are found once
+  // MODE 1: a thread's pixel groups are fixed, so their image, row and
+  // column are found once
   int py[NB], px[NB];
   long long poff[NB];
-  if constexpr (IMP) {
+  if constexpr (MODE == GV_IM2COL) {
     const int HW = ic.H * ic.W;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
@@ -161,8 +170,17 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int gkb = k0 + bk, gn = n0 + bn + 64 * j;
-      if constexpr (!IMP) {
+      if constexpr (MODE == GV_BF16) {
         rb[j] = (gkb < K && gn < N) ? *reinterpret_cast<const uint4*>(B + gkb * sbk + gn) : make_uint4(0, 0, 0, 0);
+      } else if constexpr (MODE == GV_UP) {
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gkb < K && gn < N) {
+          const float4* src = reinterpret_cast<const float4*>(ic.X + (long long)gkb * sbk + gn);
+          const float4 lo = src[0], hi = src[1];
+          v = make_uint4(to_bf16(lo.x) | ((uint32_t)to_bf16(lo.y) << 16), to_bf16(lo.z) | ((uint32_t)to_bf16(lo.w) << 16),
+                         to_bf16(hi.x) | ((uint32_t)to_bf16(hi.y) << 16), to_bf16(hi.z) | ((uint32_t)to_bf16(hi.w) << 16));
+        }
+        rb[j] = v;
       } else {
         uint16_t v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         (void)gn;
@@ -217,6 +235,22 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
   }
   const int col = n0 + wn * 32 + (lane & 31);
   if (col >= N) return;
+  if constexpr (MODE == GV_UP) {
+    // row 4 co + 2 a + e of pixel (b, y, x) lands on (b, 2 y + a, 2 x + e) of channel co
+    const int hw = ic.H * ic.W, b = col / hw, yx = col - b * hw, y = yx / ic.W, x = yx - y * ic.W;
+    float* base = C + (long long)b * 4 * hw + (long long)(2 * y) * (2 * ic.W) + 2 * x;
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
+        if (row < M) {
+          const int co = row >> 2, a = (row >> 1) & 1, e = row & 1;
+          base[(long long)co * ic.Bn * 4 * hw + a * 2 * ic.W + e] = acc[4 * g + r] + bias[co];
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
@@ -284,31 +318,82 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   f32x16 acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  // Staging: a thread takes 8 channels of a tile position (8 loads, each
+  // coalesced over the positions; one 16-byte LDS store) and 16-byte groups
+  // of the reordered weights. With 64-row tiles the next chunk's loads are
+  // issued before the current chunk's MFMAs and converted only when stored;
+  // with 32-row tiles (three input items per thread) the registers that takes
+  // cost more occupancy than the overlap gains, so each chunk is loaded and
+  // stored in turn.
+  const int np = TR * TC;
+  constexpr bool PF = MT == 64;
+  constexpr int XI = 2, WI = (MT * 18 + 255) / 256;   // prefetch: 2 np <= 512 items
+  float xv[XI][8];
+  uint4 wv4[WI];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int j = 0; j < XI; ++j) {
+      const int e = tid + 256 * j;
+      const int g = e >= np ? 1 : 0, pos = e - g * np, r = pos / TC, cc = pos - r * TC;
+      const int y = y0 + r - 1, x = x0 + cc - 1;
+      const bool in = e < 2 * np && y >= 0 && y < H && x >= 0 && x < W;
+      const float* src = X + ((long long)(c0 + 8 * g) * Bn + b) * HW + (long long)y * W + x;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xv[j][q] = (in && c0 + 8 * g + q < Ci) ? src[(long long)q * Bn * HW] : 0.f;
+    }
+    const uint16_t* wsrc = Wr + (long long)(c0 / HC) * Co * 9 * HC;
+#pragma unroll
+    for (int j = 0; j < WI; ++j) {
+      const int e = tid + 256 * j, m = e / 18, q = e - m * 18, co = co0 + m;
+      wv4[j] = (e < MT * 18 && co < Co) ? *reinterpret_cast<const uint4*>(wsrc + (long long)co * 9 * HC + 8 * q)
+                                         : make_uint4(0, 0, 0, 0);
+    }
+  };
+  if constexpr (PF) load(0);
   for (int c0 = 0; c0 < Ci; c0 += HC) {
     __syncthreads();
-    // input: a thread takes 8 channels of one tile position (8 loads, each
-    // coalesced over the positions) and writes them with one 16-byte store
-    const int np = TR * TC;
-    for (int e = tid; e < 2 * np; e += 256) {
-      const int g = e / np, pos = e - g * np, r = pos / TC, cc = pos - r * TC;
-      const int y = y0 + r - 1, x = x0 + cc - 1;
-      const bool in = y >= 0 && y < H && x >= 0 && x < W;
-      const float* src = X + ((long long)(c0 + 8 * g) * Bn + b) * HW + (long long)y * W + x;
-      uint16_t v[8];
+    if constexpr (!PF) {
+      for (int e = tid; e < 2 * np; e += 256) {
+        const int g = e >= np ? 1 : 0, pos = e - g * np, r = pos / TC, cc = pos - r * TC;
+        const int y = y0 + r - 1, x = x0 + cc - 1;
+        const bool in = y >= 0 && y < H && x >= 0 && x < W;
+        const float* src = X + ((long long)(c0 + 8 * g) * Bn + b) * HW + (long long)y * W + x;
+        uint16_t v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = (in && c0 + 8 * g + q < Ci) ? to_bf16(src[(long long)q * Bn * HW]) : (uint16_t)0;
-      *reinterpret_cast<uint4*>(&Xs[pos * HC + 8 * g]) =
-          make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
-                     v[6] | ((uint32_t)v[7] << 16));
-    }
-    // weights: contiguous 144 values per output channel in the reordered copy
-    const uint16_t* wsrc = Wr + (long long)(c0 / HC) * Co * 9 * HC;
-    for (int e = tid; e < MT * 18; e += 256) {
-      const int m = e / 18, q = e - m * 18, co = co0 + m;
-      *reinterpret_cast<uint4*>(&Ws[m][8 * q]) =
-          co < Co ? *reinterpret_cast<const uint4*>(wsrc + (long long)co * 9 * HC + 8 * q) : make_uint4(0, 0, 0, 0);
+        for (int q = 0; q < 8; ++q)
+          v[q] = (in && c0 + 8 * g + q < Ci) ? to_bf16(src[(long long)q * Bn * HW]) : (uint16_t)0;
+        *reinterpret_cast<uint4*>(&Xs[pos * HC + 8 * g]) =
+            make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
+                       v[6] | ((uint32_t)v[7] << 16));
+      }
+      const uint16_t* wsrc = Wr + (long long)(c0 / HC) * Co * 9 * HC;
+      for (int e = tid; e < MT * 18; e += 256) {
+        const int m = e / 18, q = e - m * 18, co = co0 + m;
+        *reinterpret_cast<uint4*>(&Ws[m][8 * q]) =
+            co < Co ? *reinterpret_cast<const uint4*>(wsrc + (long long)co * 9 * HC + 8 * q) : make_uint4(0, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < XI; ++j) {
+        const int e = tid + 256 * j;
+        if (e < 2 * np) {
+          const int g = e >= np ? 1 : 0, pos = e - g * np;
+          uint16_t v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = to_bf16(xv[j][q]);
+          *reinterpret_cast<uint4*>(&Xs[pos * HC + 8 * g]) =
+              make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
+                         v[6] | ((uint32_t)v[7] << 16));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < WI; ++j) {
+        const int e = tid + 256 * j;
+        if (e < MT * 18) *reinterpret_cast<uint4*>(&Ws[e / 18][8 * (e % 18)]) = wv4[j];
+      }
     }
     __syncthreads();
+    if (PF && c0 + HC < Ci) load(c0 + HC);
 #pragma unroll
     for (int kyx = 0; kyx < 9; ++kyx) {
       const int ky = kyx / 3, kx = kyx - 3 * ky;
@@ -337,6 +422,26 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
         yp[(long long)co * Bn * HW] = v;
       }
     }
+}
+
+// 1 x 1 convolution to one output channel plus its bias, four pixels per
+// thread: Y[n] = bias + sum_c W[c] X[c][n], both operands rounded to BF16 as
+// in the products, FP32 accumulation in channel order.
+__global__ void k_conv1_out(const uint16_t* __restrict__ Wb, const float* __restrict__ X,
+                            const float* __restrict__ bias, float* __restrict__ Y, int C, long long N) {
+  const long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i >= N) return;
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int c = 0; c < C; ++c) {
+    const float w = from_bf16(Wb[c]);
+    const float4 x = *reinterpret_cast<const float4*>(X + (long long)c * N + i);
+    s.x = fmaf(w, from_bf16(to_bf16(x.x)), s.x);
+    s.y = fmaf(w, from_bf16(to_bf16(x.y)), s.y);
+    s.z = fmaf(w, from_bf16(to_bf16(x.z)), s.z);
+    s.w = fmaf(w, from_bf16(to_bf16(x.w)), s.w);
+  }
+  const float b = bias[0];
+  *reinterpret_cast<float4*>(Y + i) = make_float4(s.x + b, s.y + b, s.z + b, s.w + b);
 }
 
 // sum the split-K partials in order: C[m][n] (+)= sum_z P[z][m][n]
@@ -700,11 +805,11 @@ hipError_t gemm(const GemmOp& g, hipStream_t st) {
   if (vec) {
     const Im2col none{nullptr, 0, 0, 0};
     if (g.M <= 32)
-      hipLaunchKernelGGL((k_gemm_v<32, false>), dim3((g.N + 127) / 128, (g.M + 31) / 32), dim3(256), 0, st,
+      hipLaunchKernelGGL((k_gemm_v<32, GV_BF16>), dim3((g.N + 127) / 128, (g.M + 31) / 32), dim3(256), 0, st,
                          (const uint16_t*)g.A, g.sam, (const uint16_t*)g.B, g.sbk, none, out, (long long)g.N, g.M,
                          g.N, g.K, acc, nullptr, 0);
     else
-      hipLaunchKernelGGL((k_gemm_v<64, false>), dim3((g.N + 63) / 64, (g.M + 63) / 64), dim3(256), 0, st,
+      hipLaunchKernelGGL((k_gemm_v<64, GV_BF16>), dim3((g.N + 63) / 64, (g.M + 63) / 64), dim3(256), 0, st,
                          (const uint16_t*)g.A, g.sam, (const uint16_t*)g.B, g.sbk, none, out, (long long)g.N, g.M,
                          g.N, g.K, acc, nullptr, 0);
   } else if (g.a_bf16 && g.b_bf16)
@@ -739,7 +844,8 @@ bool conv3_implicit(const uint16_t* Wb, const uint16_t* Wr, const float* X, floa
   // columns fits the tile
   if (Wr && W % 8 == 0 && bias && (long long)Bn * H * W <= 0x7fffffffLL && ((uintptr_t)Wr & 15) == 0) {
     const int MT = Co <= 32 ? 32 : 64, NT = 4096 / MT, BC = W < 64 ? W : 64;
-    if (NT % BC == 0 && (NT / BC + 2) * (BC + 2) * HC <= HX) {
+    const int np = (NT / BC + 2) * (BC + 2);
+    if (NT % BC == 0 && np * HC <= HX && (MT == 32 || 2 * np <= 512)) {
       const int BR = NT / BC;
       const long long blocks = (long long)Bn * ((H + BR - 1) / BR) * ((W + BC - 1) / BC);
       if (MT == 32)
@@ -756,11 +862,28 @@ bool conv3_implicit(const uint16_t* Wb, const uint16_t* Wr, const float* X, floa
   if (W % 8 || K % 8 || ((uintptr_t)Wb & 15) || N > 0x7fffffffLL) return false;
   const Im2col ic{X, Bn, H, W};
   if (Co <= 32)
-    hipLaunchKernelGGL((k_gemm_v<32, true>), dim3((unsigned)((N + 127) / 128), (Co + 31) / 32), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_gemm_v<32, GV_IM2COL>), dim3((unsigned)((N + 127) / 128), (Co + 31) / 32), dim3(256), 0, st,
                        Wb, (long long)K, nullptr, 0LL, ic, Y, N, Co, (int)N, K, 0, bias, (int)relu);
   else
-    hipLaunchKernelGGL((k_gemm_v<64, true>), dim3((unsigned)((N + 63) / 64), (Co + 63) / 64), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_gemm_v<64, GV_IM2COL>), dim3((unsigned)((N + 63) / 64), (Co + 63) / 64), dim3(256), 0, st,
                        Wb, (long long)K, nullptr, 0LL, ic, Y, N, Co, (int)N, K, 0, bias, (int)relu);
+  return true;
+}
+
+bool up_direct(const uint16_t* Wb, const float* X, const float* bias, float* Y, int Co, int Ci, int Bn, int h,
+               int w, hipStream_t st) {
+  const long long N = (long long)Bn * h * w;
+  if (N % 8 || Ci % 8 || N > 0x7fffffffLL || ((uintptr_t)Wb & 15) || ((uintptr_t)X & 15)) return false;
+  const Im2col ic{X, Bn, h, w};
+  const int M = 4 * Co;
+  hipLaunchKernelGGL((k_gemm_v<64, GV_UP>), dim3((unsigned)((N + 63) / 64), (M + 63) / 64), dim3(256), 0, st, Wb,
+                     (long long)Ci, nullptr, N, ic, Y, 0LL, M, (int)N, Ci, 0, bias, 0);
+  return true;
+}
+
+bool conv1_out(const uint16_t* Wb, const float* X, const float* bias, float* Y, int C, long long N, hipStream_t st) {
+  if (N % 4 || ((uintptr_t)X & 15) || ((uintptr_t)Y & 15)) return false;
+  L1(k_conv1_out, N / 4, Wb, X, bias, Y, C, N);
   return true;
 }
 

@@ -347,22 +347,28 @@ hipError_t forward(seg_nn* n, const uint16_t* frames, const float* stin, int Bn,
   chk(conv3(n, E3B, e3a, Bn, H / 4, W / 4, b3, true, st));
   // decoder
   float* z2 = at<float>(n, p.z2);
-  chk(gemm_wx(n, U2, b3, false, N4, z2, st));
-  up_scatter(z2, bias(n, U2), cat2, 64, Bn, H / 4, W / 4, st);
+  if (!up_direct(wbf(n, U2), b3, bias(n, U2), cat2, 64, 128, Bn, H / 4, W / 4, st)) {
+    chk(gemm_wx(n, U2, b3, false, N4, z2, st));
+    up_scatter(z2, bias(n, U2), cat2, 64, Bn, H / 4, W / 4, st);
+  }
   float* d2a = at<float>(n, p.d2a);
   float* d2 = at<float>(n, p.d2);
   chk(conv3(n, D2A, cat2, Bn, H / 2, W / 2, d2a, true, st));
   chk(conv3(n, D2B, d2a, Bn, H / 2, W / 2, d2, true, st));
   float* z1 = at<float>(n, p.z1);
-  chk(gemm_wx(n, U1, d2, false, N2, z1, st));
-  up_scatter(z1, bias(n, U1), cat1, 32, Bn, H / 2, W / 2, st);
+  if (!up_direct(wbf(n, U1), d2, bias(n, U1), cat1, 32, 64, Bn, H / 2, W / 2, st)) {
+    chk(gemm_wx(n, U1, d2, false, N2, z1, st));
+    up_scatter(z1, bias(n, U1), cat1, 32, Bn, H / 2, W / 2, st);
+  }
   float* d1a = at<float>(n, p.d1a);
   float* d1 = at<float>(n, p.d1);
   chk(conv3(n, D1A, cat1, Bn, H, W, d1a, true, st));
   chk(conv3(n, D1B, d1a, Bn, H, W, d1, true, st));
   float* logit = at<float>(n, p.logit);
-  chk(gemm_wx(n, FO, d1, false, N, logit, st));
-  bias_act(logit, bias(n, FO), 1, N, false, st);
+  if (!conv1_out(wbf(n, FO), d1, bias(n, FO), logit, n->P[FO].cols, N, st)) {
+    chk(gemm_wx(n, FO, d1, false, N, logit, st));
+    bias_act(logit, bias(n, FO), 1, N, false, st);
+  }
   chk(hipGetLastError());
   return e;
 }

@@ -34,6 +34,16 @@ void im2col3(const float* X, uint16_t* col, int C, int Bn, int H, int W, hipStre
 // (W % 8 or Ci 9 % 8 not 0), and the caller takes the im2col + GEMM path.
 bool conv3_implicit(const uint16_t* Wb, const uint16_t* Wr, const float* X, float* Y, int Co, int Ci, int Bn,
                     int H, int W, const float* bias, bool relu, hipStream_t st);
+// Transposed 2 x 2 convolution, stride 2, with its bias, written straight to
+// channels 0 .. Co - 1 of Y [.][Bn][2 h][2 w]:
+// Y[co][b][2 y + a][2 x + e] = bias[co] + sum_c W[4 co + 2 a + e][c] X[c][b][y][x]
+// (BF16 operands, FP32 accumulation). False (nothing launched) when Bn h w or
+// Ci is not a multiple of 8 or W, X are not 16-byte aligned.
+bool up_direct(const uint16_t* Wb, const float* X, const float* bias, float* Y, int Co, int Ci, int Bn, int h,
+               int w, hipStream_t st);
+// Y [N] = bias[0] + W [1][C] X [C][N] (BF16 operands, FP32 accumulation);
+// false (nothing launched) when N % 4 or X, Y are not 16-byte aligned.
+bool conv1_out(const uint16_t* Wb, const float* X, const float* bias, float* Y, int C, long long N, hipStream_t st);
 // Wr [ceil(Ci / 16)][Co][9][16] from W [Co][Ci 9] (zero past Ci)
 void conv3_reorder(const uint16_t* Wb, uint16_t* Wr, int Co, int Ci, hipStream_t st);
 size_t conv3_reordered_size(int Co, int Ci);
