@@ -36,12 +36,9 @@ namespace seg {
 namespace {
 
 constexpr int CT = 1024;
-constexpr int CW = CT / 64;   // 16 waves: the MFMA phases assign work by wave
+constexpr int CW = CT / 64;   // 16 waves
+constexpr int CV = CT - 64;   // waves 0..14 of the HALS product phases (wave 15: Gram)
 constexpr int R8 = kMaxRank;
-
-// FP64 MFMA 16x16x4: lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16)
-// and holds D(4 j + l / 16, l % 16) in element j.
-typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double wsum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -57,6 +54,48 @@ __device__ __forceinline__ void pair_of(int k, int& n1, int& n2) {
     ++n1;
   }
   n2 = n1 + k;
+}
+
+// Gram matrix X^T X of the first NR columns of X [len][R8] (LDS), by the 64
+// lanes of one wave: lane (chunk q, column n1) of QG = 64 / NR row chunks
+// sums its chunk for all n2 into part[(q NR + n1) R8 + n2] ...
+template <int NR>
+__device__ __forceinline__ void gram_part(const double* X, int len, int lane, double* part) {
+  constexpr int QG = 64 / NR;
+  if (lane >= QG * NR) return;
+  const int q = lane / NR, n1 = lane - q * NR;
+  const int span = (len + QG - 1) / QG, j1 = min(len, (q + 1) * span);
+  double s0[NR], s1[NR];
+#pragma unroll
+  for (int n = 0; n < NR; ++n) s0[n] = s1[n] = 0.0;
+  int j = q * span;
+  for (; j + 1 < j1; j += 2) {
+    const double x0 = X[j * R8 + n1], x1 = X[(j + 1) * R8 + n1];
+#pragma unroll
+    for (int n = 0; n < NR; ++n) {
+      s0[n] = fma(x0, X[j * R8 + n], s0[n]);
+      s1[n] = fma(x1, X[(j + 1) * R8 + n], s1[n]);
+    }
+  }
+  if (j < j1) {
+    const double x0 = X[j * R8 + n1];
+#pragma unroll
+    for (int n = 0; n < NR; ++n) s0[n] = fma(x0, X[j * R8 + n], s0[n]);
+  }
+#pragma unroll
+  for (int n = 0; n < NR; ++n) part[(q * NR + n1) * R8 + n] = s0[n] + s1[n];
+}
+
+// ... and entry k = n1 NR + n2 of the total, chunks added in order (chunks
+// past the data hold zeros)
+template <int NR>
+__device__ __forceinline__ double gram_total(int len, int k, const double* part) {
+  constexpr int QG = 64 / NR;
+  const int n1 = k / NR, n2 = k - n1 * NR;
+  const int span = (len + QG - 1) / QG, used = (len + span - 1) / span;
+  double v = part[n1 * R8 + n2];
+  for (int q = 1; q < used; ++q) v += part[(q * NR + n1) * R8 + n2];
+  return v;
 }
 
 __device__ double block_max(double v, double* red) {
@@ -144,11 +183,10 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
   __shared__ double red[CW];
   __shared__ int redi[CW];
   __shared__ double gF[R8 * R8], gA[R8 * R8];
-  __shared__ double red2[CT];   // Gram chunk sums (chunks x pairs <= CT)
+  __shared__ double gpart[64 * R8];   // Gram chunk sums (64 lanes x R8)
   __shared__ int picks[R8];
   __shared__ int flag;
   const int g = blockIdx.x, t = threadIdx.x;
-  const int wv = t >> 6, lr = t & 15, lk = (t >> 4) & 3;   // wave, MFMA lane row / k
   const int c = s.wg_comp[g];
   const int w0 = s.wg_base[c], nw = s.wg_n[c], r = g - w0;
   const int off = a.coff[c], Mc = a.coff[c + 1] - off;
@@ -323,32 +361,54 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
       constexpr int NR = decltype(rank)::value;
       constexpr int NP = NR * (NR + 1) / 2;
       double* FtP = scr;                    // [NR][K] totals (after the meeting)
-      const int nt = (K + 15) / 16;         // 16-segment tiles of F^T P
       for (int sweep = -1; sweep < a.sweeps; ++sweep) {
-        // ---- partial F^T P (tiles 0 .. nt-1) and F^T F (tile nt) over own
-        // rows on FP64 MFMA, written straight to this workgroup's slot
+        // ---- partial F^T P and F^T F over own rows (FP64, fixed order),
+        // written to this workgroup's slot. Waves 0..14: thread (row chunk
+        // q, segment i) sums its rows for all NR columns of F. Wave 15: F^T
+        // F, lane (row chunk q, column n1). Chunks are then added in order.
         double* xs = slot(r, ex);
-        for (int ti = wv; ti <= nt; ti += CW) {
-          const bool gram = ti == nt;
-          const int i = ti * 16 + lr;
-          d4 acc = {0.0, 0.0, 0.0, 0.0};
-          for (int m0 = 0; m0 < ml; m0 += 4) {
-            const int m = m0 + lk;
-            const double fv = m < ml && lr < NR ? F[m * R8 + lr] : 0.0;
-            const double pv = gram ? fv : (m < ml && i < K ? (double)Pl[m * Kp + i] : 0.0);
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fv, pv, acc, 0, 0, 0);
-          }
+        {
+          const int QC = max(1, min(min(CV / K, 8), s.scr / (K * NR)));
+          const int rows = (ml + QC - 1) / QC;
+          if (t < CV) {
+            for (int e = t; e < QC * K; e += CV) {
+              const int q = e / K, i = e - q * K;
+              const int m1 = min(ml, (q + 1) * rows);
+              double s0[NR], s1[NR];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int n = 4 * j + lk;
-            if (n < NR) {
-              if (gram) {
-                if (lr < NR) put(xs + R8 * K + n * R8 + lr, acc[j]);
-              } else if (i < K) {
-                put(xs + (size_t)n * K + i, acc[j]);
+              for (int n = 0; n < NR; ++n) s0[n] = s1[n] = 0.0;
+              int m = q * rows;
+              for (; m + 1 < m1; m += 2) {
+                const double p0 = (double)Pl[m * Kp + i], p1 = (double)Pl[(m + 1) * Kp + i];
+#pragma unroll
+                for (int n = 0; n < NR; ++n) {
+                  s0[n] = fma(F[m * R8 + n], p0, s0[n]);
+                  s1[n] = fma(F[(m + 1) * R8 + n], p1, s1[n]);
+                }
+              }
+              if (m < m1) {
+                const double p0 = (double)Pl[m * Kp + i];
+#pragma unroll
+                for (int n = 0; n < NR; ++n) s0[n] = fma(F[m * R8 + n], p0, s0[n]);
+              }
+#pragma unroll
+              for (int n = 0; n < NR; ++n) {
+                if (QC == 1) put(xs + n * K + i, s0[n] + s1[n]);
+                else scr[(size_t)e * NR + n] = s0[n] + s1[n];
               }
             }
+          } else {
+            gram_part<NR>(F, ml, t - CV, gpart);
           }
+          __syncthreads();
+          if (QC > 1)
+            for (int o = t; o < NR * K; o += CT) {
+              const int n = o / K, i = o - n * K;
+              double v = scr[(size_t)i * NR + n];
+              for (int q = 1; q < QC; ++q) v += scr[((size_t)q * K + i) * NR + n];
+              put(xs + o, v);
+            }
+          if (t < NR * NR) put(xs + R8 * K + (t / NR) * R8 + t % NR, gram_total<NR>(ml, t, gpart));
         }
         if (!meet(arrivals, abandoned, error, (ex + 1) * (unsigned)nw, s.limit, &flag)) return false;
         // ---- totals over the component's workgroups (slot order) into LDS
@@ -393,60 +453,49 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
         }
         __syncthreads();
         if (sweep < 0) continue;
-        // ---- P A^T of own rows (16-row tiles x KS segment parts, waves
-        // 0..11) and A A^T (four segment parts, waves 12..15) on FP64 MFMA
+        // ---- P A^T of own rows and A A^T (FP64, fixed order). Waves
+        // 0..14: thread (segment chunk q, own row m) sums its segments for
+        // all NR rows of A. Wave 15: A A^T, lane (segment chunk q, row n1),
+        // chunked by K and NR only, so identical in every workgroup. Chunks
+        // are then added in order.
         {
-          const int rt = (ml + 15) / 16;
-          const int KS = 12 / rt;
-          if (wv < 12) {
-            if (wv < rt * KS) {
-              const int rtile = wv / KS, ks = wv - rtile * KS;
-              const int kc4 = ((K + KS - 1) / KS + 3) & ~3;
-              const int i0 = ks * kc4, i1 = min(K, i0 + kc4);
-              const int m = rtile * 16 + lr;
-              d4 acc = {0.0, 0.0, 0.0, 0.0};
-              for (int ib = i0; ib < i1; ib += 4) {
-                const int i = ib + lk;
-                const double pv = m < ml && i < i1 ? (double)Pl[m * Kp + i] : 0.0;
-                const double av = i < i1 && lr < NR ? A[i * R8 + lr] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pv, av, acc, 0, 0, 0);
+          // at most 16 chunks: their in-order sum is a chain of dependent adds
+          const int QK = max(1, min(min(CV / ml, 16), s.scr / (ml * NR)));
+          const int seg = (K + QK - 1) / QK;
+          if (t < CV) {
+            for (int e = t; e < QK * ml; e += CV) {
+              const int q = e / ml, m = e - q * ml;
+              const int i1 = min(K, (q + 1) * seg);
+              double s0[NR], s1[NR];
+#pragma unroll
+              for (int n = 0; n < NR; ++n) s0[n] = s1[n] = 0.0;
+              int i = q * seg;
+              for (; i + 1 < i1; i += 2) {
+                const double p0 = (double)Pl[m * Kp + i], p1 = (double)Pl[m * Kp + i + 1];
+#pragma unroll
+                for (int n = 0; n < NR; ++n) {
+                  s0[n] = fma(p0, A[i * R8 + n], s0[n]);
+                  s1[n] = fma(p1, A[(i + 1) * R8 + n], s1[n]);
+                }
+              }
+              if (i < i1) {
+                const double p0 = (double)Pl[m * Kp + i];
+#pragma unroll
+                for (int n = 0; n < NR; ++n) s0[n] = fma(p0, A[i * R8 + n], s0[n]);
               }
 #pragma unroll
-              for (int j = 0; j < 4; ++j)
-                if (lr < R8) scr[((size_t)wv * 16 + 4 * j + lk) * R8 + lr] = acc[j];
+              for (int n = 0; n < NR; ++n) scr[(size_t)e * NR + n] = s0[n] + s1[n];
             }
           } else {
-            const int ka = wv - 12;
-            const int kc4 = ((K + 3) / 4 + 3) & ~3;
-            const int i0 = ka * kc4, i1 = min(K, i0 + kc4);
-            d4 acc = {0.0, 0.0, 0.0, 0.0};
-            for (int ib = i0; ib < i1; ib += 4) {
-              const int i = ib + lk;
-              const double av = i < i1 && lr < NR ? A[i * R8 + lr] : 0.0;
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, av, acc, 0, 0, 0);
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int n1 = 4 * j + lk;
-              if (n1 < R8 && lr < R8) red2[ka * 64 + n1 * R8 + lr] = acc[j];
-            }
+            gram_part<NR>(A, K, t - CV, gpart);
           }
           __syncthreads();
-          if (t < NP) {   // A A^T: the four parts in order, upper triangle mirrored
-            int n1, n2;
-            pair_of<NR>(t, n1, n2);
-            const double v = ((red2[n1 * R8 + n2] + red2[64 + n1 * R8 + n2]) + red2[128 + n1 * R8 + n2]) +
-                             red2[192 + n1 * R8 + n2];
-            gA[n1 * R8 + n2] = v;
-            gA[n2 * R8 + n1] = v;
-          }
-          for (int e = t; e < ml * NR; e += CT) {   // P A^T of own rows: parts in order
-            const int m = e / NR, n = e - m * NR;
-            const int rtile = m >> 4, mm = m & 15;
-            double v = 0.0;
-            for (int ks = 0; ks < KS; ++ks) v += scr[((size_t)(rtile * KS + ks) * 16 + mm) * R8 + n];
+          for (int e = t; e < ml * NR; e += CT) {   // P A^T: chunks in order
+            double v = scr[e];
+            for (int q = 1; q < QK; ++q) v += scr[(size_t)q * ml * NR + e];
             GP[e] = v;
           }
+          if (t < NR * NR) gA[(t / NR) * R8 + t % NR] = gram_total<NR>(K, t, gpart);
           __syncthreads();
         }
         // ---- the own F rows (columns of F in order)
@@ -541,7 +590,7 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
     return false;
   if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || clock_khz <= 0)
     return false;
-  const size_t budget = max_lds > 16384 ? (size_t)max_lds - 12288 : 0;  // static LDS ~11 KB
+  const size_t budget = max_lds > 16384 ? (size_t)max_lds - 12288 : 0;  // static LDS ~1.3 KB, with room to spare
   const int K = a.K;
   const int ncomp = a.ncomp;
   if (K < 1 || ncomp < 1) return false;
