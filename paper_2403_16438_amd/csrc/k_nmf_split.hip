@@ -86,15 +86,32 @@ __device__ __forceinline__ void gram_part(const double* X, int len, int lane, do
   for (int n = 0; n < NR; ++n) part[(q * NR + n1) * R8 + n] = s0[n] + s1[n];
 }
 
-// ... and entry k = n1 NR + n2 of the total, chunks added in order (chunks
-// past the data hold zeros)
+// ... and entry k = n1 NR + n2 of the total, all QG chunks added in order
+// (chunks past the data hold zeros); the bound is a constant, so the loads
+// are issued ahead of the dependent adds
 template <int NR>
-__device__ __forceinline__ double gram_total(int len, int k, const double* part) {
+__device__ __forceinline__ double gram_total(int k, const double* part) {
   constexpr int QG = 64 / NR;
   const int n1 = k / NR, n2 = k - n1 * NR;
-  const int span = (len + QG - 1) / QG, used = (len + span - 1) / span;
   double v = part[n1 * R8 + n2];
-  for (int q = 1; q < used; ++q) v += part[(q * NR + n1) * R8 + n2];
+#pragma unroll 8
+  for (int q = 1; q < QG; ++q) v += part[(q * NR + n1) * R8 + n2];
+  return v;
+}
+
+// in-order sum x[0] + x[step] + ... + x[(n - 1) step], n <= 16, loads issued
+// in groups of four ahead of the adds
+__device__ __forceinline__ double chunk_sum(const double* x, size_t step, int n) {
+  double v = x[0];
+  int q = 1;
+  for (; q + 3 < n; q += 4) {
+    const double a = x[q * step], b = x[(q + 1) * step], c = x[(q + 2) * step], d = x[(q + 3) * step];
+    v += a;
+    v += b;
+    v += c;
+    v += d;
+  }
+  for (; q < n; ++q) v += x[q * step];
   return v;
 }
 
@@ -404,11 +421,9 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
           if (QC > 1)
             for (int o = t; o < NR * K; o += CT) {
               const int n = o / K, i = o - n * K;
-              double v = scr[(size_t)i * NR + n];
-              for (int q = 1; q < QC; ++q) v += scr[((size_t)q * K + i) * NR + n];
-              put(xs + o, v);
+              put(xs + o, chunk_sum(scr + (size_t)i * NR + n, (size_t)K * NR, QC));
             }
-          if (t < NR * NR) put(xs + R8 * K + (t / NR) * R8 + t % NR, gram_total<NR>(ml, t, gpart));
+          if (t < NR * NR) put(xs + R8 * K + (t / NR) * R8 + t % NR, gram_total<NR>(t, gpart));
         }
         if (!meet(arrivals, abandoned, error, (ex + 1) * (unsigned)nw, s.limit, &flag)) return false;
         // ---- totals over the component's workgroups (slot order) into LDS
@@ -491,11 +506,9 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
           }
           __syncthreads();
           for (int e = t; e < ml * NR; e += CT) {   // P A^T: chunks in order
-            double v = scr[e];
-            for (int q = 1; q < QK; ++q) v += scr[(size_t)q * ml * NR + e];
-            GP[e] = v;
+            GP[e] = chunk_sum(scr + e, (size_t)ml * NR, QK);
           }
-          if (t < NR * NR) gA[(t / NR) * R8 + t % NR] = gram_total<NR>(K, t, gpart);
+          if (t < NR * NR) gA[(t / NR) * R8 + t % NR] = gram_total<NR>(t, gpart);
           __syncthreads();
         }
         // ---- the own F rows (columns of F in order)
@@ -626,7 +639,12 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
   if (best_mw == 0) return false;
   const int mw = best_mw;
   int scr = 0;
-  const size_t lds = split_lds(K, mw, &scr);
+  size_t lds = split_lds(K, mw, &scr);
+  // spare LDS (up to 2 R8 K more doubles) widens the scratch of the HALS
+  // products' chunk partials, so more chunks run at once at higher ranks
+  const size_t more = std::min<size_t>((budget - lds) / 8, (size_t)2 * R8 * K);
+  scr += (int)more;
+  lds += 8 * more;
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_nmf_split, CT, lds) != hipSuccess || occ < 1)
     return false;
