@@ -234,8 +234,9 @@ def unet_bench(vdev, k_time, reps, dev):
             "mac_per_patch": mac,
             "roofline": {"bound": "mfma", "achieved": flops / t_net / 1e12, "peak": BF16_PEAK / 1e12,
                          "unit": "TFLOP/s", "frac": flops / t_net / BF16_PEAK,
-                         "note": "patches, normalisation, im2col, BF16 MFMA products, merge: the push "
-                                 "time of a SEG_DET_UNET session minus the plain push"}}
+                         "note": "patches, normalisation, direct 3x3 and transposed 2x2 convolutions on "
+                                 "BF16 MFMA, merge: the push time of a SEG_DET_UNET session minus the "
+                                 "plain push"}}
 
 
 def serve_bench(args):

@@ -402,8 +402,9 @@ __global__ __launch_bounds__(NT) void k_nmf(NmfArgs a) {
 
 void plan_nmf(NmfArgs& a, int max_mc) {
   int dev = 0, max_lds = 65536;
-  if (hipGetDevice(&dev) == hipSuccess)
-    hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    max_lds = 65536;   // the smallest LDS of the targets, if the query fails
   const size_t budget = max_lds > 16384 ? (size_t)max_lds - 8192 : 0;  // static LDS ~5 KB
   const size_t K = (size_t)a.K;
   int Q = (int)std::max<size_t>(1, std::min<size_t>(16, NT / std::max<size_t>(1, K)));
