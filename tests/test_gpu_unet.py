@@ -99,6 +99,47 @@ def test_forward_probabilities(case):
     assert np.abs(p - 1.0 / (1.0 + np.exp(-logit))).max() <= 2e-2
 
 
+@pytest.mark.parametrize("B,H,W", [(1, 24, 24), (2, 24, 40), (2, 32, 16)])
+def test_convolution_paths_vs_reference(B, H, W):
+    """Shapes that route the convolutions through every kernel path: the
+    direct halo kernel (W a multiple of 8 whose column block divides the
+    tile), the product that gathers the im2col itself (W = 24 or 40 at full
+    resolution), im2col + product (W = 12, 10, 6 or 4 at lower resolutions),
+    and the transposed convolutions both fused (B H W / 16 a multiple of 8)
+    and through the product + scatter (B = 1, 24 x 24)."""
+    rng = np.random.default_rng(B * 1000 + H * W)
+    S = rng.uniform(800, 1200, (B, H, W))
+    T = rng.uniform(0, 60, (B, H, W))
+    T[:, 4:9, 5:10] += 180
+    st = np.stack([S, T], axis=1).astype(np.float32)
+    labels = np.zeros((B, H, W), np.float32)
+    labels[:, 4:9, 5:10] = 1
+    theta = he_init(5)
+    theta += (0.01 * rng.standard_normal(theta.size)).astype(np.float32)
+    net = SummaryUNet(B, H, W, theta)
+    sd = torch.from_numpy(st).to(DEV)
+    p = net.forward(sd).cpu().numpy()
+    rt = _ref_theta(theta)
+    logit, _, _ = unet_st.forward(rt, st.astype(np.float64))
+    # BF16 operands through 13 layers, logits here up to |20|: measured mean
+    # error about 1.5e-3, max about 0.03 at interior pixels; an indexing or
+    # padding mistake moves many pixels by 0.1 or more
+    err = np.abs(p - 1.0 / (1.0 + np.exp(-logit)))
+    print("prob error max", err.max(), "mean", err.mean(), "logit range", logit.min(), logit.max())
+    assert err.mean() <= 5e-3 and err.max() <= 6e-2
+    loss, g = net.backward(sd, torch.from_numpy(labels).to(DEV), want_grad=True)
+    g = g.cpu().numpy().astype(np.float64)
+    rloss, rg = unet_st.loss_and_grad(rt, st.astype(np.float64), labels)
+    assert abs(loss - rloss) <= 1e-2 * abs(rloss), (loss, rloss)
+    for name, r, c, wo, bo in param_layout():
+        sl = slice(wo, bo + nn_ref.bias_len(name, r))
+        den = np.linalg.norm(rg[sl])
+        cos = float(g[sl] @ rg[sl] / max(np.linalg.norm(g[sl]) * den, 1e-30))
+        assert cos >= 0.99, (name, cos)
+    print("loss", loss, "reference", rloss)
+    net.close()
+
+
 def test_rmsprop_reduces_loss(case):
     st, labels, theta = case
     net = SummaryUNet(2, 16, 16, theta)
