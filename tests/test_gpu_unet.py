@@ -216,4 +216,4 @@ def test_segmentation_quality(trained, record_property):
     record_property("f1_unet", float(np.mean(f_unet)))
     record_property("f1_plain", float(np.mean(f_plain)))
     print("F1 summary U-Net", f_unet, "plain", f_plain)
-    assert np.mean(f_unet) >= 0.75      # measured 0.87 (plain 0.96)
+    assert np.mean(f_unet) >= 0.75      # measured 0.89 (plain 0.96)
