@@ -281,6 +281,10 @@ __global__ void k_region_accum(FinalizeArgs a, long long n, int* __restrict__ ro
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const int l = g < n ? a.lab[g] : -1;
+  // a wave without a labelled pixel contributes nothing (most waves: the
+  // event regions are sparse); the wave leaves as a whole, so the shuffles
+  // below always see all its lanes
+  if (__ballot(l >= 0) == 0) return;
   unsigned cnt = 0, sx = 0, sy = 0;
   unsigned long long sxx = 0, syy = 0, sxy = 0;
   int x0 = INT_MAX, x1 = -1, y0 = INT_MAX, y1 = -1;
