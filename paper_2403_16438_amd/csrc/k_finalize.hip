@@ -190,24 +190,37 @@ __global__ void k_ccl_flatten(int* __restrict__ lab, long long n) {
 
 // ------------------------------------------------------ compaction of roots
 
+// Exclusive scan over a block of NTH threads (integer, so exact in any
+// order): a shuffle scan within each wave, then the wave totals (sh holds
+// NTH / 64 of them); two barriers. Returns the exclusive prefix, the block
+// total in *total.
+template <int NTH>
 __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < BS; off <<= 1) {
-    const int add = t >= off ? sh[t - off] : 0;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d);
+    if (lane >= d) x += y;
   }
-  const int incl = sh[t];
-  *total = sh[BS - 1];
+  if (lane == 63) sh[w] = x;
   __syncthreads();
-  return incl - v;
+  int before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < NTH / 64; ++k) {
+    const int s = sh[k];
+    before += k < w ? s : 0;
+    all += s;
+  }
+  __syncthreads();   // sh is reused by the next call
+  *total = all;
+  return before + x - v;
 }
 
+constexpr int SCAN_NT = 1024;   // threads of the one-block scan of block sums
+
 __global__ void k_count_roots(const int* __restrict__ lab, long long n, int* __restrict__ sums) {
-  __shared__ int sh[BS];
+  __shared__ int sh[BS / 64];
   const long long base = (long long)blockIdx.x * CHUNK + (long long)threadIdx.x * PER;
   int c = 0;
   for (int k = 0; k < PER; ++k) {
@@ -215,19 +228,19 @@ __global__ void k_count_roots(const int* __restrict__ lab, long long n, int* __r
     if (g < n && lab[g] == (int)g) ++c;
   }
   int total;
-  block_exclusive_scan(c, sh, &total);
+  block_exclusive_scan<BS>(c, sh, &total);
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
 // exclusive scan of nb block sums by one block; grand total to *total
-__global__ void k_scan_sums(int* __restrict__ sums, int nb, int* __restrict__ total) {
-  __shared__ int sh[BS];
+__global__ __launch_bounds__(SCAN_NT) void k_scan_sums(int* __restrict__ sums, int nb, int* __restrict__ total) {
+  __shared__ int sh[SCAN_NT / 64];
   int carry = 0;
-  for (int base = 0; base < nb; base += BS) {
+  for (int base = 0; base < nb; base += SCAN_NT) {
     const int i = base + threadIdx.x;
     const int v = i < nb ? sums[i] : 0;
     int tot;
-    const int ex = block_exclusive_scan(v, sh, &tot);
+    const int ex = block_exclusive_scan<SCAN_NT>(v, sh, &tot);
     if (i < nb) sums[i] = carry + ex;
     carry += tot;
   }
@@ -237,7 +250,7 @@ __global__ void k_scan_sums(int* __restrict__ sums, int nb, int* __restrict__ to
 // id[g] = rank of root g among all roots (only written at roots)
 __global__ void k_assign_ids(const int* __restrict__ lab, long long n, const int* __restrict__ sums,
                              int* __restrict__ id) {
-  __shared__ int sh[BS];
+  __shared__ int sh[BS / 64];
   const long long base = (long long)blockIdx.x * CHUNK + (long long)threadIdx.x * PER;
   int flags[PER];
   int c = 0;
@@ -247,7 +260,7 @@ __global__ void k_assign_ids(const int* __restrict__ lab, long long n, const int
     c += flags[k];
   }
   int total;
-  int r = block_exclusive_scan(c, sh, &total) + sums[blockIdx.x];
+  int r = block_exclusive_scan<BS>(c, sh, &total) + sums[blockIdx.x];
   for (int k = 0; k < PER; ++k)
     if (flags[k]) id[base + k] = r++;
 }
@@ -501,7 +514,7 @@ hipError_t compact_roots(const int* lab, long long n, int* sums, int scan_cap, i
   const long long nb = (n + CHUNK - 1) / CHUNK;
   if (nb > scan_cap) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_count_roots, dim3((unsigned)nb), dim3(BS), 0, st, lab, n, sums);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(BS), 0, st, sums, (int)nb, total);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_NT), 0, st, sums, (int)nb, total);
   hipLaunchKernelGGL(k_assign_ids, dim3((unsigned)nb), dim3(BS), 0, st, lab, n, sums, id);
   return hipGetLastError();
 }
