@@ -424,24 +424,18 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
     }
 }
 
-// 1 x 1 convolution to one output channel plus its bias, four pixels per
-// thread: Y[n] = bias + sum_c W[c] X[c][n], both operands rounded to BF16 as
-// in the products, FP32 accumulation in channel order.
+// 1 x 1 convolution to one output channel plus its bias, one pixel per
+// thread (enough workgroups to fill the chip): Y[n] = bias + sum_c W[c]
+// X[c][n], both operands rounded to BF16 as in the products, FP32
+// accumulation in channel order.
 __global__ void k_conv1_out(const uint16_t* __restrict__ Wb, const float* __restrict__ X,
                             const float* __restrict__ bias, float* __restrict__ Y, int C, long long N) {
-  const long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-  for (int c = 0; c < C; ++c) {
-    const float w = from_bf16(Wb[c]);
-    const float4 x = *reinterpret_cast<const float4*>(X + (long long)c * N + i);
-    s.x = fmaf(w, from_bf16(to_bf16(x.x)), s.x);
-    s.y = fmaf(w, from_bf16(to_bf16(x.y)), s.y);
-    s.z = fmaf(w, from_bf16(to_bf16(x.z)), s.z);
-    s.w = fmaf(w, from_bf16(to_bf16(x.w)), s.w);
-  }
-  const float b = bias[0];
-  *reinterpret_cast<float4*>(Y + i) = make_float4(s.x + b, s.y + b, s.z + b, s.w + b);
+  float s = 0.f;
+#pragma unroll 8
+  for (int c = 0; c < C; ++c) s = fmaf(from_bf16(Wb[c]), from_bf16(to_bf16(X[(long long)c * N + i])), s);
+  Y[i] = s + bias[0];
 }
 
 // sum the split-K partials in order: C[m][n] (+)= sum_z P[z][m][n]
@@ -716,24 +710,26 @@ __global__ void k_to_bf16(const float* __restrict__ w, uint16_t* __restrict__ wb
 
 // ---- summary-image input (S, T) -------------------------------------------
 
-// One block per patch: exact-enough FP64 mean and population deviation of
-// S, then channel 0 = (S - mean) / max(sd, 1e-3), channel 1 = T / sqrt(S + 25).
-__global__ __launch_bounds__(256) void k_st_norm(const float* __restrict__ stin, float* __restrict__ x, int Bn,
-                                                 long long HW) {
+// One 1024-thread block per patch (the FP64 divisions and square roots of
+// the pixels are the work): exact-enough FP64 mean and population deviation
+// of S, then channel 0 = (S - mean) / max(sd, 1e-3), channel 1 = T / sqrt(S + 25).
+constexpr int NORM_NT = 1024;
+__global__ __launch_bounds__(NORM_NT) void k_st_norm(const float* __restrict__ stin, float* __restrict__ x, int Bn,
+                                                     long long HW) {
   const int b = blockIdx.x, tid = threadIdx.x;
   const float* S = stin + (size_t)b * 2 * HW;
   const float* T = S + HW;
   double s = 0.0, s2 = 0.0;
-  for (long long i = tid; i < HW; i += 256) {
+  for (long long i = tid; i < HW; i += NORM_NT) {
     const double v = S[i];
     s += v;
     s2 += v * v;
   }
-  __shared__ double r1[256], r2[256];
+  __shared__ double r1[NORM_NT], r2[NORM_NT];
   r1[tid] = s;
   r2[tid] = s2;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = NORM_NT / 2; o > 0; o >>= 1) {
     if (tid < o) {
       r1[tid] += r1[tid + o];
       r2[tid] += r2[tid + o];
@@ -742,7 +738,7 @@ __global__ __launch_bounds__(256) void k_st_norm(const float* __restrict__ stin,
   }
   const double m = r1[0] / (double)HW;
   const double sd = fmax(sqrt(fmax(r2[0] / (double)HW - m * m, 0.0)), 1e-3);
-  for (long long i = tid; i < HW; i += 256) {
+  for (long long i = tid; i < HW; i += NORM_NT) {
     x[(size_t)b * HW + i] = (float)(((double)S[i] - m) / sd);
     x[((size_t)Bn + b) * HW + i] = (float)((double)T[i] / sqrt(fmax((double)S[i], 0.0) + 25.0));
   }
@@ -882,8 +878,7 @@ bool up_direct(const uint16_t* Wb, const float* X, const float* bias, float* Y, 
 }
 
 bool conv1_out(const uint16_t* Wb, const float* X, const float* bias, float* Y, int C, long long N, hipStream_t st) {
-  if (N % 4 || ((uintptr_t)X & 15) || ((uintptr_t)Y & 15)) return false;
-  L1(k_conv1_out, N / 4, Wb, X, bias, Y, C, N);
+  L1(k_conv1_out, N, Wb, X, bias, Y, C, N);
   return true;
 }
 
@@ -938,7 +933,7 @@ void rmsprop(float* w, const float* g, float* v, uint16_t* wb, long long n, floa
 void to_bf16_copy(const float* w, uint16_t* wb, long long n, hipStream_t st) { L1(k_to_bf16, n, w, wb, n); }
 
 void st_norm(const float* stin, float* x, int Bn, long long HW, hipStream_t stream) {
-  hipLaunchKernelGGL(k_st_norm, dim3((unsigned)Bn), dim3(256), 0, stream, stin, x, Bn, HW);
+  hipLaunchKernelGGL(k_st_norm, dim3((unsigned)Bn), dim3(NORM_NT), 0, stream, stin, x, Bn, HW);
 }
 int st_origins(int n) { return (n - 64 + 31) / 32 + 1; }
 void st_patches(const float* S, const float* T, int H, int W, float* out, hipStream_t st) {

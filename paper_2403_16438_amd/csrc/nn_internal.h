@@ -42,7 +42,7 @@ bool conv3_implicit(const uint16_t* Wb, const uint16_t* Wr, const float* X, floa
 bool up_direct(const uint16_t* Wb, const float* X, const float* bias, float* Y, int Co, int Ci, int Bn, int h,
                int w, hipStream_t st);
 // Y [N] = bias[0] + W [1][C] X [C][N] (BF16 operands, FP32 accumulation);
-// false (nothing launched) when N % 4 or X, Y are not 16-byte aligned.
+// always launched (returns true).
 bool conv1_out(const uint16_t* Wb, const float* X, const float* bias, float* Y, int C, long long N, hipStream_t st);
 // Wr [ceil(Ci / 16)][Co][9][16] from W [Co][Ci 9] (zero past Ci)
 void conv3_reorder(const uint16_t* Wb, uint16_t* Wr, int Co, int Ci, hipStream_t st);
