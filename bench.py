@@ -476,3 +476,7 @@ def main():
 
 if __name__ == "__main__":
     main()
+    # release every native object (sessions, networks, batch objects) while
+    # the HIP runtime is certainly alive, before the interpreter exits
+    from paper_2403_16438_amd import shutdown
+    shutdown()

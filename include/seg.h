@@ -23,7 +23,10 @@
  *     host memory. `stream` is a hipStream_t (NULL = the default stream).
  *   - The caller owns the workspace (device memory of seg_workspace_bytes()
  *     bytes) and every frame buffer. The library never allocates device
- *     memory, and keeps no global mutable state: sessions are independent.
+ *     memory for a session, and sessions share no state, with one
+ *     process-wide exception: a lock serialises the cooperative NMF launches
+ *     of concurrent finalizes (so their grids cannot each hold part of the
+ *     device waiting for the rest).
  *   - A session is used by one thread at a time.
  *   - A HIP error inside a session makes it fail permanently (sticky):
  *     every later call on it returns SEG_E_DEVICE; other sessions are
@@ -82,6 +85,8 @@ extern "C" {
 #define SEG_MAP_T 1            /* temporal summary, Eq. 2                           */
 #define SEG_MAP_P 2            /* detection map p_i = max(0, T_i / sigma - theta)   */
 #define SEG_MAP_B 3            /* kept-region mask b_i as 0.0 / 1.0                 */
+#define SEG_MAP_D 4            /* noise-scale term D_i = mean over the segment of
+                                  max(0, median - smoothed value)                   */
 
 typedef struct seg_config {
   uint32_t height, width;   /* frame size in pixels, >= 1                          */
@@ -184,15 +189,18 @@ int seg_get_image(seg_session* s, int kind, void* host_out);
 
 /* Copy `count` per-segment maps starting at segment `first` of kind SEG_MAP_*
  * into dev_out ([count][height][width] float, device memory), ordered on
- * `stream`. S and T are available after the push that completes a segment;
- * P and B need a finalized session.
+ * `stream`. S, T and D are available after the push that completes a
+ * segment; P and B need a finalized session.
  * Errors: SEG_E_INVAL (range), SEG_E_STATE, SEG_E_DEVICE. */
 int seg_get_segment_maps(seg_session* s, int kind, uint32_t first,
                          uint32_t count, float* dev_out, void* stream);
 
 /* Load precomputed per-segment summaries instead of pushing frames, then
- * finalize as usual. For resuming a recording and for checking the
- * footprint reconstruction on its own. All pointers are host memory:
+ * finalize as usual. This is the entry point for stage isolation: the
+ * footprint reconstruction (events, region filter, aggregation, components,
+ * NMF) runs on summaries computed elsewhere, e.g. by a reference
+ * implementation, so it can be checked on its own; it also resumes a
+ * recording whose summaries were kept. All pointers are host memory:
  *   T, S, D  float [k][height][width]   Eq. 2, Eq. 1, noise-scale term D_i
  *   U        float [k][height][width]   sum over the segment of V - R_i
  *   P        float [5][k][height][width] sums over the segment of
@@ -216,6 +224,8 @@ int seg_load_summaries(seg_session* s, uint32_t k, const float* T,
  * memory, so each push rewrites the table (one host-to-device copy) and
  * replays the graph. Every session's result is the same as when it is
  * pushed alone: each (segment, tile) item runs the same code on the same data.
+ * Pushes of one batch object may use different streams: each push orders its
+ * table upload after the previous push's replay.
  */
 typedef struct seg_batch seg_batch;   /* opaque */
 

@@ -29,7 +29,7 @@ SEG_NMF_AUTO, SEG_NMF_SINGLE, SEG_NMF_SPLIT = 0, 1, 2
 
 SEG_IMG_MEAN, SEG_IMG_CORR, SEG_IMG_NOISE = 0, 1, 2
 SEG_IMG_EVENT_COUNT, SEG_IMG_MASK_COUNT, SEG_IMG_LABELS = 3, 4, 5
-SEG_MAP_S, SEG_MAP_T, SEG_MAP_P, SEG_MAP_B = 0, 1, 2, 3
+SEG_MAP_S, SEG_MAP_T, SEG_MAP_P, SEG_MAP_B, SEG_MAP_D = 0, 1, 2, 3, 4
 
 
 class seg_config(C.Structure):

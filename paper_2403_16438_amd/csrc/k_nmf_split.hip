@@ -608,7 +608,8 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
   const int ncomp = a.ncomp;
   if (K < 1 || ncomp < 1) return false;
   const int XS = ((R8 * K + R8 * R8) + 31) / 32 * 32;
-  if ((size_t)ncu * 2 * XS * 8 > xbuf_bytes) return false;
+  // exchange slots: two per workgroup of the largest launch, in xbuf
+  const size_t slot_bytes = (size_t)2 * XS * 8;
   // Slice widths in order of preference (measured: 96 rows balance the
   // per-sweep exchange against the per-workgroup work; at most twelve
   // 16-row tiles). Components are packed, in order, into launches of at most
@@ -619,7 +620,7 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
   for (const int mw : widths) {
     int scr = 0;
     if (split_lds(K, mw, &scr) > budget) continue;
-    int groups = 1, in_group = 0;
+    int groups = 1, in_group = 0, widest = 0;
     bool fits = true;
     for (int k = 0; k < ncomp && fits; ++k) {
       const int nwk = (coff[k + 1] - coff[k] + mw - 1) / mw;
@@ -630,7 +631,9 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
       } else {
         in_group += nwk;
       }
+      widest = std::max(widest, in_group);
     }
+    fits = fits && (size_t)widest * slot_bytes <= xbuf_bytes;
     if (fits && (best_mw == 0 || groups < best_groups)) {
       best_mw = mw;
       best_groups = groups;

@@ -734,6 +734,7 @@ int seg_get_segment_maps(seg_session* s, int kind, uint32_t first, uint32_t coun
   switch (kind) {
     case SEG_MAP_S: base = l.S; break;
     case SEG_MAP_T: base = l.T; break;
+    case SEG_MAP_D: base = l.D; break;
     case SEG_MAP_P:
       if (s->state != State::Finalized) return SEG_E_STATE;
       base = l.p;
@@ -888,6 +889,7 @@ struct seg_batch {
   hipGraph_t graph;
   hipGraphExec_t exec;
   hipEvent_t copied;     // the last table upload has completed
+  hipEvent_t replayed;   // the last replay (which reads the device table) has completed
   bool have_copy;
 };
 
@@ -923,6 +925,7 @@ int seg_batch_create(uint32_t max_slots, void* dev_table, size_t bytes, seg_batc
   b->grid = 2 * cus;  // two resident workgroups per CU
   bool ok = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&b->replayed, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
     const hipError_t le = seg::launch_block_stats_batch(b->dev_table, b->grid, b->capture);
@@ -981,12 +984,16 @@ int seg_push_batch(seg_batch* b, seg_session* const* sessions, const uint16_t* c
   if (b->have_copy && hipEventSynchronize(b->copied) != hipSuccess) return SEG_E_DEVICE;
   const int items = seg::fill_batch_table(b->host_table, ls.data(), (int)count);
   if (items > 0) {
+    // the previous replay reads the device table for its whole run: a push
+    // on another stream must not overwrite it before that replay ends
+    if (b->have_copy && hipStreamWaitEvent(st, b->replayed, 0) != hipSuccess) return SEG_E_DEVICE;
     if (hipMemcpyAsync(b->dev_table, b->host_table, seg::batch_table_bytes(), hipMemcpyHostToDevice, st) !=
             hipSuccess ||
         hipEventRecord(b->copied, st) != hipSuccess)
       return SEG_E_DEVICE;
     b->have_copy = true;
-    if (hipGraphLaunch(b->exec, st) != hipSuccess) return SEG_E_DEVICE;
+    if (hipGraphLaunch(b->exec, st) != hipSuccess || hipEventRecord(b->replayed, st) != hipSuccess)
+      return SEG_E_DEVICE;
   }
   // tails and counters, as in seg_push_frames
   for (uint32_t k = 0; k < count; ++k) {
@@ -1018,10 +1025,11 @@ int seg_push_batch(seg_batch* b, seg_session* const* sessions, const uint16_t* c
 int seg_batch_destroy(seg_batch* b) {
   if (!b) return SEG_OK;
   (void)hipSetDevice(b->device);
-  if (b->have_copy) (void)hipEventSynchronize(b->copied);
+  if (b->have_copy) (void)hipEventSynchronize(b->replayed);
   (void)hipGraphExecDestroy(b->exec);
   (void)hipGraphDestroy(b->graph);
   (void)hipEventDestroy(b->copied);
+  (void)hipEventDestroy(b->replayed);
   (void)hipStreamDestroy(b->capture);
   (void)hipHostFree(b->host_table);
   delete b;

@@ -8,7 +8,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import abi
+from . import abi, lifetime
 
 
 class MotionCorrector:
@@ -22,6 +22,7 @@ class MotionCorrector:
             self.workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
             aligned = (self.workspace.data_ptr() + 255) & ~255
             self.handle = abi.seg_mc_create(self.cfg, aligned, self.nbytes)
+        lifetime.track(self)
         self.H, self.W = height, width
         self.n_patches, self.n_vectors = abi.seg_mc_layout(self.handle)
 
@@ -78,7 +79,8 @@ class MotionCorrector:
             self.handle = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        if lifetime.released_by_finalizer():
+            try:
+                self.close()
+            except Exception:
+                pass

@@ -29,7 +29,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from . import abi
+from . import abi, lifetime
 from .session import Session
 
 
@@ -77,6 +77,7 @@ class Batch:
         with torch.cuda.device(self.device):
             self.table = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
             self.handle = abi.seg_batch_create(max_slots, (self.table.data_ptr() + 255) & ~255, nbytes)
+        lifetime.track(self)
         self.max_slots = max_slots
 
     def push(self, sessions, frames, stream=None) -> None:
@@ -90,10 +91,11 @@ class Batch:
             self.handle = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        if lifetime.released_by_finalizer():
+            try:
+                self.close()
+            except Exception:
+                pass
 
 
 @dataclass
@@ -200,8 +202,13 @@ class Server:
                 lv.sess.finalize(self.finals)
                 out = dict(footprints=lv.sess.footprints(), segments=lv.sess.num_segments)
                 if lv.spec.keep_maps:
-                    out["S"] = lv.sess.segment_maps(abi.SEG_MAP_S).cpu().numpy()
-                    out["T"] = lv.sess.segment_maps(abi.SEG_MAP_T).cpu().numpy()
+                    maps = lambda k: lv.sess.segment_maps(k).cpu().numpy()
+                    out.update(S=maps(abi.SEG_MAP_S), T=maps(abi.SEG_MAP_T), D=maps(abi.SEG_MAP_D),
+                               P=maps(abi.SEG_MAP_P), B=maps(abi.SEG_MAP_B) > 0.5,
+                               sigma=lv.sess.image(abi.SEG_IMG_NOISE),
+                               count=lv.sess.image(abi.SEG_IMG_EVENT_COUNT),
+                               nb=lv.sess.image(abi.SEG_IMG_MASK_COUNT),
+                               labels=lv.sess.image(abi.SEG_IMG_LABELS))
                 torch.cuda.current_stream(self.device).synchronize()
             return out
 

@@ -8,7 +8,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import abi
+from . import abi, lifetime
 
 
 def to_device_frames(video: np.ndarray, device="cuda") -> torch.Tensor:
@@ -41,6 +41,7 @@ class Session:
             base = self.workspace.data_ptr()
             aligned = (base + 255) & ~255
             self.handle = abi.seg_create(self.cfg, aligned, self.nbytes)
+        lifetime.track(self)
         self.H, self.W = height, width
 
     def set_model(self, net) -> None:
@@ -137,10 +138,11 @@ class Session:
             self.handle = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        if lifetime.released_by_finalizer():
+            try:
+                self.close()
+            except Exception:
+                pass
 
 
 def segment_video(video: np.ndarray, block: int | None = None, net=None, **overrides) -> Session:

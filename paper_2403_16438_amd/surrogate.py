@@ -10,7 +10,7 @@ import ctypes as C
 import numpy as np
 import torch
 
-from . import abi
+from . import abi, lifetime
 
 LAYERS = ["t1", "t2", "t3", "e1a", "e1b", "e2a", "e2b", "e3a", "e3b", "u2", "d2a", "d2b", "u1",
           "d1a", "d1b", "out"]
@@ -57,6 +57,7 @@ class Surrogate:
                                         C.c_void_p((self.ws.data_ptr() + 255) & ~255), nb.value, C.byref(h)),
                   "seg_nn_create")
         self.handle = h
+        lifetime.track(self)
         self.load(he_init(0) if theta is None else theta)
 
     def _st(self):
@@ -101,10 +102,11 @@ class Surrogate:
             self.handle = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        if lifetime.released_by_finalizer():
+            try:
+                self.close()
+            except Exception:
+                pass
 
 
 def gemm_test(A: torch.Tensor, B: torch.Tensor, a_trans=False, b_trans=False, splits=1) -> torch.Tensor:

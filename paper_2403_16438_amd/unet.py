@@ -10,7 +10,7 @@ import ctypes as C
 import numpy as np
 import torch
 
-from . import abi
+from . import abi, lifetime
 from .surrogate import LAYERS
 
 
@@ -84,6 +84,7 @@ class SummaryUNet:
                                            C.c_void_p((self.ws.data_ptr() + 255) & ~255), nb.value, C.byref(h)),
                   "seg_nn_st_create")
         self.handle = h
+        lifetime.track(self)
         self.load(he_init(0) if theta is None else theta)
 
     def load(self, theta) -> None:
@@ -128,7 +129,8 @@ class SummaryUNet:
             self.handle = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        if lifetime.released_by_finalizer():
+            try:
+                self.close()
+            except Exception:
+                pass

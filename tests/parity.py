@@ -82,3 +82,64 @@ def compare_footprints(gpu: dict, ref_list: list, min_iou=0.99):
     if ious:
         assert min(ious) >= min_iou, ious
     return ious
+
+
+# The GPU and the oracle fed the same FP32 summaries differ only by FP64
+# rounding (sigma sums the same FP32 D values in another order): decisions
+# farther than this from the threshold (relative to theta) must agree.
+Z_ROUNDING = 1e-12
+
+
+def session_outputs(sess) -> dict:
+    """Everything a finalized plain-detector session reports, on the host."""
+    from paper_2403_16438_amd import abi
+    maps = lambda k: sess.segment_maps(k).cpu().numpy()
+    return dict(S=maps(abi.SEG_MAP_S), T=maps(abi.SEG_MAP_T), D=maps(abi.SEG_MAP_D),
+                P=maps(abi.SEG_MAP_P), B=maps(abi.SEG_MAP_B) > 0.5,
+                sigma=sess.image(abi.SEG_IMG_NOISE), count=sess.image(abi.SEG_IMG_EVENT_COUNT),
+                nb=sess.image(abi.SEG_IMG_MASK_COUNT), labels=sess.image(abi.SEG_IMG_LABELS),
+                fp=sess.footprints())
+
+
+def check_finalize_stage_isolation(g: dict, prm: oracle.Params, min_iou=0.99):
+    """Stage isolation of the footprint reconstruction (Sec. III-D, Eq. 3):
+    the oracle fed the session's own FP32 T and D against what the session's
+    finalize reported (g, from session_outputs). Event counts, kept masks b_i,
+    n_b and component labels bit-exact; noise scale and detection maps within
+    1e-6; footprints the same per component with mask IoU >= min_iou.
+
+    Nothing is skipped: a decision within FP64 rounding of the threshold
+    fails the test. Returns the oracle's result."""
+    r = oracle_from_summaries(g["T"], g["D"], prm)
+    near = r["margin"] <= Z_ROUNDING * prm.event_z
+    assert not near.any(), f"{int(near.sum())} event decisions within FP64 rounding of theta"
+    np.testing.assert_allclose(g["sigma"], r["sigma"], rtol=1e-6, atol=1e-30)
+    assert np.array_equal(g["count"], r["count"]), "event counts"
+    assert np.array_equal(g["B"], r["b"]), "kept masks b_i"
+    assert np.array_equal(g["nb"], r["nb"]), "n_b"
+    assert np.array_equal(g["labels"], r["labels"]), "labels"
+    np.testing.assert_allclose(g["P"], r["p"], rtol=1e-6, atol=1e-6)
+    compare_footprints(g["fp"], r["footprints"], min_iou)
+    return r
+
+
+def check_against_full_oracle(g: dict, ref, prm: oracle.Params, min_iou=0.99):
+    """The session's outputs against the whole oracle run on the video: S
+    bit-exact, T and the noise scale within 1e-4, event counts bit-exact on
+    pixels with no decision in the 1e-6 theta window, and, when no decision
+    lies in that window, kept masks, n_b, labels and footprints as well.
+    Returns the number of pixels with a decision in the window (the
+    downstream stages are then compared by stage isolation, which callers
+    always run as well)."""
+    assert np.array_equal(g["S"], ref.S.astype(np.float32)), "S"
+    assert_image_close(g["T"], ref.T, what="T")
+    assert_image_close(g["D"], ref.D, what="D")
+    assert_image_close(g["sigma"], ref.sigma, what="sigma")
+    window = (ref.event_margin <= EVENT_WINDOW * prm.event_z).any(0)
+    assert np.array_equal(g["count"][~window], ref.count[~window]), "event counts"
+    if not window.any():
+        assert np.array_equal(g["B"], ref.b), "kept masks b_i"
+        assert np.array_equal(g["nb"], ref.nb), "n_b"
+        assert np.array_equal(g["labels"], ref.labels), "labels"
+        compare_footprints(g["fp"], ref.footprints, min_iou)
+    return int(window.sum())

@@ -56,10 +56,12 @@ def test_split_is_reproducible(wide):
 
 
 def test_auto_path_small_case():
-    """64 x 64 x 1,000 (20 segments): the automatic choice (split) against the
+    """64 x 64 x 1,000 (20 segments): the automatic choice (split: the
+    exchange slots of its few workgroups fit the workspace) against the
     oracle."""
     video, _ = simulate(preset(1), 0)
     sess = segment_video(video)
+    assert sess.profile()["nmf_path"] == abi.SEG_NMF_SPLIT
     ref = oracle.segment(video, params_from_config(sess.cfg))
     compare_footprints(sess.footprints(), ref.footprints)
 

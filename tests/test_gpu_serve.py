@@ -1,15 +1,23 @@
 """Streaming server: continuous batching across sessions of different frame
-sizes, admission by HBM budget, and each session's result identical alone
-and in the mix (bit for bit: every work item runs the same code on the same
-data)."""
+sizes, admission by HBM budget, each session's result identical alone and in
+the mix (bit for bit: every work item runs the same code on the same data),
+and every served session against the FP64 oracle run on its video: S
+bit-exact, T, D and the noise scale within 1e-4, event counts bit-exact
+outside the threshold window, and the footprint reconstruction by stage
+isolation (counts, kept masks, n_b and labels bit-exact, footprints at
+IoU >= 0.99). The last check uses the four frame sizes of the 16-session
+workload (128 x 128, 256 x 256, 512 x 128, 512 x 512)."""
 import numpy as np
 import pytest
 import torch
 
 from paper_2403_16438_amd import abi, Session
 from paper_2403_16438_amd.serve import Batch, Server, SessionSpec
+import oracle
 from synth import preset
 from synth.gpu import GpuScene
+
+from parity import check_against_full_oracle, check_finalize_stage_isolation, params_from_config
 
 pytestmark = pytest.mark.gpu
 
@@ -40,6 +48,48 @@ def mix():
     out = srv.run(_specs())
     srv.close()
     return out
+
+
+def _served_against_oracle(spec, res):
+    """One served session (results with keep_maps) against the oracle run on
+    the frames its camera rendered."""
+    frames = spec.blocks * spec.block_frames
+    video = GpuScene(spec.cfg, spec.seed).render(0, frames).cpu().numpy().view(np.uint16)
+    cfg = abi.seg_default_config(spec.cfg.height, spec.cfg.width, frames)
+    prm = params_from_config(cfg)
+    ref = oracle.segment(video, prm)
+    g = dict(res, fp=res["footprints"])
+    in_window = check_against_full_oracle(g, ref, prm)
+    check_finalize_stage_isolation(g, prm)
+    return ref, in_window
+
+
+@pytest.mark.parametrize("name", ["a", "b", "c"])
+def test_served_session_against_oracle(mix, name):
+    spec = [s for s in _specs() if s.name == name][0]
+    _served_against_oracle(spec, mix["results"][name])
+
+
+def test_workload_frame_sizes_against_oracle():
+    """One served session of each frame size of the 16-session workload, two
+    500-frame blocks each, admitted and batched together."""
+    sizes = [(128, 128), (256, 256), (512, 128), (512, 512)]
+    specs = []
+    for k, (h, w) in enumerate(sizes):
+        scale = h * w / 65536.0                   # the workload's density scaling
+        n = max(2, int(round(30 * scale)))
+        cfg = preset(5, height=h, width=w, frames=1000, n_neurons=n, n_overlap=int(round(0.2 * n)),
+                     n_blobs=max(1, int(round(5 * scale))))
+        specs.append(SessionSpec(f"s{h}x{w}", cfg, 5100 + k, 1000.0, 0.0, blocks=2, block_frames=500,
+                                 keep_maps=True))
+    srv = Server(hbm_budget=24 << 30, time_scale=25.0)
+    out = srv.run(specs)
+    srv.close()
+    assert out["blocks"] == 8 and set(out["results"]) == {s.name for s in specs}
+    assert out["mean_batch"] > 1.0          # blocks of different sessions shared launches
+    for sp in specs:
+        ref, in_window = _served_against_oracle(sp, out["results"][sp.name])
+        print(sp.name, "footprints", len(ref.footprints), "pixels with a window decision", in_window)
 
 
 def test_mix_runs_all_blocks(mix):

@@ -14,6 +14,8 @@ import oracle.traces as otr
 from paper_2403_16438_amd import abi, segment_video, Session, to_device_frames
 from synth import preset, simulate
 
+from scenes import ring_video
+
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 
@@ -135,32 +137,10 @@ def test_overlapping_footprints_and_large_mask():
     assert np.array_equal(got.cpu().numpy(), _ref(video, fp["masks"]))
 
 
-def _ring_video(n_cells=6, radius=7.0, sigma=3.0, frames=1000, seed=0):
-    """Hand-built scene: n_cells Gaussian cells on a ring, neighbours
-    overlapping, cell j firing (two frames, +40% of its footprint) in
-    segments j, j + n_cells, ... Poisson-Gaussian noise around 1000."""
-    rng = np.random.default_rng(seed)
-    yy, xx = np.mgrid[0:64, 0:64].astype(np.float64)
-    cells = []
-    for j in range(n_cells):
-        ang = 2 * np.pi * j / n_cells
-        cx, cy = 32 + radius * np.cos(ang), 32 + radius * np.sin(ang)
-        cells.append(np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / (2 * sigma ** 2)))
-    cells = np.array(cells)
-    act = np.zeros((frames, n_cells))
-    for j in range(n_cells):
-        for seg in range(j, frames // 50, n_cells):
-            act[seg * 50 + 20 + j, j] = 1.0
-            act[seg * 50 + 21 + j, j] = 0.5
-    mean = 1000.0 * (1.0 + 0.4 * np.tensordot(act, cells, axes=1))
-    v = rng.poisson(mean) + rng.normal(0.0, 5.0, mean.shape)
-    return np.clip(np.rint(v), 0, 65535).astype(np.uint16)
-
-
 def test_component_with_many_footprints():
     """Six overlapping cells in one component (the oracle finds six
     footprints): mask bits up to the fifth and beyond."""
-    video = _ring_video()
+    video = ring_video()
     sess = segment_video(video)
     fp = sess.footprints()
     assert np.bincount(fp["component"]).max() >= 5
