@@ -23,10 +23,11 @@
  *     host memory. `stream` is a hipStream_t (NULL = the default stream).
  *   - The caller owns the workspace (device memory of seg_workspace_bytes()
  *     bytes) and every frame buffer. The library never allocates device
- *     memory for a session, and sessions share no state, with one
- *     process-wide exception: a lock serialises the cooperative NMF launches
- *     of concurrent finalizes (so their grids cannot each hold part of the
- *     device waiting for the rest).
+ *     memory for a session, and sessions share no state, with two
+ *     process-wide exceptions: one lock serialises the cooperative NMF
+ *     launches of concurrent finalizes (so their grids cannot each hold part
+ *     of the device waiting for the rest), and seg_mc_estimate_static
+ *     (seg_mc.h) keeps its partial sums in a fixed device array per GPU.
  *   - A session is used by one thread at a time.
  *   - A HIP error inside a session makes it fail permanently (sticky):
  *     every later call on it returns SEG_E_DEVICE; other sessions are

@@ -85,6 +85,26 @@ int seg_mc_get_template(seg_mc* mc, uint16_t* host_out);
 int seg_mc_estimate(seg_mc* mc, const uint16_t* dev_frames, uint64_t n_frames,
                     int32_t* dev_motion, double* dev_scores, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * motion of up to SEG_MC_STATIC_MAX_FRAMES frames, exactly as
+ * seg_mc_estimate computes it (same kernels, same order of sums, same
+ * results), but the per-slice partial ZNCC sums go to a fixed device array
+ * inside the library instead of the corrector's workspace. That array holds
+ * 7 MiB on every GPU the library runs on, from the first corrector created
+ * there until the process ends; nothing is allocated or freed by this call.
+ * Every call on one GPU shares that GPU's array (each call writes every
+ * entry it reads, so nothing carries over between calls): calls that overlap
+ * in time on one GPU, from any corrector or stream, race, and the caller
+ * must order them (one stream, or events). Ordered on `stream`, no
+ * synchronisation.
+ * Errors: SEG_E_INVAL (NULL with n_frames > 0), SEG_E_STATE (no template),
+ * SEG_E_CAPACITY (n_frames > SEG_MC_STATIC_MAX_FRAMES), SEG_E_DEVICE (the
+ * array's device address could not be resolved, or a launch failed). */
+#define SEG_MC_STATIC_MAX_FRAMES 256
+int seg_mc_estimate_static(seg_mc* mc, const uint16_t* dev_frames, uint64_t n_frames,
+                           int32_t* dev_motion, double* dev_scores, void* stream);
+
 /* Corrected frames: dev_out[t](y, x) = dev_frames[t](y + my, x + mx) with
  * (my, mx) = dev_motion[t] where that pixel lies in the frame, else the
  * template's value at (y, x). dev_out must not overlap dev_frames.

@@ -134,6 +134,7 @@ def _load():
         "seg_mc_set_template": (C.c_int, [P, P, u32, P]),
         "seg_mc_get_template": (C.c_int, [P, P]),
         "seg_mc_estimate": (C.c_int, [P, P, C.c_uint64, P, P, P]),
+        "seg_mc_estimate_static": (C.c_int, [P, P, C.c_uint64, P, P, P]),
         "seg_mc_apply": (C.c_int, [P, P, C.c_uint64, P, P, P]),
         "seg_mc_destroy": (C.c_int, [P]),
         "seg_strerror": (C.c_char_p, [C.c_int]),
@@ -315,6 +316,16 @@ def seg_mc_estimate(h, dev_frames: int, n: int, dev_motion: int, dev_scores: int
     check(lib.seg_mc_estimate(h, C.c_void_p(dev_frames), n, C.c_void_p(dev_motion),
                               C.c_void_p(dev_scores) if dev_scores else None, C.c_void_p(stream)),
           "seg_mc_estimate")
+
+
+SEG_MC_STATIC_MAX_FRAMES = 256
+
+
+def seg_mc_estimate_static(h, dev_frames: int, n: int, dev_motion: int, dev_scores: int | None,
+                           stream: int) -> None:
+    check(lib.seg_mc_estimate_static(h, C.c_void_p(dev_frames), n, C.c_void_p(dev_motion),
+                                     C.c_void_p(dev_scores) if dev_scores else None, C.c_void_p(stream)),
+          "seg_mc_estimate_static")
 
 
 def seg_mc_apply(h, dev_frames: int, n: int, dev_motion: int, dev_out: int, stream: int) -> None:

@@ -18,6 +18,14 @@
 // the final products round.
 #include "seg_motion.h"
 
+#include <mutex>
+
+// Partial ZNCC sums of seg_mc_estimate_static, for callers that cannot
+// allocate device memory: one copy per GPU, held until the process ends.
+// Host code never passes this name to a kernel (on the host it is only a
+// stand-in): the device address comes from mc_static_scratch below.
+static __device__ __align__(256) double scratch[seg::kMcStaticDoubles];
+
 namespace seg {
 namespace {
 
@@ -233,7 +241,7 @@ __global__ __launch_bounds__(kSThreads) void k_mc_scores(McScoreArgs a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int d = t * 16 + 4 * j + q;
-        a.part[((size_t)slice * kMcChunk + f0 + col) * g.Vp + d] = score[i][j];
+        a.part[((size_t)slice * a.chunk + f0 + col) * g.Vp + d] = score[i][j];
       }
     }
   }
@@ -243,15 +251,15 @@ __global__ __launch_bounds__(kSThreads) void k_mc_scores(McScoreArgs a) {
 
 // One wave per frame: lanes take vectors d = lane, lane + 64, ...; the slice
 // sums are added in slice order; the first maximum wins.
-__global__ __launch_bounds__(kThreads) void k_mc_pick(McGeom g, const double* __restrict__ part, int n,
-                                                      int32_t* motion, double* scores) {
+__global__ __launch_bounds__(kThreads) void k_mc_pick(McGeom g, const double* __restrict__ part, int chunk,
+                                                      int n, int32_t* motion, double* scores) {
   const int f = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (f >= n) return;
   double best = -1.0e300;
   int arg = 0x7fffffff;
   for (int d = lane; d < g.V; d += 64) {
     double s = 0.0;
-    for (int sl = 0; sl < g.S; ++sl) s += part[((size_t)sl * kMcChunk + f) * g.Vp + d];
+    for (int sl = 0; sl < g.S; ++sl) s += part[((size_t)sl * chunk + f) * g.Vp + d];
     if (scores) scores[(size_t)f * g.V + d] = s;
     if (s > best) {
       best = s;
@@ -355,12 +363,12 @@ hipError_t launch_mc_scores(const McScoreArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_mc_pick(const McGeom& g, const double* part, int n, int32_t* motion, double* scores,
-                          hipStream_t st) {
+hipError_t launch_mc_pick(const McGeom& g, const double* part, int chunk, int n, int32_t* motion,
+                          double* scores, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int per = kThreads / 64;
-  hipLaunchKernelGGL(k_mc_pick, dim3((unsigned)((n + per - 1) / per)), dim3(kThreads), 0, st, g, part, n, motion,
-                     scores);
+  hipLaunchKernelGGL(k_mc_pick, dim3((unsigned)((n + per - 1) / per)), dim3(kThreads), 0, st, g, part, chunk, n,
+                     motion, scores);
   return hipGetLastError();
 }
 
@@ -381,6 +389,24 @@ hipError_t launch_mc_apply(const uint16_t* in, long long n, int H, int W, const 
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+hipError_t mc_static_scratch(double** ptr) {
+  static std::mutex mu;
+  static double* cache[kMaxMcDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxMcDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> hold(mu);
+  if (!cache[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    cache[dev] = static_cast<double*>(p);
+  }
+  *ptr = cache[dev];
   return hipSuccess;
 }
 

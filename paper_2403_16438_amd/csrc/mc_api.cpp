@@ -13,6 +13,7 @@ struct seg_mc {
   char* ws;
   size_t at_tmpl, at_ii, at_sT, at_vT, at_part, total;
   int device;
+  double* scratch;   // this device's copy of the static partial-sum array (or null)
   bool have_template;
   bool failed;
 };
@@ -124,6 +125,12 @@ int seg_mc_create(const seg_mc_config* cfg, void* dev_workspace, size_t bytes, s
     delete m;
     return SEG_E_DEVICE;
   }
+  // the static partial-sum array's address on this device, for
+  // seg_mc_estimate_static (which fails with SEG_E_DEVICE if it is missing)
+  if (seg::mc_static_scratch(&m->scratch) != hipSuccess) {
+    (void)hipGetLastError();
+    m->scratch = nullptr;
+  }
   *out = m;
   return SEG_OK;
 }
@@ -179,12 +186,38 @@ int seg_mc_estimate(seg_mc* mc, const uint16_t* dev_frames, uint64_t n_frames, i
     a.sT = at<double>(mc, mc->at_sT);
     a.vT = at<double>(mc, mc->at_vT);
     a.part = at<double>(mc, mc->at_part);
+    a.chunk = seg::kMcChunk;
     if ((e = fail(mc, seg::launch_mc_scores(a, st)))) return e;
-    if ((e = fail(mc, seg::launch_mc_pick(g, a.part, n, dev_motion + 2 * f0,
+    if ((e = fail(mc, seg::launch_mc_pick(g, a.part, a.chunk, n, dev_motion + 2 * f0,
                                           dev_scores ? dev_scores + f0 * g.V : nullptr, st))))
       return e;
   }
   return SEG_OK;
+}
+
+int seg_mc_estimate_static(seg_mc* mc, const uint16_t* dev_frames, uint64_t n_frames, int32_t* dev_motion,
+                           double* dev_scores, void* stream) {
+  int e = enter(mc);
+  if (e) return e;
+  if (!mc->have_template) return SEG_E_STATE;
+  if (n_frames > (uint64_t)seg::kMcStaticFrames) return SEG_E_CAPACITY;
+  if (n_frames == 0) return SEG_OK;
+  if (!dev_frames || !dev_motion) return SEG_E_INVAL;
+  const seg::McGeom& g = mc->g;
+  if ((size_t)g.S * seg::kMcStaticFrames * g.Vp > seg::kMcStaticDoubles) return SEG_E_CAPACITY;
+  if (!mc->scratch) return fail(mc, hipErrorInvalidSymbol);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  seg::McScoreArgs a{};
+  a.g = g;
+  a.frames = dev_frames;
+  a.n = (int)n_frames;
+  a.tmpl = at<uint16_t>(mc, mc->at_tmpl);
+  a.sT = at<double>(mc, mc->at_sT);
+  a.vT = at<double>(mc, mc->at_vT);
+  a.part = mc->scratch;          // every entry the pick reads is written first
+  a.chunk = seg::kMcStaticFrames;
+  if ((e = fail(mc, seg::launch_mc_scores(a, st)))) return e;
+  return fail(mc, seg::launch_mc_pick(g, a.part, a.chunk, a.n, dev_motion, dev_scores, st));
 }
 
 int seg_mc_apply(seg_mc* mc, const uint16_t* dev_frames, uint64_t n_frames, const int32_t* dev_motion,

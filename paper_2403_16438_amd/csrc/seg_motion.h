@@ -32,11 +32,12 @@ struct McGeom {
 struct McScoreArgs {
   McGeom g;
   const uint16_t* frames;   // [n][H][W]
-  int n;                    // frames of this launch, <= kMcChunk
+  int n;                    // frames of this launch, <= chunk
   const uint16_t* tmpl;     // [H][W]
   const double* sT;         // [P][Vp] template window sums
   const double* vT;         // [P][Vp] 1 / sqrt(441 sum T^2 - (sum T)^2), 0 if that is 0
-  double* part;             // [S][kMcChunk][Vp] per-slice ZNCC sums
+  double* part;             // [S][chunk][Vp] per-slice ZNCC sums
+  int chunk;                // frame stride of `part`, >= n
 };
 
 // template = per-pixel sum of n frames, rounded half up after division by n
@@ -47,9 +48,19 @@ hipError_t launch_mc_tables(const McGeom& g, const uint16_t* tmpl, unsigned long
                             double* sT, double* vT, hipStream_t st);
 hipError_t launch_mc_scores(const McScoreArgs& a, hipStream_t st);
 // per frame: slice sums in order, argmax (first maximum), motion = -d;
-// scores (may be null) [n][V]
-hipError_t launch_mc_pick(const McGeom& g, const double* part, int n, int32_t* motion, double* scores,
-                          hipStream_t st);
+// scores (may be null) [n][V]; `part` as in McScoreArgs with frame stride chunk
+hipError_t launch_mc_pick(const McGeom& g, const double* part, int chunk, int n, int32_t* motion,
+                          double* scores, hipStream_t st);
+
+// Fixed device array for the partial sums of callers that cannot allocate:
+// kMcStaticFrames frames of the largest geometry (8 slices, 448 padded
+// vectors at radius 10), 7 MiB per GPU, alive until the process ends.
+constexpr int kMcStaticFrames = 256;
+constexpr int kMaxMcDevices = 64;
+constexpr size_t kMcStaticDoubles = (size_t)kMcSlices * kMcStaticFrames * 448;
+// Device address of that array on the current device, resolved once per
+// device (hipGetSymbolAddress) and cached. Returns the HIP status.
+hipError_t mc_static_scratch(double** ptr);
 // out(y, x) = in(y + my, x + mx) inside the frame, else tmpl(y, x)
 hipError_t launch_mc_apply(const uint16_t* in, long long n, int H, int W, const int32_t* motion,
                            const uint16_t* tmpl, uint16_t* out, hipStream_t st);

@@ -56,6 +56,22 @@ class MotionCorrector:
                             sc.data_ptr() if sc is not None else None, self._stream(stream))
         return (motion, sc) if scores else motion
 
+    def estimate_static(self, frames: torch.Tensor, motion: torch.Tensor, scores: torch.Tensor | None = None,
+                        stream=None) -> None:
+        """seg_mc_estimate_static: as estimate(), into caller-given outputs
+        (int32 [n, 2] and optionally float64 [n, V]), with the partial sums in
+        the library's fixed device array; n <= SEG_MC_STATIC_MAX_FRAMES."""
+        self._check(frames)
+        n = frames.shape[0]
+        if (motion.dtype != torch.int32 or tuple(motion.shape) != (n, 2) or not motion.is_contiguous()
+                or motion.device != self.device):
+            raise ValueError("motion must be contiguous int32 [n, 2] on the corrector's device")
+        if scores is not None and (scores.dtype != torch.float64 or tuple(scores.shape) != (n, self.n_vectors)
+                                   or not scores.is_contiguous() or scores.device != self.device):
+            raise ValueError("scores must be contiguous float64 [n, V] on the corrector's device")
+        abi.seg_mc_estimate_static(self.handle, frames.data_ptr(), n, motion.data_ptr(),
+                                   scores.data_ptr() if scores is not None else None, self._stream(stream))
+
     def apply(self, frames: torch.Tensor, motion: torch.Tensor, out: torch.Tensor | None = None,
               stream=None) -> torch.Tensor:
         self._check(frames)
