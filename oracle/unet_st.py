@@ -78,13 +78,13 @@ def patches(S: np.ndarray, T: np.ndarray) -> np.ndarray:
     return np.array(out, np.float64)
 
 
-def normalise(st: np.ndarray) -> np.ndarray:
+def normalise(st: np.ndarray, nm=nn_ref.EXACT) -> np.ndarray:
     """[B][2][64][64] raw (S, T) -> network input."""
     s = st[:, 0].astype(np.float64)
     t = st[:, 1].astype(np.float64)
     m = s.mean(axis=(1, 2), keepdims=True)
     sd = np.maximum(s.std(axis=(1, 2), keepdims=True), 1e-3)
-    return np.stack([(s - m) / sd, t / np.sqrt(np.maximum(s, 0.0) + 25.0)], axis=1)
+    return nm.s(np.stack([(s - m) / sd, t / np.sqrt(np.maximum(s, 0.0) + 25.0)], axis=1))
 
 
 def tent() -> np.ndarray:
@@ -107,59 +107,60 @@ def merge(prob: np.ndarray, H: int, W: int) -> np.ndarray:
     return num / den
 
 
-def forward(theta, st):
-    """Logits [B][64][64] of raw patches st [B][2][64][64], and the cache."""
+def forward(theta, st, nm=nn_ref.EXACT):
+    """Logits [B][64][64] of raw patches st [B][2][64][64], and the cache
+    (nm: where the arithmetic rounds, see nn_ref.Numerics)."""
     p = unpack(np.asarray(theta, np.float64))
     c = {}
-    c["x"] = normalise(st)
+    c["x"] = normalise(st, nm)
     relu = lambda v: np.maximum(v, 0.0)
-    c["e1a"] = relu(nn_ref.conv3(c["x"], p["e1a.w"], p["e1a.b"]))
-    c["s1"] = relu(nn_ref.conv3(c["e1a"], p["e1b.w"], p["e1b.b"]))
+    c["e1a"] = relu(nn_ref.conv3(c["x"], p["e1a.w"], p["e1a.b"], nm))
+    c["s1"] = relu(nn_ref.conv3(c["e1a"], p["e1b.w"], p["e1b.b"], nm))
     c["p1"], c["arg1"] = nn_ref.pool(c["s1"])
-    c["e2a"] = relu(nn_ref.conv3(c["p1"], p["e2a.w"], p["e2a.b"]))
-    c["s2"] = relu(nn_ref.conv3(c["e2a"], p["e2b.w"], p["e2b.b"]))
+    c["e2a"] = relu(nn_ref.conv3(c["p1"], p["e2a.w"], p["e2a.b"], nm))
+    c["s2"] = relu(nn_ref.conv3(c["e2a"], p["e2b.w"], p["e2b.b"], nm))
     c["p2"], c["arg2"] = nn_ref.pool(c["s2"])
-    c["e3a"] = relu(nn_ref.conv3(c["p2"], p["e3a.w"], p["e3a.b"]))
-    c["b3"] = relu(nn_ref.conv3(c["e3a"], p["e3b.w"], p["e3b.b"]))
-    c["cat2"] = np.concatenate([nn_ref.up(c["b3"], p["u2.w"], p["u2.b"]), c["s2"]], axis=1)
-    c["d2a"] = relu(nn_ref.conv3(c["cat2"], p["d2a.w"], p["d2a.b"]))
-    c["d2"] = relu(nn_ref.conv3(c["d2a"], p["d2b.w"], p["d2b.b"]))
-    c["cat1"] = np.concatenate([nn_ref.up(c["d2"], p["u1.w"], p["u1.b"]), c["s1"]], axis=1)
-    c["d1a"] = relu(nn_ref.conv3(c["cat1"], p["d1a.w"], p["d1a.b"]))
-    c["d1"] = relu(nn_ref.conv3(c["d1a"], p["d1b.w"], p["d1b.b"]))
-    logit = np.einsum("c,bcyx->byx", p["out.w"][0], c["d1"]) + p["out.b"][0]
+    c["e3a"] = relu(nn_ref.conv3(c["p2"], p["e3a.w"], p["e3a.b"], nm))
+    c["b3"] = relu(nn_ref.conv3(c["e3a"], p["e3b.w"], p["e3b.b"], nm))
+    c["cat2"] = np.concatenate([nn_ref.up(c["b3"], p["u2.w"], p["u2.b"], nm), c["s2"]], axis=1)
+    c["d2a"] = relu(nn_ref.conv3(c["cat2"], p["d2a.w"], p["d2a.b"], nm))
+    c["d2"] = relu(nn_ref.conv3(c["d2a"], p["d2b.w"], p["d2b.b"], nm))
+    c["cat1"] = np.concatenate([nn_ref.up(c["d2"], p["u1.w"], p["u1.b"], nm), c["s1"]], axis=1)
+    c["d1a"] = relu(nn_ref.conv3(c["cat1"], p["d1a.w"], p["d1a.b"], nm))
+    c["d1"] = relu(nn_ref.conv3(c["d1a"], p["d1b.w"], p["d1b.b"], nm))
+    logit = nm.s(np.einsum("c,bcyx->byx", nm.q(p["out.w"][0]), nm.q(c["d1"])) + p["out.b"][0])
     return logit, c, p
 
 
-def loss_and_grad(theta, st, labels):
+def loss_and_grad(theta, st, labels, nm=nn_ref.EXACT):
     """Mean binary cross-entropy and its gradient with respect to theta."""
-    logit, c, p = forward(theta, st)
-    loss, dl = nn_ref.bce(logit, labels.astype(np.float64))
+    logit, c, p = forward(theta, st, nm)
+    loss, dl = nn_ref.bce(logit, labels.astype(np.float64), nm)
     g = {}
-    g["out.w"] = np.einsum("byx,bcyx->c", dl, c["d1"])[None]
-    g["out.b"] = np.array([dl.sum()])
-    dd1 = p["out.w"][0][None, :, None, None] * dl[:, None] * (c["d1"] > 0)
-    dd1a, g["d1b.w"], g["d1b.b"] = nn_ref.conv3_bwd(c["d1a"], p["d1b.w"], dd1)
+    g["out.w"] = nm.s(np.einsum("byx,bcyx->c", nm.q(dl), nm.q(c["d1"])))[None]
+    g["out.b"] = nm.s(np.array([dl.sum()]))
+    dd1 = nm.s(nm.q(p["out.w"][0])[None, :, None, None] * nm.q(dl)[:, None]) * (c["d1"] > 0)
+    dd1a, g["d1b.w"], g["d1b.b"] = nn_ref.conv3_bwd(c["d1a"], p["d1b.w"], dd1, nm)
     dd1a = dd1a * (c["d1a"] > 0)
-    dcat1, g["d1a.w"], g["d1a.b"] = nn_ref.conv3_bwd(c["cat1"], p["d1a.w"], dd1a)
-    dd2, g["u1.w"], g["u1.b"] = nn_ref.up_bwd(c["d2"], p["u1.w"], dcat1[:, :32])
+    dcat1, g["d1a.w"], g["d1a.b"] = nn_ref.conv3_bwd(c["cat1"], p["d1a.w"], dd1a, nm)
+    dd2, g["u1.w"], g["u1.b"] = nn_ref.up_bwd(c["d2"], p["u1.w"], dcat1[:, :32], nm)
     ds1 = dcat1[:, 32:]
     dd2 = dd2 * (c["d2"] > 0)
-    dd2a, g["d2b.w"], g["d2b.b"] = nn_ref.conv3_bwd(c["d2a"], p["d2b.w"], dd2)
+    dd2a, g["d2b.w"], g["d2b.b"] = nn_ref.conv3_bwd(c["d2a"], p["d2b.w"], dd2, nm)
     dd2a = dd2a * (c["d2a"] > 0)
-    dcat2, g["d2a.w"], g["d2a.b"] = nn_ref.conv3_bwd(c["cat2"], p["d2a.w"], dd2a)
-    db3, g["u2.w"], g["u2.b"] = nn_ref.up_bwd(c["b3"], p["u2.w"], dcat2[:, :64])
+    dcat2, g["d2a.w"], g["d2a.b"] = nn_ref.conv3_bwd(c["cat2"], p["d2a.w"], dd2a, nm)
+    db3, g["u2.w"], g["u2.b"] = nn_ref.up_bwd(c["b3"], p["u2.w"], dcat2[:, :64], nm)
     ds2 = dcat2[:, 64:]
     db3 = db3 * (c["b3"] > 0)
-    de3a, g["e3b.w"], g["e3b.b"] = nn_ref.conv3_bwd(c["e3a"], p["e3b.w"], db3)
+    de3a, g["e3b.w"], g["e3b.b"] = nn_ref.conv3_bwd(c["e3a"], p["e3b.w"], db3, nm)
     de3a = de3a * (c["e3a"] > 0)
-    dp2, g["e3a.w"], g["e3a.b"] = nn_ref.conv3_bwd(c["p2"], p["e3a.w"], de3a)
-    ds2 = (ds2 + nn_ref.pool_bwd(dp2, c["arg2"], c["s2"].shape)) * (c["s2"] > 0)
-    de2a, g["e2b.w"], g["e2b.b"] = nn_ref.conv3_bwd(c["e2a"], p["e2b.w"], ds2)
+    dp2, g["e3a.w"], g["e3a.b"] = nn_ref.conv3_bwd(c["p2"], p["e3a.w"], de3a, nm)
+    ds2 = nm.s(ds2 + nn_ref.pool_bwd(dp2, c["arg2"], c["s2"].shape)) * (c["s2"] > 0)
+    de2a, g["e2b.w"], g["e2b.b"] = nn_ref.conv3_bwd(c["e2a"], p["e2b.w"], ds2, nm)
     de2a = de2a * (c["e2a"] > 0)
-    dp1, g["e2a.w"], g["e2a.b"] = nn_ref.conv3_bwd(c["p1"], p["e2a.w"], de2a)
-    ds1 = (ds1 + nn_ref.pool_bwd(dp1, c["arg1"], c["s1"].shape)) * (c["s1"] > 0)
-    de1a, g["e1b.w"], g["e1b.b"] = nn_ref.conv3_bwd(c["e1a"], p["e1b.w"], ds1)
+    dp1, g["e2a.w"], g["e2a.b"] = nn_ref.conv3_bwd(c["p1"], p["e2a.w"], de2a, nm)
+    ds1 = nm.s(ds1 + nn_ref.pool_bwd(dp1, c["arg1"], c["s1"].shape)) * (c["s1"] > 0)
+    de1a, g["e1b.w"], g["e1b.b"] = nn_ref.conv3_bwd(c["e1a"], p["e1b.w"], ds1, nm)
     de1a = de1a * (c["e1a"] > 0)
-    _, g["e1a.w"], g["e1a.b"] = nn_ref.conv3_bwd(c["x"], p["e1a.w"], de1a)
+    _, g["e1a.w"], g["e1a.b"] = nn_ref.conv3_bwd(c["x"], p["e1a.w"], de1a, nm)
     return loss, pack(g)
