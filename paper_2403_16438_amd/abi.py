@@ -10,7 +10,10 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libseg.so")
+# SEG_LIBRARY selects another build of the same library, e.g. the one whose
+# host code is instrumented with address and undefined-behaviour sanitizers
+# (build.build_sanitized)
+LIB_PATH = os.environ.get("SEG_LIBRARY") or os.path.join(HERE, "libseg.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "seg.h")
 
 SEG_OK = 0

@@ -37,5 +37,29 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def asan_runtime() -> str:
+    """Path of the toolchain's address-sanitizer runtime (to preload into a
+    Python process that loads the sanitized library)."""
+    return subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True,
+                          text=True, check=True).stdout.strip()
+
+
+def build_sanitized(out: str) -> str:
+    """The same library with its host code instrumented by the address and
+    undefined-behaviour sanitizers (device code unchanged), for the CPU
+    checks of the host logic; load it with SEG_LIBRARY=<out> and the runtime
+    of asan_runtime() preloaded."""
+    subprocess.run([sys.executable, os.path.join(CSRC, "gen_selnet.py"), os.path.join(CSRC, "selnet_gen.h")],
+                   check=True, stdout=subprocess.DEVNULL)
+    host_only = "-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined"
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"] + host_only.split() + [
+        "-Xarch_host", "-fno-omit-frame-pointer", "-shared-libsan"]
+    cmd = [HIPCC] + flags + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
