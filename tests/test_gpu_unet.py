@@ -5,8 +5,10 @@ Bars:
 - patches bit-exact against the reference;
 - the weighted merge within 1e-6 (the GPU accumulates in FP64 and rounds to
   FP32);
-- loss and gradients against the FP64 reference at the same BF16 weights,
-  as for the frame network (every product rounds its operands to BF16);
+- loss, gradients and probabilities against the FP64 reference at the same
+  BF16 weights in its BF16 numerics mode (every product rounds its operands
+  to BF16, tensors are stored in FP32, as in the kernels): every layer's
+  gradient within 2e-2 norm-wise, on every convolution path;
 - the session's probability maps bit-identical to the network run on the
   session's own S and T;
 - after training on simulated summary pairs, segmentation of held-out
@@ -66,6 +68,19 @@ def case():
     return st, labels, theta
 
 
+BF16 = nn_ref.Numerics(bf16=True)
+
+
+def _per_layer(g, rg):
+    errs, cos = {}, {}
+    for name, r, c, wo, bo in param_layout():
+        sl = slice(wo, bo + nn_ref.bias_len(name, r))
+        den = np.linalg.norm(rg[sl])
+        errs[name] = np.linalg.norm(g[sl] - rg[sl]) / max(den, 1e-30)
+        cos[name] = float(g[sl] @ rg[sl] / max(np.linalg.norm(g[sl]) * den, 1e-30))
+    return errs, cos
+
+
 def _ref_theta(theta):
     t = theta.astype(np.float64).copy()
     for name, r, c, wo, bo in param_layout():
@@ -78,25 +93,23 @@ def test_loss_and_gradients_vs_reference(case):
     net = SummaryUNet(2, 16, 16, theta)
     loss, g = net.backward(torch.from_numpy(st).to(DEV), torch.from_numpy(labels).to(DEV), want_grad=True)
     g = g.cpu().numpy().astype(np.float64)
-    rloss, rg = unet_st.loss_and_grad(_ref_theta(theta), st.astype(np.float64), labels)
-    assert abs(loss - rloss) <= 1e-2 * abs(rloss), (loss, rloss)
-    errs, cos = {}, {}
-    for name, r, c, wo, bo in param_layout():
-        sl = slice(wo, bo + nn_ref.bias_len(name, r))
-        den = np.linalg.norm(rg[sl])
-        errs[name] = np.linalg.norm(g[sl] - rg[sl]) / max(den, 1e-30)
-        cos[name] = float(g[sl] @ rg[sl] / max(np.linalg.norm(g[sl]) * den, 1e-30))
-    assert min(cos.values()) >= 0.99, cos
-    assert max(errs[k] for k in ("out", "d1b", "d1a", "u1", "d2b")) <= 3e-2, errs
-    assert max(errs.values()) <= 0.15, errs
+    rloss, rg = unet_st.loss_and_grad(_ref_theta(theta), st.astype(np.float64), labels, BF16)
+    errs, cos = _per_layer(g, rg)
+    print("loss", loss, "reference", rloss)
+    print("norm-wise gradient error per layer (BF16 reference):", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 2e-2, errs
+    assert min(cos.values()) >= 0.999, cos
+    assert abs(loss - rloss) <= 2e-3 * abs(rloss), (loss, rloss)
 
 
 def test_forward_probabilities(case):
     st, labels, theta = case
     net = SummaryUNet(2, 16, 16, theta)
     p = net.forward(torch.from_numpy(st).to(DEV)).cpu().numpy()
-    logit, _, _ = unet_st.forward(_ref_theta(theta), st.astype(np.float64))
-    assert np.abs(p - 1.0 / (1.0 + np.exp(-logit))).max() <= 2e-2
+    logit, _, _ = unet_st.forward(_ref_theta(theta), st.astype(np.float64), BF16)
+    err = np.abs(p - 1.0 / (1.0 + np.exp(-logit)))
+    print("prob error max", err.max(), "mean", err.mean())
+    assert err.mean() <= 2e-3 and err.max() <= 2e-2
 
 
 @pytest.mark.parametrize("B,H,W", [(1, 24, 24), (2, 24, 40), (2, 32, 16)])
@@ -120,23 +133,24 @@ def test_convolution_paths_vs_reference(B, H, W):
     sd = torch.from_numpy(st).to(DEV)
     p = net.forward(sd).cpu().numpy()
     rt = _ref_theta(theta)
-    logit, _, _ = unet_st.forward(rt, st.astype(np.float64))
-    # BF16 operands through 13 layers, logits here up to |20|: measured mean
-    # error about 1.5e-3, max about 0.03 at interior pixels; an indexing or
-    # padding mistake moves many pixels by 0.1 or more
+    # against the reference in its BF16 numerics mode (operands of every
+    # product rounded to BF16, tensors stored in FP32, as the kernels do)
+    logit, _, _ = unet_st.forward(rt, st.astype(np.float64), BF16)
     err = np.abs(p - 1.0 / (1.0 + np.exp(-logit)))
     print("prob error max", err.max(), "mean", err.mean(), "logit range", logit.min(), logit.max())
-    assert err.mean() <= 5e-3 and err.max() <= 6e-2
     loss, g = net.backward(sd, torch.from_numpy(labels).to(DEV), want_grad=True)
     g = g.cpu().numpy().astype(np.float64)
-    rloss, rg = unet_st.loss_and_grad(rt, st.astype(np.float64), labels)
-    assert abs(loss - rloss) <= 1e-2 * abs(rloss), (loss, rloss)
-    for name, r, c, wo, bo in param_layout():
-        sl = slice(wo, bo + nn_ref.bias_len(name, r))
-        den = np.linalg.norm(rg[sl])
-        cos = float(g[sl] @ rg[sl] / max(np.linalg.norm(g[sl]) * den, 1e-30))
-        assert cos >= 0.99, (name, cos)
+    rloss, rg = unet_st.loss_and_grad(rt, st.astype(np.float64), labels, BF16)
+    errs, cos = _per_layer(g, rg)
     print("loss", loss, "reference", rloss)
+    print("norm-wise gradient error per layer (BF16 reference):", {k: f"{v:.1e}" for k, v in errs.items()})
+    # what remains are BF16 roundings that FP32 accumulation (GPU) and FP64
+    # sums (reference) put on either side of a rounding boundary; an indexing
+    # or padding mistake moves many pixels by 0.1 or more
+    assert err.mean() <= 2e-3 and err.max() <= 3e-2
+    assert max(errs.values()) <= 2e-2, errs
+    assert min(cos.values()) >= 0.999, cos
+    assert abs(loss - rloss) <= 2e-3 * abs(rloss), (loss, rloss)
     net.close()
 
 
