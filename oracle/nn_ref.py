@@ -91,9 +91,19 @@ EXACT = Numerics()
 # ---------------------------------------------------------------- ops
 
 def normalise(frames, nm=EXACT):
+    """(V - mean) / sqrt(mean + 25) per pixel over the segment's frames. In
+    the BF16 mode each operation rounds to FP32 as a single-precision
+    evaluation does: the integer sum (exact), mean = sum / T, the reciprocal
+    root of mean + 25, then (V - mean) times it."""
+    if nm.bf16:
+        f32 = np.float32
+        v = frames.astype(f32)
+        m = (v.sum(axis=1, keepdims=True, dtype=np.float64).astype(f32) / f32(frames.shape[1])).astype(f32)
+        inv = (f32(1.0) / np.sqrt(m + f32(25.0))).astype(f32)
+        return ((v - m) * inv).astype(f32).astype(np.float64)
     v = frames.astype(np.float64)                    # [B][T][H][W]
     m = v.mean(axis=1, keepdims=True)
-    return nm.s((v - m) / np.sqrt(m + 25.0))
+    return (v - m) / np.sqrt(m + 25.0)
 
 
 def tconv(x, W, b, stride, pad, tout, nm=EXACT):

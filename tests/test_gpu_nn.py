@@ -1,6 +1,8 @@
 """Surrogate detector on the GPU: the BF16 MFMA product against an exact
-product of the BF16-rounded operands, and the network's loss and gradients
-against the FP64 reference (oracle/nn_ref.py) at the same BF16 weights."""
+product of the BF16-rounded operands, and the network's loss, gradients and
+probabilities against the FP64 reference (oracle/nn_ref.py) at the same BF16
+weights, in its BF16 numerics mode (operands of every product rounded to BF16,
+tensors stored in FP32, as the kernels do): every layer within 2e-2."""
 import numpy as np
 import pytest
 import torch
@@ -49,38 +51,53 @@ def _ref_theta(theta):
     return t
 
 
-def test_loss_and_gradients_vs_reference(case):
-    frames, labels, theta = case
-    sur = Surrogate(2, 16, 16, theta)
-    fd = torch.from_numpy(frames.view(np.int16)).cuda()
-    ld = torch.from_numpy(labels).cuda()
-    loss, g = sur.backward(fd, ld, want_grad=True)
-    g = g.cpu().numpy().astype(np.float64)
-    rloss, rg = nn_ref.loss_and_grad(_ref_theta(theta), frames, labels)
-    assert abs(loss - rloss) <= 1e-2 * abs(rloss), (loss, rloss)
-    # Every GEMM rounds both operands to BF16 (relative 2^-9), and forward
-    # rounding flips a few ReLU / max-pool decisions relative to FP64, so the
-    # norm-wise error grows with the number of layers a gradient crosses:
-    # measured 0.1 % at the output layer, ~1 % through the decoder, ~10 % at
-    # the first temporal layer. Directions must agree everywhere.
+def _per_layer(g, rg):
     errs, cos = {}, {}
     for name, r, c, wo, bo in param_layout():
         sl = slice(wo, bo + (r // 4 if name in ("u2", "u1") else r))
         den = np.linalg.norm(rg[sl])
         errs[name] = np.linalg.norm(g[sl] - rg[sl]) / max(den, 1e-30)
         cos[name] = float(g[sl] @ rg[sl] / max(np.linalg.norm(g[sl]) * den, 1e-30))
-    assert min(cos.values()) >= 0.99, cos
-    assert max(errs[k] for k in ("out", "d1b", "d1a", "u1", "d2b")) <= 3e-2, errs
-    assert max(errs.values()) <= 0.15, errs
+    return errs, cos
+
+
+def test_loss_and_gradients_vs_reference(case):
+    """Against the reference in its BF16 numerics mode, which rounds both
+    operands of every product to BF16 and stores tensors in FP32 where the
+    kernels do: every layer's weight and bias gradient within 2e-2
+    norm-wise. The exact FP64 reference differs by the BF16 operand rounding
+    itself (measured 0.1 % at the output layer to about 10 % at the first
+    temporal layer), so against it only the directions are held."""
+    frames, labels, theta = case
+    sur = Surrogate(2, 16, 16, theta)
+    fd = torch.from_numpy(frames.view(np.int16)).cuda()
+    ld = torch.from_numpy(labels).cuda()
+    loss, g = sur.backward(fd, ld, want_grad=True)
+    g = g.cpu().numpy().astype(np.float64)
+    rloss, rg = nn_ref.loss_and_grad(_ref_theta(theta), frames, labels, nn_ref.Numerics(bf16=True))
+    errs, cos = _per_layer(g, rg)
+    _, rg64 = nn_ref.loss_and_grad(_ref_theta(theta), frames, labels)
+    errs64, cos64 = _per_layer(g, rg64)
+    print("loss", loss, "reference", rloss)
+    print("norm-wise gradient error per layer, BF16 reference:", {k: f"{v:.1e}" for k, v in errs.items()})
+    print("norm-wise gradient error per layer, FP64 reference:", {k: f"{v:.1e}" for k, v in errs64.items()})
+    assert max(errs.values()) <= 2e-2, errs
+    assert min(cos.values()) >= 0.999, cos
+    assert min(cos64.values()) >= 0.99, cos64
+    assert abs(loss - rloss) <= 2e-3 * abs(rloss), (loss, rloss)
 
 
 def test_forward_probabilities(case):
     frames, labels, theta = case
     sur = Surrogate(2, 16, 16, theta)
     p = sur.forward(torch.from_numpy(frames.view(np.int16)).cuda()).cpu().numpy()
-    logit, _, _ = nn_ref.forward(_ref_theta(theta), frames)
+    logit, _, _ = nn_ref.forward(_ref_theta(theta), frames, nn_ref.Numerics(bf16=True))
     ref = 1.0 / (1.0 + np.exp(-logit))
-    assert np.abs(p - ref).max() <= 2e-2
+    # what remains are BF16 roundings that FP32 accumulation (GPU) and FP64
+    # sums (reference) put on either side of a rounding boundary
+    err = np.abs(p - ref)
+    print("prob error max", err.max(), "mean", err.mean())
+    assert err.mean() <= 2e-3 and err.max() <= 2e-2
 
 
 def test_rmsprop_reduces_loss(case):

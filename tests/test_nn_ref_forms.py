@@ -164,3 +164,15 @@ def test_summary_unet_reference_uses_the_same_operators():
     _, c, p = unet_st.forward(theta, st)
     e1a = np.maximum(nn_ref.conv3(unet_st.normalise(st), p["e1a.w"], p["e1a.b"]), 0.0)
     assert np.array_equal(c["e1a"], e1a)
+
+
+def test_bf16_mode_normalisation_is_single_precision():
+    """In the BF16 mode the normalisation is evaluated in FP32 (each operation
+    rounded): on the hand values above it stays within a few FP32 ulps of the
+    exact one and is itself representable in FP32."""
+    f = np.full((1, 50, 2, 2), 975, np.uint16)
+    f[0, 7, 1, 0] = 1025
+    x = nn_ref.normalise(f, nn_ref.Numerics(bf16=True))
+    assert np.array_equal(x, x.astype(np.float32).astype(np.float64))
+    assert np.array_equal(x[0, :, 0, 0], np.zeros(50))
+    assert abs(x[0, 7, 1, 0] - 49.0 / np.sqrt(1001.0)) < 4 * np.spacing(np.float32(1.55))
