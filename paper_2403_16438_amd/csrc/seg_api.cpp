@@ -109,7 +109,8 @@ Layout make_layout(const seg_config& c) {
   if (c.detector == SEG_DET_UNET) {
     uint32_t np = 0;
     seg_nn_st_patch_count(c.height, c.width, &np);
-    stage = (size_t)np * 3 * 4096 * 4;   // patches (S, T) and their probabilities
+    // patches (S, T) and their probabilities of kUnetGroup segments
+    stage = (size_t)kUnetGroup * np * 3 * 4096 * 4;
   }
   l.stage = take(stage);
   l.total = o;
@@ -154,25 +155,34 @@ int surrogate_maps(seg_session* s, const uint16_t* dev_frames, uint32_t nseg, hi
 }
 
 // Summary-image U-Net: for segments first .. first + nseg - 1 (whose S and T
-// are written), cut the patches, run the network in batches and merge the
-// patch probabilities into p[k].
+// are written), cut the patches of up to kUnetGroup segments at a time, run
+// the network over all of them in batches of its size (so the small
+// low-resolution layers see more patches per launch), and merge each
+// segment's patch probabilities into p[k].
 int unet_maps(seg_session* s, uint32_t first, uint32_t nseg, hipStream_t st) {
   const size_t M = s->M;
   const uint32_t H = s->cfg.height, W = s->cfg.width;
   uint32_t np = 0, B = 0;
   if (seg_nn_st_patch_count(H, W, &np) || seg_nn_shape(s->net, &B, nullptr, nullptr)) return fail(s, hipErrorUnknown);
   float* in = at<float>(s, s->lay.stage);
-  float* prob = in + (size_t)np * 2 * 4096;
-  for (uint32_t j = 0; j < nseg; ++j) {
-    const size_t k = first + j;
-    if (seg_nn_st_patches(at<float>(s, s->lay.S) + k * M, at<float>(s, s->lay.T) + k * M, H, W, in, st))
-      return fail(s, hipErrorUnknown);
-    for (uint32_t a = 0; a < np; a += B) {
-      const uint32_t b = std::min(B, np - a);
+  float* prob = in + (size_t)seg::kUnetGroup * np * 2 * 4096;
+  for (uint32_t j0 = 0; j0 < nseg; j0 += seg::kUnetGroup) {
+    const uint32_t g = std::min<uint32_t>(seg::kUnetGroup, nseg - j0);
+    for (uint32_t q = 0; q < g; ++q) {
+      const size_t k = first + j0 + q;
+      if (seg_nn_st_patches(at<float>(s, s->lay.S) + k * M, at<float>(s, s->lay.T) + k * M, H, W,
+                            in + (size_t)q * np * 2 * 4096, st))
+        return fail(s, hipErrorUnknown);
+    }
+    const uint32_t total = g * np;
+    for (uint32_t a = 0; a < total; a += B) {
+      const uint32_t b = std::min(B, total - a);
       if (seg_nn_st_forward(s->net, in + (size_t)a * 2 * 4096, b, prob + (size_t)a * 4096, st))
         return fail(s, hipErrorUnknown);
     }
-    if (seg_nn_st_merge(prob, H, W, at<float>(s, s->lay.p) + k * M, st)) return fail(s, hipErrorUnknown);
+    for (uint32_t q = 0; q < g; ++q)
+      if (seg_nn_st_merge(prob + (size_t)q * np * 4096, H, W, at<float>(s, s->lay.p) + (first + j0 + q) * M, st))
+        return fail(s, hipErrorUnknown);
   }
   return SEG_OK;
 }

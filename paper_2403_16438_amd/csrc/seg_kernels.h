@@ -20,6 +20,7 @@ constexpr int kMaxRank = 8;       // NMF rank cap per component
 constexpr int kMaxDim = 2048;     // frame height / width limit
 constexpr int kMaxSegments = 4096;
 constexpr int kMaxBatch = 64;     // sessions per batched launch
+constexpr int kUnetGroup = 8;     // segments whose summary patches share network calls
 
 // ---- kernel launchers (defined in the .hip files) ----
 

@@ -91,11 +91,11 @@ class Batch:
             self.handle = None
 
     def __del__(self):
-        if lifetime.released_by_finalizer():
-            try:
+        try:   # at interpreter exit the lifetime module may already be torn down
+            if lifetime.released_by_finalizer():
                 self.close()
-            except Exception:
-                pass
+        except Exception:
+            pass
 
 
 @dataclass

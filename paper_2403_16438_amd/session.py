@@ -138,11 +138,11 @@ class Session:
             self.handle = None
 
     def __del__(self):
-        if lifetime.released_by_finalizer():
-            try:
+        try:   # at interpreter exit the lifetime module may already be torn down
+            if lifetime.released_by_finalizer():
                 self.close()
-            except Exception:
-                pass
+        except Exception:
+            pass
 
 
 def segment_video(video: np.ndarray, block: int | None = None, net=None, **overrides) -> Session:

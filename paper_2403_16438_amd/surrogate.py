@@ -102,11 +102,11 @@ class Surrogate:
             self.handle = None
 
     def __del__(self):
-        if lifetime.released_by_finalizer():
-            try:
+        try:   # at interpreter exit the lifetime module may already be torn down
+            if lifetime.released_by_finalizer():
                 self.close()
-            except Exception:
-                pass
+        except Exception:
+            pass
 
 
 def gemm_test(A: torch.Tensor, B: torch.Tensor, a_trans=False, b_trans=False, splits=1) -> torch.Tensor:

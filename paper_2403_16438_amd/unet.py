@@ -129,8 +129,8 @@ class SummaryUNet:
             self.handle = None
 
     def __del__(self):
-        if lifetime.released_by_finalizer():
-            try:
+        try:   # at interpreter exit the lifetime module may already be torn down
+            if lifetime.released_by_finalizer():
                 self.close()
-            except Exception:
-                pass
+        except Exception:
+            pass
