@@ -7,8 +7,8 @@
 // and the column-wise sweeps are free of bank conflicts. Everything that needs
 // all pixels of the component is a sum (or max) over pixels, so each
 // workgroup writes its partial over its own rows to an exchange slot in HBM,
-// the component's workgroups meet at a barrier, and each one adds the slots
-// of all workgroups in the same fixed order. They thus hold bit-identical
+// and each workgroup of the component waits for and adds the slots of all of
+// them in the same fixed order. They thus hold bit-identical
 // totals and take identical decisions without further communication:
 //   SPA     per step: partial squared column norms of the residual, then the
 //           partial projections onto the picked direction (two exchanges);
@@ -20,12 +20,24 @@
 //           the F rows it owns from its LDS rows of P_c
 //   scale   partial column maxima of F (one exchange)
 // The arithmetic is the single-workgroup kernel's (same update order, FP64,
-// clipping, zero-Gram rule); only the summation order over pixels differs.
+// clipping, zero-Gram rule); only the summation order of the sums differs.
+// A sweep has five workgroup barriers: after the F^T P partials, after the
+// gather, after the A update, after the P A^T partials and after the F
+// update; the Gram matrices are formed within one wave, which needs none.
 //
-// Barrier: a per-component arrival counter (agent-scope release/acquire).
-// The launch is cooperative, so all workgroups are resident; the wait is
-// still bounded by a wall-clock limit, after which the component is marked
-// abandoned, every workgroup of it leaves, and the error flag is set.
+// Exchange: every slot value travels as two 64-bit words (its high and low
+// halves), each tagged in its upper 32 bits with the number of the exchange
+// that wrote it, and written and read with relaxed agent-scope atomics. A
+// word read with the expected tag therefore holds that exchange's half
+// (single-copy atomicity of the word), so readers poll the slot words
+// themselves: no arrival counter, no fences, and the values are exact. Two
+// slots per workgroup alternate between exchanges; a workgroup can only
+// overwrite a slot after every workgroup of its component has read it (it
+// needs their next slots first), and the slots are cleared before each
+// launch, so a stale word never carries the expected tag. The launch is
+// cooperative, so all workgroups are resident; a wait is still bounded by a
+// wall-clock limit, after which the component is marked abandoned, every
+// workgroup of it leaves, and the error flag is set.
 #include <algorithm>
 #include <climits>
 #include <type_traits>
@@ -56,46 +68,40 @@ __device__ __forceinline__ void pair_of(int k, int& n1, int& n2) {
   n2 = n1 + k;
 }
 
-// Gram matrix X^T X of the first NR columns of X [len][R8] (LDS), by the 64
-// lanes of one wave: lane (chunk q, column n1) of QG = 64 / NR row chunks
-// sums its chunk for all n2 into part[(q NR + n1) R8 + n2] ...
+// X^T X of the first NR columns of X [len][R8] (LDS) by the 64 lanes of one
+// wave: lane (chunk q, entry p of the upper triangle) sums its chunk of rows
+// for entry p, the QG chunk partials go to part [QG][NP] (LDS), and lane p < NP
+// adds the partials of entry p in chunk order. Returns that total in lanes
+// p < NP (0 elsewhere). The wave needs no barrier: the LDS requests of a wave
+// complete in order.
 template <int NR>
-__device__ __forceinline__ void gram_part(const double* X, int len, int lane, double* part) {
-  constexpr int QG = 64 / NR;
-  if (lane >= QG * NR) return;
-  const int q = lane / NR, n1 = lane - q * NR;
-  const int span = (len + QG - 1) / QG, j1 = min(len, (q + 1) * span);
-  double s0[NR], s1[NR];
-#pragma unroll
-  for (int n = 0; n < NR; ++n) s0[n] = s1[n] = 0.0;
-  int j = q * span;
-  for (; j + 1 < j1; j += 2) {
-    const double x0 = X[j * R8 + n1], x1 = X[(j + 1) * R8 + n1];
-#pragma unroll
-    for (int n = 0; n < NR; ++n) {
-      s0[n] = fma(x0, X[j * R8 + n], s0[n]);
-      s1[n] = fma(x1, X[(j + 1) * R8 + n], s1[n]);
+__device__ __forceinline__ double gram_wave(const double* X, int len, int lane, double* part) {
+  constexpr int NP = NR * (NR + 1) / 2;
+  constexpr int QG = NP <= 4 ? 16 : NP <= 8 ? 8 : NP <= 16 ? 4 : NP <= 32 ? 2 : 1;
+  if (lane < QG * NP) {
+    const int q = lane / NP, p = lane - q * NP;
+    int n1, n2;
+    pair_of<NR>(p, n1, n2);
+    const int span = (len + QG - 1) / QG, j1 = min(len, (q + 1) * span);
+    double g0 = 0.0, g1 = 0.0;
+    int j = q * span;
+    for (; j + 1 < j1; j += 2) {
+      g0 = fma(X[j * R8 + n1], X[j * R8 + n2], g0);
+      g1 = fma(X[(j + 1) * R8 + n1], X[(j + 1) * R8 + n2], g1);
     }
+    if (j < j1) g0 = fma(X[j * R8 + n1], X[j * R8 + n2], g0);
+    part[q * NP + p] = g0 + g1;
   }
-  if (j < j1) {
-    const double x0 = X[j * R8 + n1];
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  double v = 0.0;
+  if (lane < NP) {
+    double x[QG];
 #pragma unroll
-    for (int n = 0; n < NR; ++n) s0[n] = fma(x0, X[j * R8 + n], s0[n]);
+    for (int q = 0; q < QG; ++q) x[q] = part[q * NP + lane];
+    v = x[0];
+#pragma unroll
+    for (int q = 1; q < QG; ++q) v += x[q];
   }
-#pragma unroll
-  for (int n = 0; n < NR; ++n) part[(q * NR + n1) * R8 + n] = s0[n] + s1[n];
-}
-
-// ... and entry k = n1 NR + n2 of the total, all QG chunks added in order
-// (chunks past the data hold zeros); the bound is a constant, so the loads
-// are issued ahead of the dependent adds
-template <int NR>
-__device__ __forceinline__ double gram_total(int k, const double* part) {
-  constexpr int QG = 64 / NR;
-  const int n1 = k / NR, n2 = k - n1 * NR;
-  double v = part[n1 * R8 + n2];
-#pragma unroll 8
-  for (int q = 1; q < QG; ++q) v += part[(q * NR + n1) * R8 + n2];
   return v;
 }
 
@@ -154,45 +160,40 @@ __device__ void block_argmax(double v, int idx, double* red, int* redi, double* 
   __syncthreads();
 }
 
-// Slot writes are agent-scope stores: they go through to the level where all
-// XCDs see them, so the release at the meeting finds no dirty slot lines to
-// write back from the L2.
-__device__ __forceinline__ void put(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+using u64 = unsigned long long;
+
+__device__ __forceinline__ void put_word(u64* p, unsigned tag, unsigned half) {
+  __hip_atomic_store(p, ((u64)tag << 32) | half, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// All workgroups of one component meet here; `target` is the number of
-// arrivals that completes this meeting. Returns false when the component was
-// abandoned (time limit), uniformly for the whole workgroup.
-__device__ bool meet(unsigned* arrivals, unsigned* abandoned, unsigned* error, unsigned target,
-                     long long limit, int* flag) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    // release the workgroup's slot writes, arrive, poll without acquiring
-    // (an acquire per poll would invalidate the caches every time), then
-    // acquire once
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_fetch_add(arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int ok = 1;
-    const long long t0 = wall_clock64();
-    while (__hip_atomic_load(arrivals, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(abandoned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-        ok = 0;
-        break;
-      }
-      if (wall_clock64() - t0 > limit) {
-        __hip_atomic_store(abandoned, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
+__device__ __forceinline__ u64 get_word(u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool tagged(u64 w, unsigned tag) { return (unsigned)(w >> 32) == tag; }
+
+// Waits until both halves at p and p + xs carry `tag` and returns them;
+// ok is false when the component was abandoned or the wall-clock limit
+// passed (then it marks the component abandoned and sets the error flag).
+struct Halves {
+  u64 hi, lo;
+  bool ok;
+};
+__device__ __forceinline__ Halves wait_words(u64* p, int xs, unsigned tag, unsigned* abandoned,
+                                             unsigned* error, long long limit) {
+  const long long t0 = wall_clock64();
+  for (unsigned n = 0;; ++n) {
+    __builtin_amdgcn_s_sleep(2);
+    const u64 hi = get_word(p), lo = get_word(p + xs);
+    if (tagged(hi, tag) && tagged(lo, tag)) return {hi, lo, true};
+    if ((n & 15) == 15 && __hip_atomic_load(abandoned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+      return {0, 0, false};
+    if (wall_clock64() - t0 > limit) {
+      __hip_atomic_store(abandoned, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return {0, 0, false};
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    *flag = ok;
   }
-  __syncthreads();
-  return *flag != 0;
 }
 
 __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
@@ -202,61 +203,80 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
   __shared__ double gF[R8 * R8], gA[R8 * R8];
   __shared__ double gpart[64 * R8];   // Gram chunk sums (64 lanes x R8)
   __shared__ int picks[R8];
-  __shared__ int flag;
+  __shared__ int bad;
   const int g = blockIdx.x, t = threadIdx.x;
   const int c = s.wg_comp[g];
   const int w0 = s.wg_base[c], nw = s.wg_n[c], r = g - w0;
   const int off = a.coff[c], Mc = a.coff[c + 1] - off;
   const int mw = s.mw, lo = r * mw, ml = min(mw, Mc - lo);  // own rows [lo, lo + ml)
-  const int K = a.K, Kp = s.Kp;
-  // LDS: A [K][R8], F [mw][R8], P A^T [mw][R8], scratch [scr], P rows [mw][Kp] (float)
+  const int K = a.K, Kp = s.Kp, XS = s.XS;
+  // LDS: A [K][R8], F [mw][R8], F^T P totals [R8][K], scratch [scr], P rows [mw][Kp] (float)
   double* A = dyn;
   double* F = A + (size_t)K * R8;
-  double* GP = F + (size_t)mw * R8;
-  double* scr = GP + (size_t)mw * R8;
+  double* FtP = F + (size_t)mw * R8;
+  double* scr = FtP + (size_t)R8 * K;
   float* Pl = reinterpret_cast<float*>(scr + s.scr);
   double* R = a.R + (long long)(off + lo) * K;  // own residual rows [ml][K], HBM
-  unsigned* arrivals = s.sync + c;
-  unsigned* abandoned = s.sync + a.ncomp + c;
-  unsigned* error = s.sync + 2 * a.ncomp;
+  unsigned* abandoned = s.sync + c;
+  unsigned* error = s.sync + a.ncomp;
   unsigned ex = 0;  // exchanges done
-  auto slot = [&](int w, unsigned e) { return s.xbuf + ((size_t)(w0 + w) * 2 + (e & 1)) * s.XS; };
-  // sum (or max) of element j over the component's slots of exchange e, in
-  // slot order; sixteen loads are in flight at a time
-  auto gather = [&](size_t j, unsigned e, bool take_max) {
-    double v = 0.0;
-    for (int wb = 0; wb < nw; wb += 16) {
-      double x[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) x[q] = wb + q < nw ? slot(wb + q, e)[j] : 0.0;
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (wb + q < nw) v = take_max ? fmax(v, x[q]) : v + x[q];
-    }
-    return v;
+  bool dead = false;  // this thread gave up waiting (the workgroup leaves at the next check)
+  if (t == 0) bad = 0;
+  // slot of workgroup w for exchange e: XS high words, then XS low words
+  auto slot = [&](int w, unsigned e) { return s.xbuf + ((size_t)(w0 + w) * 2 + (e & 1)) * 2 * XS; };
+  // element j of this workgroup's slot for exchange e
+  auto put = [&](unsigned e, size_t j, double v) {
+    u64* p = slot(r, e) + j;
+    const u64 b = (u64)__double_as_longlong(v);
+    put_word(p, e + 1, (unsigned)(b >> 32));
+    put_word(p + XS, e + 1, (unsigned)b);
   };
-  // two elements at once, twelve slots per round of memory latency
-  auto gather2 = [&](size_t j0, size_t j1, unsigned e, double& v0, double& v1) {
-    v0 = 0.0;
-    v1 = 0.0;
+  // sum (or max) of element j over the component's slots of exchange e, in
+  // slot order, waiting for each slot's words; twelve slots per round of
+  // memory latency
+  auto gather = [&](size_t j, unsigned e, bool take_max) {
+    const unsigned tag = e + 1;
+    double v = 0.0;
+    if (dead) return v;
     for (int wb = 0; wb < nw; wb += 12) {
-      double x[12], y[12];
+      u64 hi[12], lw[12];
+      // all 24 loads go out before the first use (slots past the last are
+      // read as the last one and not used)
 #pragma unroll
       for (int q = 0; q < 12; ++q) {
-        const double* sp = slot(wb + q, e);
-        x[q] = wb + q < nw ? sp[j0] : 0.0;
-        y[q] = wb + q < nw ? sp[j1] : 0.0;
+        u64* p = slot(min(wb + q, nw - 1), e) + j;
+        hi[q] = get_word(p);
+        lw[q] = get_word(p + XS);
       }
+      asm volatile("" : "+v"(hi[0]), "+v"(hi[1]), "+v"(hi[2]), "+v"(hi[3]), "+v"(hi[4]), "+v"(hi[5]),
+                        "+v"(hi[6]), "+v"(hi[7]), "+v"(hi[8]), "+v"(hi[9]), "+v"(hi[10]), "+v"(hi[11]),
+                        "+v"(lw[0]), "+v"(lw[1]), "+v"(lw[2]), "+v"(lw[3]), "+v"(lw[4]), "+v"(lw[5]),
+                        "+v"(lw[6]), "+v"(lw[7]), "+v"(lw[8]), "+v"(lw[9]), "+v"(lw[10]), "+v"(lw[11]));
 #pragma unroll
       for (int q = 0; q < 12; ++q)
         if (wb + q < nw) {
-          v0 += x[q];
-          v1 += y[q];
+          if (!tagged(hi[q], tag) || !tagged(lw[q], tag)) {
+            const Halves h = dead ? Halves{0, 0, false}
+                                  : wait_words(slot(wb + q, e) + j, XS, tag, abandoned, error, s.limit);
+            if (!h.ok) {
+              dead = true;
+              bad = 1;
+              return 0.0;
+            }
+            hi[q] = h.hi;
+            lw[q] = h.lo;
+          }
+          const double x = __longlong_as_double((long long)((hi[q] << 32) | (lw[q] & 0xffffffffull)));
+          v = take_max ? fmax(v, x) : v + x;
         }
     }
+    return v;
   };
-#define MEET() \
-  if (!meet(arrivals, abandoned, error, (ex + 1) * (unsigned)nw, s.limit, &flag)) return
+  __syncthreads();
+// leave when any thread of the workgroup gave up waiting (read after a barrier)
+#define LEAVE_IF_ABANDONED(ret) \
+  __syncthreads();              \
+  if (bad) return ret
 
   // gather own rows: consecutive threads read consecutive pixels of a plane
   for (int e = t; e < ml * K; e += CT) {
@@ -277,9 +297,8 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
   int N = 0;
   double ref = 0.0;
   while (N < a.max_rank) {
-    {
-      double* xs = slot(r, ex);
-      for (int i = t; i < K; i += CT) {
+    for (int i = t; i < K; i += CT) {
+      {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int m = 0;
         for (; m + 4 <= ml; m += 4) {
@@ -294,10 +313,9 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
           const double v = R[(long long)m * K + i];
           s0 += v * v;
         }
-        put(xs + i, (s0 + s1) + (s2 + s3));
+        put(ex, i, (s0 + s1) + (s2 + s3));
       }
     }
-    MEET();
     double bv = -1.0;
     int bi = INT_MAX;
     for (int i = t; i < K; i += CT) {
@@ -310,6 +328,7 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
       }
     }
     ++ex;
+    LEAVE_IF_ABANDONED();
     double best;
     int j;
     block_argmax(bv, bi, red, redi, &best, &j);
@@ -320,9 +339,8 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
     ++N;
     for (int m = t; m < ml; m += CT) U[m] = R[(long long)m * K + j] / best;
     __syncthreads();
-    {
-      double* xs = slot(r, ex);
-      for (int i = t; i < K; i += CT) {
+    for (int i = t; i < K; i += CT) {
+      {
         double s0 = 0.0, s1 = 0.0;
         int m = 0;
         for (; m + 2 <= ml; m += 2) {
@@ -330,15 +348,14 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
           s1 += U[m + 1] * R[(long long)(m + 1) * K + i];
         }
         if (m < ml) s0 += U[m] * R[(long long)m * K + i];
-        put(xs + i, s0 + s1);
+        put(ex, i, s0 + s1);
       }
     }
-    MEET();
     for (int i = t; i < K; i += CT) {
       vec[i] = gather(i, ex, false);
     }
     ++ex;
-    __syncthreads();
+    LEAVE_IF_ABANDONED();
     for (int e = t; e < ml * K; e += CT) {
       const int m = e / K, i = e - m * K;
       R[e] -= U[m] * vec[i];
@@ -349,17 +366,13 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
 
   if (N > 0) {
     // ---------------------------------------------- initial footprints
-    {
-      double* xs = slot(r, ex);
-      for (int n = 0; n < N; ++n) {
-        const int col = picks[n];
-        double mx = 0.0;
-        for (int m = t; m < ml; m += CT) mx = fmax(mx, (double)Pl[m * Kp + col]);
-        mx = block_max(mx, red);
-        if (t == 0) put(xs + n, mx);
-      }
+    for (int n = 0; n < N; ++n) {
+      const int col = picks[n];
+      double mx = 0.0;
+      for (int m = t; m < ml; m += CT) mx = fmax(mx, (double)Pl[m * Kp + col]);
+      mx = block_max(mx, red);
+      if (t == 0) put(ex, n, mx);
     }
-    MEET();
     for (int m = t; m < ml; m += CT)
       for (int n = 0; n < R8; ++n) {
         double v = 0.0;
@@ -370,20 +383,21 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
       }
     ++ex;
     for (int e = t; e < K * R8; e += CT) A[e] = 0.0;
-    __syncthreads();
+    LEAVE_IF_ABANDONED();
 
     // HALS, compiled per rank so that the sequential row/column updates run
     // without predication
     auto hals = [&](auto rank) -> bool {
       constexpr int NR = decltype(rank)::value;
       constexpr int NP = NR * (NR + 1) / 2;
-      double* FtP = scr;                    // [NR][K] totals (after the meeting)
       for (int sweep = -1; sweep < a.sweeps; ++sweep) {
         // ---- partial F^T P and F^T F over own rows (FP64, fixed order),
         // written to this workgroup's slot. Waves 0..14: thread (row chunk
-        // q, segment i) sums its rows for all NR columns of F. Wave 15: F^T
-        // F, lane (row chunk q, column n1). Chunks are then added in order.
-        double* xs = slot(r, ex);
+        // q, segment i) sums its rows for all NR columns of F; after the
+        // barrier the chunks are added in order and written to the slot,
+        // and the gather of the totals follows without another barrier.
+        // Wave 15: F^T F, whole within the wave (gram_wave), straight to the
+        // slot.
         {
           const int QC = max(1, min(min(CV / K, 8), s.scr / (K * NR)));
           const int rows = (ml + QC - 1) / QC;
@@ -410,42 +424,40 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
               }
 #pragma unroll
               for (int n = 0; n < NR; ++n) {
-                if (QC == 1) put(xs + n * K + i, s0[n] + s1[n]);
+                if (QC == 1) put(ex, (size_t)n * K + i, s0[n] + s1[n]);
                 else scr[(size_t)e * NR + n] = s0[n] + s1[n];
               }
             }
-          } else {
-            gram_part<NR>(F, ml, t - CV, gpart);
+          } else {   // F^T F of the own rows, upper triangle
+            const double v = gram_wave<NR>(F, ml, t - CV, gpart);
+            if (t - CV < NP) {
+              int n1, n2;
+              pair_of<NR>(t - CV, n1, n2);
+              put(ex, (size_t)R8 * K + n1 * R8 + n2, v);
+            }
           }
           __syncthreads();
           if (QC > 1)
             for (int o = t; o < NR * K; o += CT) {
               const int n = o / K, i = o - n * K;
-              put(xs + o, chunk_sum(scr + (size_t)i * NR + n, (size_t)K * NR, QC));
+              put(ex, o, chunk_sum(scr + (size_t)i * NR + n, (size_t)K * NR, QC));
             }
-          if (t < NR * NR) put(xs + R8 * K + (t / NR) * R8 + t % NR, gram_total<NR>(t, gpart));
         }
-        if (!meet(arrivals, abandoned, error, (ex + 1) * (unsigned)nw, s.limit, &flag)) return false;
-        // ---- totals over the component's workgroups (slot order) into LDS
-        if (t < NP) {   // upper triangle, mirrored
-          int n1, n2;
-          pair_of<NR>(t, n1, n2);
-          const double v = gather(R8 * K + n1 * R8 + n2, ex, false);
-          gF[n1 * R8 + n2] = v;
-          gF[n2 * R8 + n1] = v;
-        }
-        for (int e = t; e < NR * K; e += 2 * CT) {
-          if (e + CT < NR * K) {
-            double v0, v1;
-            gather2(e, e + CT, ex, v0, v1);
-            FtP[e] = v0;
-            FtP[e + CT] = v1;
-          } else {
+        // ---- totals over the component's workgroups (slot order) into LDS:
+        // the NR K entries of F^T P, then the upper triangle of F^T F (mirrored)
+        for (int e = t; e < NR * K + NP; e += CT) {
+          if (e < NR * K) {
             FtP[e] = gather(e, ex, false);
+          } else {
+            int n1, n2;
+            pair_of<NR>(e - NR * K, n1, n2);
+            const double v = gather((size_t)R8 * K + n1 * R8 + n2, ex, false);
+            gF[n1 * R8 + n2] = v;
+            gF[n2 * R8 + n1] = v;
           }
         }
         ++ex;
-        __syncthreads();
+        LEAVE_IF_ABANDONED(false);
         // ---- the A update (rows of A in order), every workgroup alike
         for (int i = t; i < K; i += CT) {
           double av[NR];
@@ -470,12 +482,11 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
         if (sweep < 0) continue;
         // ---- P A^T of own rows and A A^T (FP64, fixed order). Waves
         // 0..14: thread (segment chunk q, own row m) sums its segments for
-        // all NR rows of A. Wave 15: A A^T, lane (segment chunk q, row n1),
-        // chunked by K and NR only, so identical in every workgroup. Chunks
-        // are then added in order.
+        // all NR rows of A. Wave 15: A A^T whole within the wave, chunked by
+        // K and NR only, so identical in every workgroup.
+        // at most 16 chunks: their in-order sum is a chain of dependent adds
+        const int QK = max(1, min(min(CV / ml, 16), s.scr / (ml * NR)));
         {
-          // at most 16 chunks: their in-order sum is a chain of dependent adds
-          const int QK = max(1, min(min(CV / ml, 16), s.scr / (ml * NR)));
           const int seg = (K + QK - 1) / QK;
           if (t < CV) {
             for (int e = t; e < QK * ml; e += CV) {
@@ -501,22 +512,24 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
 #pragma unroll
               for (int n = 0; n < NR; ++n) scr[(size_t)e * NR + n] = s0[n] + s1[n];
             }
-          } else {
-            gram_part<NR>(A, K, t - CV, gpart);
+          } else {   // A A^T, upper triangle mirrored (every workgroup alike)
+            const double v = gram_wave<NR>(A, K, t - CV, gpart);
+            if (t - CV < NP) {
+              int n1, n2;
+              pair_of<NR>(t - CV, n1, n2);
+              gA[n1 * R8 + n2] = v;
+              gA[n2 * R8 + n1] = v;
+            }
           }
-          __syncthreads();
-          for (int e = t; e < ml * NR; e += CT) {   // P A^T: chunks in order
-            GP[e] = chunk_sum(scr + e, (size_t)ml * NR, QK);
-          }
-          if (t < NR * NR) gA[(t / NR) * R8 + t % NR] = gram_total<NR>(t, gpart);
           __syncthreads();
         }
-        // ---- the own F rows (columns of F in order)
+        // ---- the own F rows (columns of F in order), each thread adding
+        // its row's P A^T chunks in order first
         for (int m = t; m < ml; m += CT) {
           double gp[NR], f[NR];
 #pragma unroll
           for (int n = 0; n < NR; ++n) {
-            gp[n] = GP[m * NR + n];
+            gp[n] = chunk_sum(scr + (size_t)m * NR + n, (size_t)ml * NR, QK);   // P A^T: chunks in order
             f[n] = F[m * R8 + n];
           }
 #pragma unroll
@@ -551,28 +564,26 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
     if (!ok) return;
 
     // ------------------------------------------ scale to peak 1, export
-    {
-      double* xs = slot(r, ex);
-      for (int n = 0; n < N; ++n) {
-        double mx = 0.0;
-        for (int m = t; m < ml; m += CT) mx = fmax(mx, F[m * R8 + n]);
-        mx = block_max(mx, red);
-        if (t == 0) put(xs + n, mx);
-      }
+    for (int n = 0; n < N; ++n) {
+      double mx = 0.0;
+      for (int m = t; m < ml; m += CT) mx = fmax(mx, F[m * R8 + n]);
+      mx = block_max(mx, red);
+      if (t == 0) put(ex, n, mx);
     }
-    MEET();
+    double* peak = scr;
+    if (t < N) peak[t] = gather(t, ex, true);
+    ++ex;
+    LEAVE_IF_ABANDONED();
     double* Fg = a.F + (long long)(off + lo) * R8;
     double* Ag = a.A + (long long)c * R8 * a.Kmax;
     for (int n = 0; n < N; ++n) {
-      const double mx = gather(n, ex, true);
-      const double sc = mx > 0.0 ? mx : 1.0;
+      const double sc = peak[n] > 0.0 ? peak[n] : 1.0;
       for (int m = t; m < ml; m += CT) Fg[(long long)m * R8 + n] = F[m * R8 + n] / sc;
       if (r == 0)
         for (int i = t; i < K; i += CT) Ag[(long long)n * a.Kmax + i] = A[i * R8 + n] * sc;
     }
-    ++ex;
   }
-#undef MEET
+#undef LEAVE_IF_ABANDONED
   if (r == 0 && t == 0) a.N[c] = N;
 }
 
@@ -582,12 +593,13 @@ __global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
 }
 
 // Dynamic LDS of one workgroup: A [K][R8], F and P A^T [mw][R8], scratch
-// (F^T P totals, the twelve P A^T parts, or the SPA vectors), P rows [mw][Kp].
+// (F^T P totals, the chunk partials of the HALS products, the SPA vectors or
+// the final column maxima), P rows [mw][Kp].
 size_t split_lds(int K, int mw, int* scr_out) {
   const int Kp = K | 1;
-  const size_t scr = std::max<size_t>({(size_t)R8 * K, (size_t)12 * 16 * R8, (size_t)K + mw});
+  const size_t scr = std::max<size_t>({(size_t)12 * 16 * R8, (size_t)K + mw});
   if (scr_out) *scr_out = (int)scr;
-  return 8 * ((size_t)K * R8 + 2 * (size_t)mw * R8 + scr) + 4 * (size_t)mw * Kp;
+  return 8 * ((size_t)K * R8 + (size_t)mw * R8 + (size_t)R8 * K + scr) + 4 * (size_t)mw * Kp;
 }
 
 }  // namespace
@@ -608,8 +620,9 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
   const int ncomp = a.ncomp;
   if (K < 1 || ncomp < 1) return false;
   const int XS = ((R8 * K + R8 * R8) + 31) / 32 * 32;
-  // exchange slots: two per workgroup of the largest launch, in xbuf
-  const size_t slot_bytes = (size_t)2 * XS * 8;
+  // exchange slots: two per workgroup of the largest launch, in xbuf, each
+  // of XS high and XS low words
+  const size_t slot_bytes = (size_t)2 * 2 * XS * 8;
   // Slice widths in order of preference (measured: 96 rows balance the
   // per-sweep exchange against the per-workgroup work; at most twelve
   // 16-row tiles). Components are packed, in order, into launches of at most
@@ -643,9 +656,9 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
   const int mw = best_mw;
   int scr = 0;
   size_t lds = split_lds(K, mw, &scr);
-  // spare LDS (up to 2 R8 K more doubles) widens the scratch of the HALS
+  // spare LDS (up to 3 R8 K more doubles) widens the scratch of the HALS
   // products' chunk partials, so more chunks run at once at higher ranks
-  const size_t more = std::min<size_t>((budget - lds) / 8, (size_t)2 * R8 * K);
+  const size_t more = std::min<size_t>((budget - lds) / 8, (size_t)3 * R8 * K);
   scr += (int)more;
   lds += 8 * more;
   int occ = 0;
@@ -681,9 +694,17 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
 
 hipError_t launch_nmf_split(const NmfArgs& a, const NmfSplit& s, bool first, hipStream_t st) {
   hipError_t e = hipSuccess;
-  if (first) {   // the counters and flags of every component, once per plan
-    const int nsync = 2 * a.ncomp + 1;
+  if (first) {   // the abandon flags of every component and the error flag, once per plan
+    const int nsync = a.ncomp + 1;
     hipLaunchKernelGGL(k_fill_u32, dim3((nsync + 255) / 256), dim3(256), 0, st, s.sync, nsync, 0u);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {   // the slots of this launch carry no tag (tags start at 1)
+    const long long words = (long long)s.G * 2 * 2 * s.XS * 2;   // 32-bit words
+    if (words > INT_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<unsigned*>(s.xbuf), (int)words, 0u);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -479,7 +479,7 @@ int seg_finalize(seg_session* s, void* stream) {
     na.sweeps = (int)c.nmf_sweeps;
     na.delta = (double)c.spa_delta;
     // split path: the exchange slots reuse the pixel-major P_c area, the
-    // workgroup tables the SPA-direction area and the meeting counters the
+    // workgroup tables the SPA-direction area and the abandon and error flags the
     // SPA-flag area (all three belong to the single-workgroup kernel)
     seg::NmfSplit sp{};
     seg::NmfSplitTables tabs;
@@ -501,7 +501,7 @@ int seg_finalize(seg_session* s, void* stream) {
         return e;
       sp.wg_base = tab + G;
       sp.wg_n = tab + G + ncomp;
-      sp.xbuf = na.P;
+      sp.xbuf = reinterpret_cast<unsigned long long*>(na.P);
       sp.sync = reinterpret_cast<unsigned*>(na.Wk);
       hold.lock();
       if ((e = fail(s, hipEventRecord(s->ev[2], st)))) return e;
@@ -537,11 +537,11 @@ int seg_finalize(seg_session* s, void* stream) {
     if ((e = fail(s, hipMemcpyAsync(N.data(), na.N, ncomp * 4, hipMemcpyDeviceToHost, st)))) return e;
     if ((e = fail(s, hipMemcpyAsync(F.data(), na.F, F.size() * 8, hipMemcpyDeviceToHost, st)))) return e;
     if ((e = fail(s, hipMemcpyAsync(A.data(), na.A, A.size() * 8, hipMemcpyDeviceToHost, st)))) return e;
-    if (split && (e = fail(s, hipMemcpyAsync(&split_error, sp.sync + 2 * ncomp, 4, hipMemcpyDeviceToHost, st))))
+    if (split && (e = fail(s, hipMemcpyAsync(&split_error, sp.sync + ncomp, 4, hipMemcpyDeviceToHost, st))))
       return e;
     if ((e = fail(s, hipStreamSynchronize(st)))) return e;
     if (hold.owns_lock()) hold.unlock();
-    if (split_error) return fail(s, hipErrorLaunchTimeOut);  // a meeting was abandoned
+    if (split_error) return fail(s, hipErrorLaunchTimeOut);  // a wait for a slot was abandoned
     // algorithmic work of the NMF (seg_profile)
     {
       const double Kd = (double)s->K, S = (double)c.nmf_sweeps;

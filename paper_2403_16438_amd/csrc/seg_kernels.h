@@ -105,8 +105,8 @@ struct NmfSplit {
   const int* wg_comp;    // [G] component of each workgroup of the launch
   const int* wg_base;    // [ncomp] first workgroup of each component within its launch
   const int* wg_n;       // [ncomp] workgroups of each component
-  double* xbuf;          // [G][2][XS] exchange slots
-  unsigned* sync;        // [2 ncomp + 1] arrivals, abandon flags, error flag
+  unsigned long long* xbuf;  // [G][2][2 XS] exchange slots: tagged high, then low words
+  unsigned* sync;        // [ncomp + 1] abandon flags, error flag
 };
 // Host copies of the workgroup tables and the launches (first workgroup in
 // `comp`, workgroup count) of a split plan.
@@ -119,8 +119,8 @@ struct NmfSplitTables {
 // launches; false when the split path does not apply.
 bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff, size_t xbuf_bytes,
                     NmfSplitTables& tab);
-// One launch of the plan (s.G and s.wg_comp select it); `first` clears the
-// meeting counters and flags of all components.
+// One launch of the plan (s.G and s.wg_comp select it): clears its exchange
+// slots first; `first` also clears the abandon and error flags.
 hipError_t launch_nmf_split(const NmfArgs& a, const NmfSplit& s, bool first, hipStream_t st);
 
 }  // namespace seg
