@@ -493,6 +493,10 @@ __global__ void k_aggregate(FinalizeArgs a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= a.M) return;
   a.blab[x] = a.nb[x] >= a.min_event_segs ? x : -1;
+  if (x < a.Ccap) {   // per-component pixel counts and bounding boxes start empty
+    a.coff[x] = 0;
+    reinterpret_cast<int4*>(a.cbox)[x] = make_int4(INT_MAX, -1, INT_MAX, -1);
+  }
 }
 
 __global__ void k_component_labels(FinalizeArgs a) {
@@ -500,6 +504,81 @@ __global__ void k_component_labels(FinalizeArgs a) {
   if (x >= a.M) return;
   const int l = a.blab[x];
   a.comp[x] = l >= 0 ? a.rid[l] + 1 : 0;
+}
+
+// Pixel count and bounding box of each component, one update per horizontal
+// run of its pixels (by the run's first pixel): atomics on one address
+// serialise, and a component has far fewer runs than pixels.
+__global__ void k_comp_stats(FinalizeArgs a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.M) return;
+  const int c = a.comp[x];
+  if (c == 0) return;
+  const int yy = x / a.W, xx = x - yy * a.W;
+  if (xx > 0 && a.comp[x - 1] == c) return;
+  int e = xx;
+  while (e + 1 < a.W && a.comp[x + (e + 1 - xx)] == c) ++e;
+  int* b = a.cbox + 4 * (c - 1);
+  atomicAdd(&a.coff[c - 1], e - xx + 1);
+  atomicMin(b + 0, xx);
+  atomicMax(b + 1, e);
+  atomicMin(b + 2, yy);
+  atomicMax(b + 3, yy);
+}
+
+// Component offsets: exclusive scan of the pixel counts of the counters[0]
+// components, in place; coff[ncomp] = number of component pixels.
+__global__ __launch_bounds__(SCAN_NT) void k_comp_offsets(FinalizeArgs a) {
+  __shared__ int sh[SCAN_NT / 64];
+  const int n = a.counters[0];
+  int carry = 0;
+  for (int base = 0; base < n; base += SCAN_NT) {
+    const int i = base + threadIdx.x;
+    const int v = i < n ? a.coff[i] : 0;
+    int tot;
+    const int ex = block_exclusive_scan<SCAN_NT>(v, sh, &tot);
+    if (i < n) a.coff[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) a.coff[n] = carry;
+}
+
+// Pixel list of each component in raster order: a workgroup walks the
+// component's bounding box row by row, 4,096 pixels at a time (four adjacent
+// ones per thread, loaded at once), and places the component's pixels by an
+// exclusive scan of the per-thread counts, so the lists do not depend on
+// scheduling.
+constexpr int PIX_NT = 1024, PIX_PER = 4;
+__global__ __launch_bounds__(PIX_NT) void k_comp_pixels(FinalizeArgs a) {
+  __shared__ int sh[PIX_NT / 64];
+  const int n = a.counters[0];
+  for (int c = blockIdx.x; c < n; c += gridDim.x) {
+    const int4 b = reinterpret_cast<const int4*>(a.cbox)[c];
+    const int bw = b.y - b.x + 1, area = bw * (b.w - b.z + 1);
+    int run = a.coff[c];
+    for (int base = 0; base < area; base += PIX_NT * PIX_PER) {
+      int px[PIX_PER];
+      unsigned f = 0;
+#pragma unroll
+      for (int k = 0; k < PIX_PER; ++k) {
+        const int idx = base + (int)threadIdx.x * PIX_PER + k;
+        px[k] = -1;
+        if (idx < area) {
+          const int r = idx / bw;
+          px[k] = (b.z + r) * a.W + b.x + (idx - r * bw);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < PIX_PER; ++k)
+        if (px[k] >= 0 && a.comp[px[k]] == c + 1) f |= 1u << k;
+      int tot;
+      int off = run + block_exclusive_scan<PIX_NT>(__popc(f), sh, &tot);
+#pragma unroll
+      for (int k = 0; k < PIX_PER; ++k)
+        if (f >> k & 1u) a.pix[off++] = px[k];
+      run += tot;
+    }
+  }
 }
 
 __global__ void k_u8_to_f32(const uint8_t* __restrict__ in, float* __restrict__ out, long long n) {
@@ -543,6 +622,9 @@ hipError_t launch_finalize_maps(const FinalizeArgs& a, hipStream_t st) {
   e = compact_roots(a.blab, a.M, a.scan, a.scan_cap, &a.counters[0], a.rid, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_component_labels, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a);
+  hipLaunchKernelGGL(k_comp_stats, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a);
+  hipLaunchKernelGGL(k_comp_offsets, dim3(1), dim3(SCAN_NT), 0, st, a);
+  hipLaunchKernelGGL(k_comp_pixels, dim3(256), dim3(PIX_NT), 0, st, a);
   return hipGetLastError();
 }
 

@@ -95,6 +95,7 @@ Layout make_layout(const seg_config& c) {
   l.counters = take(16 * 4);
   l.pix = take(M * 4);
   l.coff = take((M + 1) * 4);
+  l.cbox = take(l.Ccap * 16);
   l.nmf_P = take(M * K * 8);
   l.nmf_PT = take(M * K * 8);
   l.nmf_R = take(M * K * 8);
@@ -414,6 +415,10 @@ int seg_finalize(seg_session* s, void* stream) {
   a.nb = at<int>(s, l.nb);
   a.blab = at<int>(s, l.blab);
   a.comp = at<int>(s, l.comp);
+  a.pix = at<int>(s, l.pix);
+  a.coff = at<int>(s, l.coff);
+  a.cbox = at<int>(s, l.cbox);
+  a.Ccap = (int)l.Ccap;
   a.scan = at<int>(s, l.scan);
   a.counters = at<int>(s, l.counters);
   a.Rcap = (long long)l.Rcap;
@@ -434,31 +439,25 @@ int seg_finalize(seg_session* s, void* stream) {
   if ((e = fail(s, hipEventRecord(s->ev[0], st)))) return e;
   if ((e = fail(s, seg::launch_finalize_maps(a, st)))) return e;
   if ((e = fail(s, hipEventRecord(s->ev[1], st)))) return e;
+  // component count and offsets (the pixel lists stay on the device for the
+  // NMF); the first few thousand offsets come with the count
   int ncomp = 0;
+  std::vector<int> coff(std::min<size_t>(s->M + 1, 4097));
   if ((e = fail(s, hipMemcpyAsync(&ncomp, a.counters, sizeof(int), hipMemcpyDeviceToHost, st)))) return e;
-  std::vector<int> comp(s->M);
-  if ((e = fail(s, hipMemcpyAsync(comp.data(), a.comp, (size_t)s->M * 4, hipMemcpyDeviceToHost, st))))
-    return e;
+  if ((e = fail(s, hipMemcpyAsync(coff.data(), a.coff, coff.size() * 4, hipMemcpyDeviceToHost, st)))) return e;
   if ((e = fail(s, hipStreamSynchronize(st)))) return e;
-  // pixel lists per component in raster order (CSR)
-  std::vector<int> coff(ncomp + 1, 0), pix;
-  for (uint32_t x = 0; x < s->M; ++x)
-    if (comp[x] > 0) ++coff[comp[x]];
-  for (int k = 0; k < ncomp; ++k) coff[k + 1] += coff[k];
-  pix.resize(coff[ncomp]);
-  {
-    std::vector<int> fill(coff.begin(), coff.end() - 1);
-    for (uint32_t x = 0; x < s->M; ++x)
-      if (comp[x] > 0) pix[fill[comp[x] - 1]++] = (int)x;
+  if ((size_t)ncomp + 1 > coff.size()) {
+    coff.resize((size_t)ncomp + 1);
+    if ((e = fail(s, hipMemcpyAsync(coff.data(), a.coff, coff.size() * 4, hipMemcpyDeviceToHost, st)))) return e;
+    if ((e = fail(s, hipStreamSynchronize(st)))) return e;
   }
+  coff.resize((size_t)ncomp + 1);
+  std::vector<int> pix(coff[ncomp]);
   s->n_comp = (uint32_t)ncomp;
   s->fps.clear();
   if (ncomp > 0) {
-    int* dpix = at<int>(s, l.pix);
-    int* dcoff = at<int>(s, l.coff);
-    if ((e = fail(s, hipMemcpyAsync(dpix, pix.data(), pix.size() * 4, hipMemcpyHostToDevice, st)))) return e;
-    if ((e = fail(s, hipMemcpyAsync(dcoff, coff.data(), coff.size() * 4, hipMemcpyHostToDevice, st))))
-      return e;
+    int* dpix = a.pix;
+    int* dcoff = a.coff;
     seg::NmfArgs na{};
     na.M = (int)s->M;
     na.K = (int)s->K;
@@ -535,6 +534,7 @@ int seg_finalize(seg_session* s, void* stream) {
     std::vector<double> F(npx * seg::kMaxRank), A((size_t)ncomp * seg::kMaxRank * s->Kmax);
     unsigned split_error = 0;
     if ((e = fail(s, hipMemcpyAsync(N.data(), na.N, ncomp * 4, hipMemcpyDeviceToHost, st)))) return e;
+    if ((e = fail(s, hipMemcpyAsync(pix.data(), dpix, pix.size() * 4, hipMemcpyDeviceToHost, st)))) return e;
     if ((e = fail(s, hipMemcpyAsync(F.data(), na.F, F.size() * 8, hipMemcpyDeviceToHost, st)))) return e;
     if ((e = fail(s, hipMemcpyAsync(A.data(), na.A, A.size() * 8, hipMemcpyDeviceToHost, st)))) return e;
     if (split && (e = fail(s, hipMemcpyAsync(&split_error, sp.sync + ncomp, 4, hipMemcpyDeviceToHost, st))))

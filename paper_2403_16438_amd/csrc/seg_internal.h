@@ -33,6 +33,7 @@ struct Layout {
   size_t counters;  // i32 [16]
   size_t pix;       // i32 [M] component pixel lists (raster order)
   size_t coff;      // i32 [M + 1] component offsets
+  size_t cbox;      // i32 [Ccap][4] component bounding boxes
   size_t nmf_P;     // f64 [M][Kmax] gathered P_c (pixel-major)
   size_t nmf_PT;    // f64 [Kmax][M] gathered P_c (segment-major)
   size_t nmf_R;     // f64 [M][Kmax] SPA residual

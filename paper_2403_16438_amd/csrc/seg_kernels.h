@@ -60,6 +60,10 @@ struct FinalizeArgs {
   int* nb;
   int* blab;
   int* comp;
+  int* pix;        // i32 [M] component pixel lists, raster order within each
+  int* coff;       // i32 [Ccap + 1] component offsets into pix
+  int* cbox;       // i32 [Ccap][4] component bounding boxes (x0, x1, y0, y1)
+  int Ccap;        // component capacity
   int* scan;
   int* counters;
   long long Rcap;
@@ -72,7 +76,8 @@ struct FinalizeArgs {
   bool prob_mode;  // surrogate: p holds probabilities, events are p >= theta
 };
 // pointwise images, events, per-segment regions, kept masks, aggregate,
-// canonical components; writes the component count to counters[0]
+// canonical components and their pixel lists; writes the component count to
+// counters[0], the offsets to coff and the lists to pix
 hipError_t launch_finalize_maps(const FinalizeArgs& a, hipStream_t st);
 hipError_t launch_u8_to_f32(const uint8_t* in, float* out, long long n, hipStream_t st);
 
