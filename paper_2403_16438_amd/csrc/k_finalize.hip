@@ -398,27 +398,28 @@ __global__ __launch_bounds__(64) void k_region_decide(FinalizeArgs a, const int*
       __syncthreads();
       continue;
     }
-    // per-row extremes of the region inside its bounding box
+    // per-row extremes of the region inside its bounding box: one lane per
+    // row, eight label loads in flight at a time
     const int x0 = a.reg_box[4 * r + 0], x1 = a.reg_box[4 * r + 1];
     const int y0 = a.reg_box[4 * r + 2], y1 = a.reg_box[4 * r + 3];
     const int rt = root[r];
     const long long img = (long long)(rt / a.M) * a.M;
-    for (int y = y0; y <= y1; ++y) {
+    for (int y = y0 + lane; y <= y1; y += 64) {
+      const int* row = a.lab + img + (long long)y * a.W;
       int mn = 0x7fffffff, mx = -1;
-      for (int x = x0 + lane; x <= x1; x += 64) {
-        if (a.lab[img + (long long)y * a.W + x] == rt) {
-          mn = min(mn, x);
-          mx = max(mx, x);
-        }
+      for (int x = x0; x <= x1; x += 8) {
+        int v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = x + k <= x1 ? row[x + k] : -1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (v[k] == rt) {
+            mn = min(mn, x + k);
+            mx = max(mx, x + k);
+          }
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        mn = min(mn, __shfl_xor(mn, off));
-        mx = max(mx, __shfl_xor(mx, off));
-      }
-      if (lane == 0) {
-        xl[y - y0] = mn;
-        xr[y - y0] = mx + 1;
-      }
+      xl[y - y0] = mn;
+      xr[y - y0] = mx + 1;
     }
     __syncthreads();
     if (lane == 0) {
