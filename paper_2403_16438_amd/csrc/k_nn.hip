@@ -320,16 +320,20 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
   // Staging: a thread takes 8 channels of a tile position (8 loads, each
   // coalesced over the positions; one 16-byte LDS store) and 16-byte groups
-  // of the reordered weights. With 64-row tiles the next chunk's loads are
-  // issued before the current chunk's MFMAs and converted only when stored;
-  // with 32-row tiles (three input items per thread) the registers that takes
-  // cost more occupancy than the overlap gains, so each chunk is loaded and
-  // stored in turn.
+  // of the reordered weights. Every load is issued unconditionally (positions
+  // outside the image or channels past Ci read a valid address and are then
+  // replaced by zero), so a thread's loads go out together and wait once:
+  // guarded loads were issued one at a time, each waiting for the previous.
+  // With 64-row tiles the next chunk's loads are issued before the current
+  // chunk's MFMAs and converted only when stored; with 32-row tiles (three
+  // input items per thread) each chunk is loaded and stored in turn.
   const int np = TR * TC;
   constexpr bool PF = MT == 64;
-  constexpr int XI = 2, WI = (MT * 18 + 255) / 256;   // prefetch: 2 np <= 512 items
+  constexpr int XI = MT == 64 ? 2 : 3;                // input items per thread: 2 np <= 256 XI
+  constexpr int WI = (MT * 18 + 255) / 256;
   float xv[XI][8];
   uint4 wv4[WI];
+  uint32_t okx[XI], okw;   // which loaded values are real (the rest become zero)
   auto load = [&](int c0) {
 #pragma unroll
     for (int j = 0; j < XI; ++j) {
@@ -337,60 +341,58 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
       const int g = e >= np ? 1 : 0, pos = e - g * np, r = pos / TC, cc = pos - r * TC;
       const int y = y0 + r - 1, x = x0 + cc - 1;
       const bool in = e < 2 * np && y >= 0 && y < H && x >= 0 && x < W;
-      const float* src = X + ((long long)(c0 + 8 * g) * Bn + b) * HW + (long long)y * W + x;
+      // clamped into the image and the channel range: always a valid address
+      const int yc = min(max(y, 0), H - 1), xc = min(max(x, 0), W - 1);
+      const float* src = X + (long long)b * HW + (long long)yc * W + xc;
+      okx[j] = 0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) xv[j][q] = (in && c0 + 8 * g + q < Ci) ? src[(long long)q * Bn * HW] : 0.f;
+      for (int q = 0; q < 8; ++q) {
+        const int c = c0 + 8 * g + q;
+        xv[j][q] = src[(long long)min(c, Ci - 1) * Bn * HW];
+        okx[j] |= (uint32_t)(in && c < Ci) << q;
+      }
     }
     const uint16_t* wsrc = Wr + (long long)(c0 / HC) * Co * 9 * HC;
+    okw = 0;
 #pragma unroll
     for (int j = 0; j < WI; ++j) {
       const int e = tid + 256 * j, m = e / 18, q = e - m * 18, co = co0 + m;
-      wv4[j] = (e < MT * 18 && co < Co) ? *reinterpret_cast<const uint4*>(wsrc + (long long)co * 9 * HC + 8 * q)
-                                         : make_uint4(0, 0, 0, 0);
+      const bool ok = e < MT * 18 && co < Co;
+      const int coc = min(co0 + min(m, MT - 1), Co - 1);   // clamped: always a valid address
+      wv4[j] = *reinterpret_cast<const uint4*>(wsrc + (long long)coc * 9 * HC + 8 * q);
+      okw |= (uint32_t)ok << j;
     }
   };
   if constexpr (PF) load(0);
   for (int c0 = 0; c0 < Ci; c0 += HC) {
     __syncthreads();
-    if constexpr (!PF) {
-      for (int e = tid; e < 2 * np; e += 256) {
-        const int g = e >= np ? 1 : 0, pos = e - g * np, r = pos / TC, cc = pos - r * TC;
-        const int y = y0 + r - 1, x = x0 + cc - 1;
-        const bool in = y >= 0 && y < H && x >= 0 && x < W;
-        const float* src = X + ((long long)(c0 + 8 * g) * Bn + b) * HW + (long long)y * W + x;
+    if constexpr (!PF) load(c0);
+    // the loaded values are taken here whether or not they are used, so the
+    // compiler keeps every load unconditional (and in flight together)
+#pragma unroll
+    for (int j = 0; j < XI; ++j)
+      asm volatile("" : "+v"(xv[j][0]), "+v"(xv[j][1]), "+v"(xv[j][2]), "+v"(xv[j][3]), "+v"(xv[j][4]),
+                        "+v"(xv[j][5]), "+v"(xv[j][6]), "+v"(xv[j][7]));
+#pragma unroll
+    for (int j = 0; j < WI; ++j) asm volatile("" : "+v"(wv4[j].x), "+v"(wv4[j].y), "+v"(wv4[j].z), "+v"(wv4[j].w));
+#pragma unroll
+    for (int j = 0; j < XI; ++j) {
+      const int e = tid + 256 * j;
+      if (e < 2 * np) {
+        const int g = e >= np ? 1 : 0, pos = e - g * np;
         uint16_t v[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-          v[q] = (in && c0 + 8 * g + q < Ci) ? to_bf16(src[(long long)q * Bn * HW]) : (uint16_t)0;
+        for (int q = 0; q < 8; ++q) v[q] = (okx[j] >> q & 1u) ? to_bf16(xv[j][q]) : (uint16_t)0;
         *reinterpret_cast<uint4*>(&Xs[pos * HC + 8 * g]) =
             make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
                        v[6] | ((uint32_t)v[7] << 16));
       }
-      const uint16_t* wsrc = Wr + (long long)(c0 / HC) * Co * 9 * HC;
-      for (int e = tid; e < MT * 18; e += 256) {
-        const int m = e / 18, q = e - m * 18, co = co0 + m;
-        *reinterpret_cast<uint4*>(&Ws[m][8 * q]) =
-            co < Co ? *reinterpret_cast<const uint4*>(wsrc + (long long)co * 9 * HC + 8 * q) : make_uint4(0, 0, 0, 0);
-      }
-    } else {
+    }
 #pragma unroll
-      for (int j = 0; j < XI; ++j) {
-        const int e = tid + 256 * j;
-        if (e < 2 * np) {
-          const int g = e >= np ? 1 : 0, pos = e - g * np;
-          uint16_t v[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) v[q] = to_bf16(xv[j][q]);
-          *reinterpret_cast<uint4*>(&Xs[pos * HC + 8 * g]) =
-              make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
-                         v[6] | ((uint32_t)v[7] << 16));
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < WI; ++j) {
-        const int e = tid + 256 * j;
-        if (e < MT * 18) *reinterpret_cast<uint4*>(&Ws[e / 18][8 * (e % 18)]) = wv4[j];
-      }
+    for (int j = 0; j < WI; ++j) {
+      const int e = tid + 256 * j;
+      if (e < MT * 18)
+        *reinterpret_cast<uint4*>(&Ws[e / 18][8 * (e % 18)]) = (okw >> j & 1u) ? wv4[j] : make_uint4(0, 0, 0, 0);
     }
     __syncthreads();
     if (PF && c0 + HC < Ci) load(c0 + HC);
@@ -411,13 +413,16 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   const int y = y0 + pr, x = x0 + pc;
   if (y >= H || x >= W) return;
   float* yp = Y + (long long)b * HW + (long long)y * W + x;
+  float bv[16];   // biases loaded together (clamped index), used where co < Co
+#pragma unroll
+  for (int k = 0; k < 16; ++k) bv[k] = bias[min(co0 + wm * 32 + 8 * (k >> 2) + 4 * (lane >> 5) + (k & 3), Co - 1)];
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int co = co0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
       if (co < Co) {
-        float v = acc[4 * g + r] + bias[co];
+        float v = acc[4 * g + r] + bv[4 * g + r];
         if (relu) v = fmaxf(v, 0.f);
         yp[(long long)co * Bn * HW] = v;
       }
