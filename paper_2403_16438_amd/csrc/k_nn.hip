@@ -4,6 +4,7 @@
 // whose output is already the next activation; matrix operands are rounded to
 // BF16 (round to nearest even) and multiplied on MFMA with FP32 accumulation.
 #include <cstdint>
+#include <type_traits>
 
 #include "nn_internal.h"
 
@@ -125,7 +126,9 @@ __global__ __launch_bounds__(256) void k_gemm(const TA* __restrict__ A, long lon
 //             product, plus bias[co], is stored to C at channel co, pixel
 //             (2 y + a, 2 x + e) of an image of 2 H x 2 W (X's pixels H x W),
 //             so the product lands directly in the concatenation buffer.
-enum { GV_BF16 = 0, GV_IM2COL = 1, GV_UP = 2 };
+//   GV_UP_H   as GV_UP, with BF16 X [K][N] (row stride sbk, passed as B) and
+//             the stored values rounded to BF16 (C then holds BF16 bits)
+enum { GV_BF16 = 0, GV_IM2COL = 1, GV_UP = 2, GV_UP_H = 3 };
 struct Im2col {
   const float* X;
   int Bn, H, W;
@@ -170,7 +173,7 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int gkb = k0 + bk, gn = n0 + bn + 64 * j;
-      if constexpr (MODE == GV_BF16) {
+      if constexpr (MODE == GV_BF16 || MODE == GV_UP_H) {
         rb[j] = (gkb < K && gn < N) ? *reinterpret_cast<const uint4*>(B + gkb * sbk + gn) : make_uint4(0, 0, 0, 0);
       } else if constexpr (MODE == GV_UP) {
         uint4 v = make_uint4(0, 0, 0, 0);
@@ -235,6 +238,21 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
   }
   const int col = n0 + wn * 32 + (lane & 31);
   if (col >= N) return;
+  if constexpr (MODE == GV_UP_H) {
+    const int hw = ic.H * ic.W, b = col / hw, yx = col - b * hw, y = yx / ic.W, x = yx - y * ic.W;
+    uint16_t* base = reinterpret_cast<uint16_t*>(C) + (long long)b * 4 * hw + (long long)(2 * y) * (2 * ic.W) + 2 * x;
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
+        if (row < M) {
+          const int co = row >> 2, a = (row >> 1) & 1, e = row & 1;
+          base[(long long)co * ic.Bn * 4 * hw + a * 2 * ic.W + e] = to_bf16(acc[4 * g + r] + bias[co]);
+        }
+      }
+    return;
+  }
   if constexpr (MODE == GV_UP) {
     // row 4 co + 2 a + e of pixel (b, y, x) lands on (b, 2 y + a, 2 x + e) of channel co
     const int hw = ic.H * ic.W, b = col / hw, yx = col - b * hw, y = yx / ic.W, x = yx - y * ic.W;
@@ -296,11 +314,16 @@ __global__ void k_conv3_reorder(const uint16_t* __restrict__ Wb, uint16_t* __res
   Wr[i] = c < Ci ? Wb[(long long)co * Ci * 9 + c * 9 + kyx] : (uint16_t)0;
 }
 
-template <int MT>
-__global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__ Wr, const float* __restrict__ X,
+// TX, TY: float (FP32) or uint16_t (BF16 bits) activations in and out. A BF16
+// output is the BF16 rounding of the FP32 value, which is what the next
+// layer's staging (or the 1 x 1 output layer) makes of an FP32 output, so
+// the two give the same network outputs.
+template <int MT, typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__ Wr, const TX* __restrict__ X,
                                                     const float* __restrict__ bias, int relu,
-                                                    float* __restrict__ Y, int Co, int Ci, int Bn, int H, int W,
+                                                    TY* __restrict__ Y, int Co, int Ci, int Bn, int H, int W,
                                                     int BC) {
+  constexpr bool XH = sizeof(TX) == 2;
   constexpr int NT = 4096 / MT;
   __shared__ __attribute__((aligned(16))) uint16_t Xs[HX];
   __shared__ __attribute__((aligned(16))) uint16_t Ws[MT][9 * HC + 8];
@@ -324,14 +347,13 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   // outside the image or channels past Ci read a valid address and are then
   // replaced by zero), so a thread's loads go out together and wait once:
   // guarded loads were issued one at a time, each waiting for the previous.
-  // With 64-row tiles the next chunk's loads are issued before the current
-  // chunk's MFMAs and converted only when stored; with 32-row tiles (three
-  // input items per thread) each chunk is loaded and stored in turn.
+  // The next chunk's loads are issued before the current chunk's MFMAs and
+  // converted only when stored.
   const int np = TR * TC;
-  constexpr bool PF = MT == 64;
   constexpr int XI = MT == 64 ? 2 : 3;                // input items per thread: 2 np <= 256 XI
   constexpr int WI = (MT * 18 + 255) / 256;
-  float xv[XI][8];
+  using XV = typename std::conditional<XH, uint32_t, float>::type;   // a loaded input value
+  XV xv[XI][8];
   uint4 wv4[WI];
   uint32_t okx[XI], okw;   // which loaded values are real (the rest become zero)
   auto load = [&](int c0) {
@@ -343,7 +365,7 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
       const bool in = e < 2 * np && y >= 0 && y < H && x >= 0 && x < W;
       // clamped into the image and the channel range: always a valid address
       const int yc = min(max(y, 0), H - 1), xc = min(max(x, 0), W - 1);
-      const float* src = X + (long long)b * HW + (long long)yc * W + xc;
+      const TX* src = X + (long long)b * HW + (long long)yc * W + xc;
       okx[j] = 0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -363,10 +385,9 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
       okw |= (uint32_t)ok << j;
     }
   };
-  if constexpr (PF) load(0);
+  load(0);
   for (int c0 = 0; c0 < Ci; c0 += HC) {
     __syncthreads();
-    if constexpr (!PF) load(c0);
     // the loaded values are taken here whether or not they are used, so the
     // compiler keeps every load unconditional (and in flight together)
 #pragma unroll
@@ -382,7 +403,12 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
         const int g = e >= np ? 1 : 0, pos = e - g * np;
         uint16_t v[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = (okx[j] >> q & 1u) ? to_bf16(xv[j][q]) : (uint16_t)0;
+        for (int q = 0; q < 8; ++q) {
+          uint16_t h;
+          if constexpr (XH) h = (uint16_t)xv[j][q];
+          else h = to_bf16(xv[j][q]);
+          v[q] = (okx[j] >> q & 1u) ? h : (uint16_t)0;
+        }
         *reinterpret_cast<uint4*>(&Xs[pos * HC + 8 * g]) =
             make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
                        v[6] | ((uint32_t)v[7] << 16));
@@ -395,7 +421,7 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
         *reinterpret_cast<uint4*>(&Ws[e / 18][8 * (e % 18)]) = (okw >> j & 1u) ? wv4[j] : make_uint4(0, 0, 0, 0);
     }
     __syncthreads();
-    if (PF && c0 + HC < Ci) load(c0 + HC);
+    if (c0 + HC < Ci) load(c0 + HC);
 #pragma unroll
     for (int kyx = 0; kyx < 9; ++kyx) {
       const int ky = kyx / 3, kx = kyx - 3 * ky;
@@ -412,7 +438,7 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   }
   const int y = y0 + pr, x = x0 + pc;
   if (y >= H || x >= W) return;
-  float* yp = Y + (long long)b * HW + (long long)y * W + x;
+  TY* yp = Y + (long long)b * HW + (long long)y * W + x;
   float bv[16];   // biases loaded together (clamped index), used where co < Co
 #pragma unroll
   for (int k = 0; k < 16; ++k) bv[k] = bias[min(co0 + wm * 32 + 8 * (k >> 2) + 4 * (lane >> 5) + (k & 3), Co - 1)];
@@ -424,7 +450,8 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
       if (co < Co) {
         float v = acc[4 * g + r] + bv[4 * g + r];
         if (relu) v = fmaxf(v, 0.f);
-        yp[(long long)co * Bn * HW] = v;
+        if constexpr (sizeof(TY) == 2) yp[(long long)co * Bn * HW] = to_bf16(v);
+        else yp[(long long)co * Bn * HW] = v;
       }
     }
 }
@@ -440,6 +467,17 @@ __global__ void k_conv1_out(const uint16_t* __restrict__ Wb, const float* __rest
   float s = 0.f;
 #pragma unroll 8
   for (int c = 0; c < C; ++c) s = fmaf(from_bf16(Wb[c]), from_bf16(to_bf16(X[(long long)c * N + i])), s);
+  Y[i] = s + bias[0];
+}
+
+// the same with BF16 input activations
+__global__ void k_conv1_out_h(const uint16_t* __restrict__ Wb, const uint16_t* __restrict__ X,
+                              const float* __restrict__ bias, float* __restrict__ Y, int C, long long N) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float s = 0.f;
+#pragma unroll 8
+  for (int c = 0; c < C; ++c) s = fmaf(from_bf16(Wb[c]), from_bf16(X[(long long)c * N + i]), s);
   Y[i] = s + bias[0];
 }
 
@@ -613,6 +651,22 @@ __global__ void k_pool(const float* __restrict__ X, float* __restrict__ Y, uint8
   if (s[W + 1] > best) { best = s[W + 1]; a = 3; }
   Y[i] = best;
   arg[i] = (uint8_t)a;
+}
+
+// the same on BF16 activations, without the argmax (inference): the maximum
+// of BF16-rounded values is the BF16 rounding of the maximum
+__global__ void k_pool_h(const uint16_t* __restrict__ X, uint16_t* __restrict__ Y, int CB, int H, int W) {
+  const int h = H / 2, w = W / 2;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)CB * h * w) return;
+  const long long cb = i / (h * w);
+  const int yx = (int)(i % (h * w)), y = yx / w, x = yx % w;
+  const uint16_t* s = X + cb * H * W + (2 * y) * W + 2 * x;
+  uint16_t best = s[0];
+  if (from_bf16(s[1]) > from_bf16(best)) best = s[1];
+  if (from_bf16(s[W]) > from_bf16(best)) best = s[W];
+  if (from_bf16(s[W + 1]) > from_bf16(best)) best = s[W + 1];
+  Y[i] = best;
 }
 
 // dX (+)= dY routed to the argmax position
@@ -839,25 +893,40 @@ void conv3_reorder(const uint16_t* Wb, uint16_t* Wr, int Co, int Ci, hipStream_t
 }
 size_t conv3_reordered_size(int Co, int Ci) { return (size_t)((Ci + HC - 1) / HC) * Co * 9 * HC; }
 
+namespace {
+// shape check and launch of the halo-tile convolution; false when the shape
+// does not fit it
+template <typename TX, typename TY>
+bool conv3_halo(const uint16_t* Wr, const TX* X, TY* Y, int Co, int Ci, int Bn, int H, int W, const float* bias,
+                bool relu, hipStream_t st) {
+  if (!(Wr && W % 8 == 0 && bias && (long long)Bn * H * W <= 0x7fffffffLL && ((uintptr_t)Wr & 15) == 0))
+    return false;
+  const int MT = Co <= 32 ? 32 : 64, NT = 4096 / MT, BC = W < 64 ? W : 64;
+  const int np = (NT / BC + 2) * (BC + 2);
+  if (!(NT % BC == 0 && np * HC <= HX && 2 * np <= 256 * (MT == 64 ? 2 : 3))) return false;
+  const int BR = NT / BC;
+  const long long blocks = (long long)Bn * ((H + BR - 1) / BR) * ((W + BC - 1) / BC);
+  if (MT == 32)
+    hipLaunchKernelGGL((k_conv3_halo<32, TX, TY>), dim3((unsigned)blocks, (Co + 31) / 32), dim3(256), 0, st, Wr, X,
+                       bias, (int)relu, Y, Co, Ci, Bn, H, W, BC);
+  else
+    hipLaunchKernelGGL((k_conv3_halo<64, TX, TY>), dim3((unsigned)blocks, (Co + 63) / 64), dim3(256), 0, st, Wr, X,
+                       bias, (int)relu, Y, Co, Ci, Bn, H, W, BC);
+  return true;
+}
+}  // namespace
+
+bool conv3_halo_h(const uint16_t* Wr, const void* X, bool x_bf16, uint16_t* Y, int Co, int Ci, int Bn, int H, int W,
+                  const float* bias, bool relu, hipStream_t st) {
+  return x_bf16 ? conv3_halo(Wr, static_cast<const uint16_t*>(X), Y, Co, Ci, Bn, H, W, bias, relu, st)
+                : conv3_halo(Wr, static_cast<const float*>(X), Y, Co, Ci, Bn, H, W, bias, relu, st);
+}
+
 bool conv3_implicit(const uint16_t* Wb, const uint16_t* Wr, const float* X, float* Y, int Co, int Ci, int Bn,
                     int H, int W, const float* bias, bool relu, hipStream_t st) {
   // direct convolution over halo tiles where a block of whole 8-aligned
   // columns fits the tile
-  if (Wr && W % 8 == 0 && bias && (long long)Bn * H * W <= 0x7fffffffLL && ((uintptr_t)Wr & 15) == 0) {
-    const int MT = Co <= 32 ? 32 : 64, NT = 4096 / MT, BC = W < 64 ? W : 64;
-    const int np = (NT / BC + 2) * (BC + 2);
-    if (NT % BC == 0 && np * HC <= HX && (MT == 32 || 2 * np <= 512)) {
-      const int BR = NT / BC;
-      const long long blocks = (long long)Bn * ((H + BR - 1) / BR) * ((W + BC - 1) / BC);
-      if (MT == 32)
-        hipLaunchKernelGGL(k_conv3_halo<32>, dim3((unsigned)blocks, (Co + 31) / 32), dim3(256), 0, st, Wr, X, bias,
-                           (int)relu, Y, Co, Ci, Bn, H, W, BC);
-      else
-        hipLaunchKernelGGL(k_conv3_halo<64>, dim3((unsigned)blocks, (Co + 63) / 64), dim3(256), 0, st, Wr, X, bias,
-                           (int)relu, Y, Co, Ci, Bn, H, W, BC);
-      return true;
-    }
-  }
+  if (conv3_halo(Wr, X, Y, Co, Ci, Bn, H, W, bias, relu, st)) return true;
   const int K = Ci * 9;
   const long long N = (long long)Bn * H * W;
   if (W % 8 || K % 8 || ((uintptr_t)Wb & 15) || N > 0x7fffffffLL) return false;
@@ -884,6 +953,20 @@ bool up_direct(const uint16_t* Wb, const float* X, const float* bias, float* Y, 
 
 bool conv1_out(const uint16_t* Wb, const float* X, const float* bias, float* Y, int C, long long N, hipStream_t st) {
   L1(k_conv1_out, N, Wb, X, bias, Y, C, N);
+  return true;
+}
+void conv1_out_h(const uint16_t* Wb, const uint16_t* X, const float* bias, float* Y, int C, long long N,
+                 hipStream_t st) {
+  L1(k_conv1_out_h, N, Wb, X, bias, Y, C, N);
+}
+bool up_direct_h(const uint16_t* Wb, const uint16_t* X, const float* bias, uint16_t* Y, int Co, int Ci, int Bn, int h,
+                 int w, hipStream_t st) {
+  const long long N = (long long)Bn * h * w;
+  if (N % 8 || Ci % 8 || N > 0x7fffffffLL || ((uintptr_t)Wb & 15) || ((uintptr_t)X & 15)) return false;
+  const Im2col ic{nullptr, Bn, h, w};
+  const int M = 4 * Co;
+  hipLaunchKernelGGL((k_gemm_v<64, GV_UP_H>), dim3((unsigned)((N + 63) / 64), (M + 63) / 64), dim3(256), 0, st, Wb,
+                     (long long)Ci, X, N, ic, reinterpret_cast<float*>(Y), 0LL, M, (int)N, Ci, 0, bias, 0);
   return true;
 }
 
@@ -916,6 +999,9 @@ void bias_grad(const float* dY, float* db, int C, long long N, hipStream_t st) {
 }
 void pool(const float* X, float* Y, uint8_t* arg, int CB, int H, int W, hipStream_t st) {
   L1(k_pool, (long long)CB * (H / 2) * (W / 2), X, Y, arg, CB, H, W);
+}
+void pool_h(const uint16_t* X, uint16_t* Y, int CB, int H, int W, hipStream_t st) {
+  L1(k_pool_h, (long long)CB * (H / 2) * (W / 2), X, Y, CB, H, W);
 }
 void pool_bwd(const float* dY, const uint8_t* arg, float* dX, int CB, int H, int W, bool acc, hipStream_t st) {
   L1(k_pool_bwd, (long long)CB * H * W, dY, arg, dX, CB, H, W, (int)acc);

@@ -373,6 +373,72 @@ hipError_t forward(seg_nn* n, const uint16_t* frames, const float* stin, int Bn,
   return e;
 }
 
+// Forward pass for inference: the U-Net's activations are kept as BF16
+// (half the bytes of every layer's reads and writes). Every consumer of an
+// activation takes it rounded to BF16 (the convolutions' staging, the
+// transposed convolutions, the output layer; a maximum commutes with the
+// rounding), so the logits are the same as forward()'s. Returns false, with
+// nothing left that forward() does not redo, when a layer's shape does not
+// fit the BF16 kernels; *err gets launch errors.
+bool forward_infer(seg_nn* n, const uint16_t* frames, const float* stin, int Bn, hipStream_t st, hipError_t* err) {
+  const Plan& p = n->plan;
+  const int H = p.H, W = p.W;
+  const long long HW = (long long)H * W;
+  const long long N = Bn * HW, N2 = N / 4;
+  if (H % 4 || W % 32) return false;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) {
+    if (x != hipSuccess && e == hipSuccess) e = x;
+  };
+  float* x0 = at<float>(n, p.x0);
+  uint16_t* col = at<uint16_t>(n, p.col);
+  const float* unet_in = nullptr;
+  if (n->st) {
+    st_norm(stin, x0, Bn, HW, st);
+    unet_in = x0;
+  } else {
+    tnorm(frames, x0, Bn, L, HW, st);
+    float* a1 = at<float>(n, p.a1);
+    im2col1(x0, col, 1, L, 10, 5, 5, 0, N, st);
+    chk(gemm_wx(n, T1, col, true, 10 * N, a1, st));
+    bias_act(a1, bias(n, T1), 32, 10 * N, true, st);
+    float* a2 = at<float>(n, p.a2);
+    im2col1(a1, col, 32, 10, 5, 5, 2, 2, N, st);
+    chk(gemm_wx(n, T2, col, true, 5 * N, a2, st));
+    bias_act(a2, bias(n, T2), 32, 5 * N, true, st);
+    float* a3 = at<float>(n, p.a3);
+    chk(gemm_wx(n, T3, a2, false, N, a3, st));
+    bias_act(a3, bias(n, T3), 32, N, true, st);
+    unet_in = a3;
+  }
+  auto h = [&](const Buf& b) { return at<uint16_t>(n, b); };
+  auto conv = [&](int id, const void* X, bool x_bf16, uint16_t* Y, int hh, int ww) {
+    return conv3_halo_h(at<uint16_t>(n, p.wr) + p.wr_off[id], X, x_bf16, Y, n->P[id].rows, n->P[id].cols / 9, Bn, hh,
+                        ww, bias(n, id), true, st);
+  };
+  // activations in the FP32 buffers' memory, as BF16
+  uint16_t *e1a = h(p.e1a), *cat1 = h(p.cat1), *s1 = cat1 + 32 * N, *p1 = h(p.p1);
+  uint16_t *e2a = h(p.e2a), *cat2 = h(p.cat2), *s2 = cat2 + 64 * N2, *p2 = h(p.p2);
+  uint16_t *e3a = h(p.e3a), *b3 = h(p.b3), *d2a = h(p.d2a), *d2 = h(p.d2), *d1a = h(p.d1a), *d1 = h(p.d1);
+  bool ok = conv(E1A, unet_in, false, e1a, H, W) && conv(E1B, e1a, true, s1, H, W);
+  if (ok) {
+    pool_h(s1, p1, 32 * Bn, H, W, st);
+    ok = conv(E2A, p1, true, e2a, H / 2, W / 2) && conv(E2B, e2a, true, s2, H / 2, W / 2);
+  }
+  if (ok) {
+    pool_h(s2, p2, 64 * Bn, H / 2, W / 2, st);
+    ok = conv(E3A, p2, true, e3a, H / 4, W / 4) && conv(E3B, e3a, true, b3, H / 4, W / 4) &&
+         up_direct_h(wbf(n, U2), b3, bias(n, U2), cat2, 64, 128, Bn, H / 4, W / 4, st) &&
+         conv(D2A, cat2, true, d2a, H / 2, W / 2) && conv(D2B, d2a, true, d2, H / 2, W / 2) &&
+         up_direct_h(wbf(n, U1), d2, bias(n, U1), cat1, 32, 64, Bn, H / 2, W / 2, st) &&
+         conv(D1A, cat1, true, d1a, H, W) && conv(D1B, d1a, true, d1, H, W);
+  }
+  if (ok) conv1_out_h(wbf(n, FO), d1, bias(n, FO), at<float>(n, p.logit), n->P[FO].cols, N, st);
+  chk(hipGetLastError());
+  *err = e;
+  return ok;
+}
+
 hipError_t backward(seg_nn* n, int Bn, hipStream_t st) {
   const Plan& p = n->plan;
   const int H = p.H, W = p.W;
@@ -580,7 +646,9 @@ static int run_forward(seg_nn* n, const uint16_t* frames, const float* stin, uin
   if ((n->st ? (const void*)stin : (const void*)frames) == nullptr || batch < 1 || (int)batch > n->plan.B)
     return SEG_E_INVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (forward(n, frames, stin, (int)batch, st) != hipSuccess) return SEG_E_DEVICE;
+  hipError_t fe = hipSuccess;
+  if (!forward_infer(n, frames, stin, (int)batch, st, &fe)) fe = forward(n, frames, stin, (int)batch, st);
+  if (fe != hipSuccess) return SEG_E_DEVICE;
   const long long N = (long long)batch * n->plan.H * n->plan.W;
   bce(at<float>(n, n->plan.logit), nullptr, nullptr, dev_prob ? dev_prob : at<float>(n, n->plan.prob), nullptr, N,
       st);

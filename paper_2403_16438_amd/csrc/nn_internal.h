@@ -44,6 +44,19 @@ bool up_direct(const uint16_t* Wb, const float* X, const float* bias, float* Y, 
 // Y [N] = bias[0] + W [1][C] X [C][N] (BF16 operands, FP32 accumulation);
 // always launched (returns true).
 bool conv1_out(const uint16_t* Wb, const float* X, const float* bias, float* Y, int C, long long N, hipStream_t st);
+// BF16 activations (inference): the halo-tile convolution with X FP32 or
+// BF16 (x_bf16) and Y BF16, the BF16 rounding of what conv3_implicit stores;
+// false (nothing launched) when the shape does not fit the halo tiles
+bool conv3_halo_h(const uint16_t* Wr, const void* X, bool x_bf16, uint16_t* Y, int Co, int Ci, int Bn, int H, int W,
+                  const float* bias, bool relu, hipStream_t st);
+// up_direct with BF16 X and Y (false under the same conditions)
+bool up_direct_h(const uint16_t* Wb, const uint16_t* X, const float* bias, uint16_t* Y, int Co, int Ci, int Bn, int h,
+                 int w, hipStream_t st);
+// conv1_out with BF16 X
+void conv1_out_h(const uint16_t* Wb, const uint16_t* X, const float* bias, float* Y, int C, long long N,
+                 hipStream_t st);
+// 2 x 2 max pooling of BF16 activations, without the argmax
+void pool_h(const uint16_t* X, uint16_t* Y, int CB, int H, int W, hipStream_t st);
 // Wr [ceil(Ci / 16)][Co][9][16] from W [Co][Ci 9] (zero past Ci)
 void conv3_reorder(const uint16_t* Wb, uint16_t* Wr, int Co, int Ci, hipStream_t st);
 size_t conv3_reordered_size(int Co, int Ci);

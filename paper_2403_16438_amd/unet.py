@@ -102,6 +102,12 @@ class SummaryUNet:
                                             _st(self.device)), "seg_nn_st_forward")
         return out
 
+    def logits(self) -> torch.Tensor:
+        """Logits [B, H, W] of the last forward or backward call."""
+        out = torch.empty((self.B, self.H, self.W), dtype=torch.float32, device=self.device)
+        abi.check(abi.lib.seg_nn_logits(self.handle, C.c_void_p(out.data_ptr()), _st(self.device)), "seg_nn_logits")
+        return out
+
     def backward(self, st: torch.Tensor, labels: torch.Tensor, want_grad=False):
         b = st.shape[0]
         loss = C.c_float()

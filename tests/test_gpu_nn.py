@@ -11,6 +11,7 @@ from oracle import nn_ref
 from paper_2403_16438_amd.surrogate import Surrogate, gemm_test, he_init, param_layout
 
 pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
 
 
 @pytest.mark.parametrize("M,N,K,at,bt,splits", [(64, 64, 32, 0, 0, 1), (37, 70, 45, 0, 0, 1),
@@ -98,6 +99,26 @@ def test_forward_probabilities(case):
     err = np.abs(p - ref)
     print("prob error max", err.max(), "mean", err.mean())
     assert err.mean() <= 2e-3 and err.max() <= 2e-2
+
+
+def test_bf16_activation_forward_equals_training_forward():
+    """The surrogate's forward-only call keeps the U-Net's activations as
+    BF16 (frame width a multiple of 32); its logits must equal, bit for bit,
+    those of the training forward with FP32 activations."""
+    rng = np.random.default_rng(12)
+    frames = rng.poisson(600.0, size=(2, 50, 64, 64)).astype(np.uint16)
+    frames[:, 20:30, 10:18, 40:48] += 300
+    fd = torch.from_numpy(frames.view(np.int16)).to(DEV)
+    labels = torch.zeros((2, 64, 64), dtype=torch.float32, device=DEV)
+    labels[:, 10:18, 40:48] = 1
+    net = Surrogate(2, 64, 64, he_init(4))
+    net.forward(fd)
+    li = net.logits().clone()
+    net.backward(fd, labels)
+    lt = net.logits()
+    torch.cuda.synchronize()
+    assert torch.equal(li, lt), (li - lt).abs().max().item()
+    net.close()
 
 
 def test_rmsprop_reduces_loss(case):

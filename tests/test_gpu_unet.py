@@ -154,6 +154,31 @@ def test_convolution_paths_vs_reference(B, H, W):
     net.close()
 
 
+def test_bf16_activation_forward_equals_training_forward():
+    """The forward-only call keeps the activations as BF16 where every layer
+    fits the BF16 kernels (64 x 64 patches); every consumer rounds its input
+    to BF16 anyway, so its logits must equal, bit for bit, those of the
+    training forward (FP32 activations) that the backward call runs."""
+    rng = np.random.default_rng(11)
+    S = rng.uniform(800, 1200, (4, 64, 64))
+    T = rng.uniform(0, 60, (4, 64, 64))
+    T[:, 20:28, 30:38] += 180
+    st = torch.from_numpy(np.stack([S, T], axis=1).astype(np.float32)).to(DEV)
+    labels = torch.zeros((4, 64, 64), dtype=torch.float32, device=DEV)
+    labels[:, 20:28, 30:38] = 1
+    theta = he_init(3)
+    theta += (0.01 * rng.standard_normal(theta.size)).astype(np.float32)
+    net = SummaryUNet(4, 64, 64, theta)
+    p = net.forward(st)
+    li = net.logits().clone()
+    net.backward(st, labels)
+    lt = net.logits()
+    torch.cuda.synchronize()
+    assert torch.equal(li, lt), (li - lt).abs().max().item()
+    assert torch.equal(p, torch.sigmoid(lt)) or (p - torch.sigmoid(lt)).abs().max().item() < 1e-6
+    net.close()
+
+
 def test_rmsprop_reduces_loss(case):
     st, labels, theta = case
     net = SummaryUNet(2, 16, 16, theta)
