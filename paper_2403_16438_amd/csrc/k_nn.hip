@@ -355,35 +355,56 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   using XV = typename std::conditional<XH, uint32_t, float>::type;   // a loaded input value
   XV xv[XI][8];
   uint4 wv4[WI];
-  uint32_t okx[XI], okw;   // which loaded values are real (the rest become zero)
+  uint32_t okx[XI], okw = 0;   // which loaded values are real (the rest become zero)
+  // per item, fixed over the chunks: its channel-0 address (position
+  // clamped into the image, so always valid), whether it is a real tile
+  // position inside the image, and its channel group g (0 or 1)
+  const long long cs = (long long)Bn * HW;   // channel stride
+  const TX* ib[XI];
+  int ig[XI];
+  uint32_t iin = 0;
+#pragma unroll
+  for (int j = 0; j < XI; ++j) {
+    const int e = tid + 256 * j;
+    const int g = e >= np ? 1 : 0, pos = e - g * np, r = pos / TC, cc = pos - r * TC;
+    const int y = y0 + r - 1, x = x0 + cc - 1;
+    iin |= (uint32_t)(e < 2 * np && y >= 0 && y < H && x >= 0 && x < W) << j;
+    const int yc = min(max(y, 0), H - 1), xc = min(max(x, 0), W - 1);
+    ib[j] = X + (long long)b * HW + (long long)yc * W + xc;
+    ig[j] = 8 * g;
+  }
+  // weights: item j's row (clamped output channel) and 16-byte group
+  const int wstep = Co * 9 * HC;
+  int wo[WI];
+#pragma unroll
+  for (int j = 0; j < WI; ++j) {
+    const int e = tid + 256 * j, m = e / 18, q = e - m * 18, co = co0 + m;
+    okw |= (uint32_t)(e < MT * 18 && co < Co) << j;
+    wo[j] = min(co0 + min(m, MT - 1), Co - 1) * 9 * HC + 8 * q;
+  }
+  const bool full = Ci % HC == 0;   // no chunk runs past the last channel
   auto load = [&](int c0) {
 #pragma unroll
     for (int j = 0; j < XI; ++j) {
-      const int e = tid + 256 * j;
-      const int g = e >= np ? 1 : 0, pos = e - g * np, r = pos / TC, cc = pos - r * TC;
-      const int y = y0 + r - 1, x = x0 + cc - 1;
-      const bool in = e < 2 * np && y >= 0 && y < H && x >= 0 && x < W;
-      // clamped into the image and the channel range: always a valid address
-      const int yc = min(max(y, 0), H - 1), xc = min(max(x, 0), W - 1);
-      const TX* src = X + (long long)b * HW + (long long)yc * W + xc;
-      okx[j] = 0;
+      const int cb = c0 + ig[j];
+      if (full) {
+        const TX* src = ib[j] + (long long)cb * cs;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int c = c0 + 8 * g + q;
-        xv[j][q] = src[(long long)min(c, Ci - 1) * Bn * HW];
-        okx[j] |= (uint32_t)(in && c < Ci) << q;
+        for (int q = 0; q < 8; ++q) xv[j][q] = src[(long long)q * cs];
+        okx[j] = (iin >> j & 1u) ? 0xffu : 0u;
+      } else {
+        okx[j] = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int c = cb + q;
+          xv[j][q] = ib[j][(long long)min(c, Ci - 1) * cs];
+          okx[j] |= (uint32_t)((iin >> j & 1u) && c < Ci) << q;
+        }
       }
     }
-    const uint16_t* wsrc = Wr + (long long)(c0 / HC) * Co * 9 * HC;
-    okw = 0;
+    const uint16_t* wsrc = Wr + (long long)(c0 / HC) * wstep;
 #pragma unroll
-    for (int j = 0; j < WI; ++j) {
-      const int e = tid + 256 * j, m = e / 18, q = e - m * 18, co = co0 + m;
-      const bool ok = e < MT * 18 && co < Co;
-      const int coc = min(co0 + min(m, MT - 1), Co - 1);   // clamped: always a valid address
-      wv4[j] = *reinterpret_cast<const uint4*>(wsrc + (long long)coc * 9 * HC + 8 * q);
-      okw |= (uint32_t)ok << j;
-    }
+    for (int j = 0; j < WI; ++j) wv4[j] = *reinterpret_cast<const uint4*>(wsrc + wo[j]);
   };
   load(0);
   for (int c0 = 0; c0 < Ci; c0 += HC) {
