@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
 // value is loaded and converted once per chunk instead of once per (ky, kx),
 // and the nine offsets read it from LDS.
 constexpr int HC = 16;                          // input channels per chunk
-constexpr int HX = 4224;                        // largest halo tile: 4 x 66 x 16
+constexpr int HX = 6336;                        // largest halo tile: 6 x 66 x 16
 // Convolution weights reordered for k_conv3_halo: Wr[chunk][co][ky 3 + kx][cl]
 // = W[co][9 (16 chunk + cl) + ky 3 + kx] (0 past Ci), so that a chunk's
 // weights of one output channel are 144 contiguous values.
@@ -318,13 +318,13 @@ __global__ void k_conv3_reorder(const uint16_t* __restrict__ Wb, uint16_t* __res
 // output is the BF16 rounding of the FP32 value, which is what the next
 // layer's staging (or the 1 x 1 output layer) makes of an FP32 output, so
 // the two give the same network outputs.
-template <int MT, typename TX, typename TY>
+template <int MT, int NTW, typename TX, typename TY>
 __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__ Wr, const TX* __restrict__ X,
                                                     const float* __restrict__ bias, int relu,
                                                     TY* __restrict__ Y, int Co, int Ci, int Bn, int H, int W,
                                                     int BC) {
   constexpr bool XH = sizeof(TX) == 2;
-  constexpr int NT = 4096 / MT;
+  constexpr int NT = 4096 / MT * NTW;   // pixels: NTW 32-pixel blocks per wave
   __shared__ __attribute__((aligned(16))) uint16_t Xs[HX];
   __shared__ __attribute__((aligned(16))) uint16_t Ws[MT][9 * HC + 8];
   const int BR = NT / BC, TC = BC + 2, TR = BR + 2;
@@ -335,12 +335,21 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   const int y0 = (rem / bx) * BR, x0 = (rem % bx) * BC;
   const int co0 = blockIdx.y * MT;
   const long long HW = (long long)H * W;
-  // this lane's pixel and its place in the halo tile
-  const int pl = wn * 32 + (lane & 31), pr = pl / BC, pc = pl - pr * BC;
-  const int kg = (lane >> 5) * 8;
-  f32x16 acc;
+  // this lane's pixels (one per 32-pixel block of the wave) and their place
+  // in the halo tile
+  int pr[NTW], pc[NTW];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  for (int t = 0; t < NTW; ++t) {
+    const int pl = (wn * NTW + t) * 32 + (lane & 31);
+    pr[t] = pl / BC;
+    pc[t] = pl - pr[t] * BC;
+  }
+  const int kg = (lane >> 5) * 8;
+  f32x16 acc[NTW];
+#pragma unroll
+  for (int t = 0; t < NTW; ++t)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
   // Staging: a thread takes 8 channels of a tile position (8 loads, each
   // coalesced over the positions; one 16-byte LDS store) and 16-byte groups
   // of the reordered weights. Every load is issued unconditionally (positions
@@ -350,7 +359,7 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   // The next chunk's loads are issued before the current chunk's MFMAs and
   // converted only when stored.
   const int np = TR * TC;
-  constexpr int XI = MT == 64 ? 2 : 3;                // input items per thread: 2 np <= 256 XI
+  constexpr int XI = MT == 64 ? 1 + NTW : 2 + NTW;     // input items per thread: 2 np <= 256 XI
   constexpr int WI = (MT * 18 + 255) / 256;
   using XV = typename std::conditional<XH, uint32_t, float>::type;   // a loaded input value
   XV xv[XI][8];
@@ -446,35 +455,41 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
 #pragma unroll
     for (int kyx = 0; kyx < 9; ++kyx) {
       const int ky = kyx / 3, kx = kyx - 3 * ky;
-      bf16x8 a, bb;
+      bf16x8 a;
       const uint16_t* ap = &Ws[wm * 32 + (lane & 31)][kyx * HC + kg];
-      const uint16_t* bp = &Xs[((pr + ky) * TC + pc + kx) * HC + kg];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        a[q] = __builtin_bit_cast(__bf16, ap[q]);
-        bb[q] = __builtin_bit_cast(__bf16, bp[q]);
+      for (int q = 0; q < 8; ++q) a[q] = __builtin_bit_cast(__bf16, ap[q]);
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        bf16x8 bb;
+        const uint16_t* bp = &Xs[((pr[t] + ky) * TC + pc[t] + kx) * HC + kg];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bb[q] = __builtin_bit_cast(__bf16, bp[q]);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[t], 0, 0, 0);
       }
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
     }
   }
-  const int y = y0 + pr, x = x0 + pc;
-  if (y >= H || x >= W) return;
-  TY* yp = Y + (long long)b * HW + (long long)y * W + x;
   float bv[16];   // biases loaded together (clamped index), used where co < Co
 #pragma unroll
   for (int k = 0; k < 16; ++k) bv[k] = bias[min(co0 + wm * 32 + 8 * (k >> 2) + 4 * (lane >> 5) + (k & 3), Co - 1)];
 #pragma unroll
-  for (int g = 0; g < 4; ++g)
+  for (int t = 0; t < NTW; ++t) {
+    const int y = y0 + pr[t], x = x0 + pc[t];
+    if (y >= H || x >= W) continue;
+    TY* yp = Y + (long long)b * HW + (long long)y * W + x;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int co = co0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
-      if (co < Co) {
-        float v = acc[4 * g + r] + bv[4 * g + r];
-        if (relu) v = fmaxf(v, 0.f);
-        if constexpr (sizeof(TY) == 2) yp[(long long)co * Bn * HW] = to_bf16(v);
-        else yp[(long long)co * Bn * HW] = v;
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = co0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
+        if (co < Co) {
+          float v = acc[t][4 * g + r] + bv[4 * g + r];
+          if (relu) v = fmaxf(v, 0.f);
+          if constexpr (sizeof(TY) == 2) yp[(long long)co * Bn * HW] = to_bf16(v);
+          else yp[(long long)co * Bn * HW] = v;
+        }
       }
-    }
+  }
 }
 
 // 1 x 1 convolution to one output channel plus its bias, one pixel per
@@ -828,23 +843,30 @@ __device__ __forceinline__ int st_count(int n) { return (n - 64 + 31) / 32 + 1; 
 __device__ __forceinline__ int st_origin(int k, int n) { return min(32 * k, n - 64); }
 
 // out [n_patch][2][64][64], patches in raster order of their origins
+// grid y: segment (S, T planes H W apart; patches np 2 4096 apart)
 __global__ void k_st_patches(const float* __restrict__ S, const float* __restrict__ T, int H, int W,
                              float* __restrict__ out) {
   const int nx = st_count(W);
   const long long total = (long long)st_count(H) * nx * 2 * 4096;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
+  S += (long long)blockIdx.y * H * W;
+  T += (long long)blockIdx.y * H * W;
+  out += (long long)blockIdx.y * total;
   const int k = (int)(i / 8192), r = (int)(i % 8192), c = r / 4096, y = (r % 4096) / 64, x = r % 64;
   const int oy = st_origin(k / nx, H), ox = st_origin(k % nx, W);
   out[i] = (c ? T : S)[(size_t)(oy + y) * W + ox + x];
 }
 
 // out(y, x) = sum_k w w prob_k / sum_k w w over the patches that hold the pixel
+// grid y: segment (probabilities np 4096 apart, maps H W apart)
 __global__ void k_st_merge(const float* __restrict__ prob, int H, int W, float* __restrict__ out) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)H * W) return;
   const int y = (int)(i / W), x = (int)(i % W);
   const int ny = st_count(H), nx = st_count(W);
+  prob += (long long)blockIdx.y * ny * nx * 4096;
+  out += (long long)blockIdx.y * H * W;
   double num = 0.0, den = 0.0;
   for (int ky = 0; ky < ny; ++ky) {
     const int oy = st_origin(ky, H);
@@ -922,17 +944,17 @@ bool conv3_halo(const uint16_t* Wr, const TX* X, TY* Y, int Co, int Ci, int Bn, 
                 bool relu, hipStream_t st) {
   if (!(Wr && W % 8 == 0 && bias && (long long)Bn * H * W <= 0x7fffffffLL && ((uintptr_t)Wr & 15) == 0))
     return false;
-  const int MT = Co <= 32 ? 32 : 64, NT = 4096 / MT, BC = W < 64 ? W : 64;
+  const int MT = Co <= 32 ? 32 : 64, NTW = 2, NT = 4096 / MT * NTW, BC = W < 64 ? W : 64;
   const int np = (NT / BC + 2) * (BC + 2);
-  if (!(NT % BC == 0 && np * HC <= HX && 2 * np <= 256 * (MT == 64 ? 2 : 3))) return false;
+  if (!(NT % BC == 0 && np * HC <= HX && 2 * np <= 256 * (MT == 64 ? 1 + NTW : 2 + NTW))) return false;
   const int BR = NT / BC;
   const long long blocks = (long long)Bn * ((H + BR - 1) / BR) * ((W + BC - 1) / BC);
   if (MT == 32)
-    hipLaunchKernelGGL((k_conv3_halo<32, TX, TY>), dim3((unsigned)blocks, (Co + 31) / 32), dim3(256), 0, st, Wr, X,
-                       bias, (int)relu, Y, Co, Ci, Bn, H, W, BC);
+    hipLaunchKernelGGL((k_conv3_halo<32, 2, TX, TY>), dim3((unsigned)blocks, (Co + 31) / 32), dim3(256), 0, st, Wr,
+                       X, bias, (int)relu, Y, Co, Ci, Bn, H, W, BC);
   else
-    hipLaunchKernelGGL((k_conv3_halo<64, TX, TY>), dim3((unsigned)blocks, (Co + 63) / 64), dim3(256), 0, st, Wr, X,
-                       bias, (int)relu, Y, Co, Ci, Bn, H, W, BC);
+    hipLaunchKernelGGL((k_conv3_halo<64, 2, TX, TY>), dim3((unsigned)blocks, (Co + 63) / 64), dim3(256), 0, st, Wr,
+                       X, bias, (int)relu, Y, Co, Ci, Bn, H, W, BC);
   return true;
 }
 }  // namespace
@@ -1049,10 +1071,15 @@ void st_norm(const float* stin, float* x, int Bn, long long HW, hipStream_t stre
 }
 int st_origins(int n) { return (n - 64 + 31) / 32 + 1; }
 void st_patches(const float* S, const float* T, int H, int W, float* out, hipStream_t st) {
-  L1(k_st_patches, (long long)st_origins(H) * st_origins(W) * 2 * 4096, S, T, H, W, out);
+  st_patches_n(S, T, H, W, 1, out, st);
 }
-void st_merge(const float* prob, int H, int W, float* out, hipStream_t st) {
-  L1(k_st_merge, (long long)H * W, prob, H, W, out);
+void st_merge(const float* prob, int H, int W, float* out, hipStream_t st) { st_merge_n(prob, H, W, 1, out, st); }
+void st_patches_n(const float* S, const float* T, int H, int W, int n, float* out, hipStream_t st) {
+  const long long total = (long long)st_origins(H) * st_origins(W) * 2 * 4096;
+  hipLaunchKernelGGL(k_st_patches, dim3(grid1(total).x, n), dim3(256), 0, st, S, T, H, W, out);
+}
+void st_merge_n(const float* prob, int H, int W, int n, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_st_merge, dim3(grid1((long long)H * W).x, n), dim3(256), 0, st, prob, H, W, out);
 }
 
 }  // namespace nn

@@ -88,6 +88,10 @@ int st_origins(int n);
 void st_patches(const float* S, const float* T, int H, int W, float* out, hipStream_t stream);
 // tent-weighted mean of patch probabilities [n_patch][64][64] over the frame
 void st_merge(const float* prob, int H, int W, float* out, hipStream_t stream);
+// the same for n segments in one launch: S, T and out planes H W apart,
+// patches [n][n_patch][2][64][64], probabilities [n][n_patch][64][64]
+void st_patches_n(const float* S, const float* T, int H, int W, int n, float* out, hipStream_t stream);
+void st_merge_n(const float* prob, int H, int W, int n, float* out, hipStream_t stream);
 
 }  // namespace nn
 }  // namespace seg

@@ -13,6 +13,7 @@
 #include "seg_internal.h"
 #include "seg_traces.h"
 #include "seg_nn.h"
+#include "nn_internal.h"
 
 using seg::Layout;
 using seg::State;
@@ -169,21 +170,17 @@ int unet_maps(seg_session* s, uint32_t first, uint32_t nseg, hipStream_t st) {
   float* prob = in + (size_t)seg::kUnetGroup * np * 2 * 4096;
   for (uint32_t j0 = 0; j0 < nseg; j0 += seg::kUnetGroup) {
     const uint32_t g = std::min<uint32_t>(seg::kUnetGroup, nseg - j0);
-    for (uint32_t q = 0; q < g; ++q) {
-      const size_t k = first + j0 + q;
-      if (seg_nn_st_patches(at<float>(s, s->lay.S) + k * M, at<float>(s, s->lay.T) + k * M, H, W,
-                            in + (size_t)q * np * 2 * 4096, st))
-        return fail(s, hipErrorUnknown);
-    }
+    // the group's patches, and below its maps, in one launch each
+    seg::nn::st_patches_n(at<float>(s, s->lay.S) + (first + j0) * M, at<float>(s, s->lay.T) + (first + j0) * M,
+                          (int)H, (int)W, (int)g, in, st);
     const uint32_t total = g * np;
     for (uint32_t a = 0; a < total; a += B) {
       const uint32_t b = std::min(B, total - a);
       if (seg_nn_st_forward(s->net, in + (size_t)a * 2 * 4096, b, prob + (size_t)a * 4096, st))
         return fail(s, hipErrorUnknown);
     }
-    for (uint32_t q = 0; q < g; ++q)
-      if (seg_nn_st_merge(prob + (size_t)q * np * 4096, H, W, at<float>(s, s->lay.p) + (first + j0 + q) * M, st))
-        return fail(s, hipErrorUnknown);
+    seg::nn::st_merge_n(prob, (int)H, (int)W, (int)g, at<float>(s, s->lay.p) + (first + j0) * M, st);
+    if (hipGetLastError() != hipSuccess) return fail(s, hipErrorUnknown);
   }
   return SEG_OK;
 }
