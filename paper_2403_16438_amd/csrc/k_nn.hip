@@ -517,6 +517,98 @@ __global__ void k_conv1_out_h(const uint16_t* __restrict__ Wb, const uint16_t* _
   Y[i] = s + bias[0];
 }
 
+// Direct 3 x 3 convolution of inputs with at most two channels (the summary
+// U-Net's first layer, input S and T) to at most 32 output channels: the
+// depth of the product is k = 9 c + 3 ky + kx (the weights' own order),
+// 18 values padded to two MFMA steps of 16, instead of one 16-channel chunk
+// per (ky, kx) with 14 channels of zeros. A workgroup computes 32 output
+// channels x 256 pixels (4 rows x 64 columns when W >= 64); the halo tile
+// holds both channels of a position as one BF16 pair.
+constexpr int C2_TX = 6 * 66;   // largest halo tile (positions)
+template <typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_conv3_c2(const uint16_t* __restrict__ Wb, const TX* __restrict__ X,
+                                                  const float* __restrict__ bias, int relu, TY* __restrict__ Y,
+                                                  int Co, int Ci, int Bn, int H, int W, int BC) {
+  constexpr int NT = 256;
+  __shared__ uint32_t Xs[C2_TX];          // (c0, c1) BF16 pairs
+  __shared__ uint16_t Ws[32][32 + 8];
+  const int BR = NT / BC, TC = BC + 2, TR = BR + 2, np = TR * TC;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int bx = (W + BC - 1) / BC, by = (H + BR - 1) / BR;
+  const int blk = blockIdx.x, b = blk / (bx * by), rem = blk - b * bx * by;
+  const int y0 = (rem / bx) * BR, x0 = (rem % bx) * BC;
+  const long long HW = (long long)H * W;
+  // halo tile: both channels of each position (zero outside the image)
+  for (int e = tid; e < np; e += 256) {
+    const int r = e / TC, cc = e - r * TC, y = y0 + r - 1, x = x0 + cc - 1;
+    uint16_t v0 = 0, v1 = 0;
+    if (y >= 0 && y < H && x >= 0 && x < W) {
+      const TX* src = X + (long long)b * HW + (long long)y * W + x;
+      if constexpr (sizeof(TX) == 2) {
+        v0 = src[0];
+        if (Ci > 1) v1 = src[(long long)Bn * HW];
+      } else {
+        v0 = to_bf16(src[0]);
+        if (Ci > 1) v1 = to_bf16(src[(long long)Bn * HW]);
+      }
+    }
+    Xs[e] = v0 | ((uint32_t)v1 << 16);
+  }
+  // weights [co][k], k = 9 c + tap, zero past 9 Ci
+  for (int e = tid; e < 32 * 32; e += 256) {
+    const int co = e >> 5, k = e & 31;
+    Ws[co][k] = (co < Co && k < 9 * Ci) ? Wb[(long long)co * 9 * Ci + k] : (uint16_t)0;
+  }
+  __syncthreads();
+  const int kg = (lane >> 5) * 8;
+  f32x16 acc[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+#pragma unroll
+  for (int st = 0; st < 2; ++st) {
+    bf16x8 a;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = __builtin_bit_cast(__bf16, Ws[lane & 31][16 * st + kg + q]);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int pl = (wv * 2 + t) * 32 + (lane & 31), pr = pl / BC, pc = pl - pr * BC;
+      bf16x8 bb;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = 16 * st + kg + q, c = k / 9, tap = k - 9 * c, ky = tap / 3, kx = tap - 3 * ky;
+        uint16_t v = 0;
+        if (k < 9 * Ci) {
+          const uint32_t pair = Xs[(pr + ky) * TC + pc + kx];
+          v = (uint16_t)(c ? pair >> 16 : pair);
+        }
+        bb[q] = __builtin_bit_cast(__bf16, v);
+      }
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int pl = (wv * 2 + t) * 32 + (lane & 31), pr = pl / BC, pc = pl - pr * BC;
+    const int y = y0 + pr, x = x0 + pc;
+    if (y >= H || x >= W) continue;
+    TY* yp = Y + (long long)b * HW + (long long)y * W + x;
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = 8 * g + 4 * (lane >> 5) + r;
+        if (co < Co) {
+          float v = acc[t][4 * g + r] + bias[co];
+          if (relu) v = fmaxf(v, 0.f);
+          if constexpr (sizeof(TY) == 2) yp[(long long)co * Bn * HW] = to_bf16(v);
+          else yp[(long long)co * Bn * HW] = v;
+        }
+      }
+  }
+}
+
 // sum the split-K partials in order: C[m][n] (+)= sum_z P[z][m][n]
 __global__ void k_splitk_reduce(const float* __restrict__ P, float* __restrict__ C, long long MN, int Z,
                                 int accumulate) {
@@ -940,10 +1032,19 @@ namespace {
 // shape check and launch of the halo-tile convolution; false when the shape
 // does not fit it
 template <typename TX, typename TY>
-bool conv3_halo(const uint16_t* Wr, const TX* X, TY* Y, int Co, int Ci, int Bn, int H, int W, const float* bias,
-                bool relu, hipStream_t st) {
+bool conv3_halo(const uint16_t* Wb, const uint16_t* Wr, const TX* X, TY* Y, int Co, int Ci, int Bn, int H, int W,
+                const float* bias, bool relu, hipStream_t st) {
   if (!(Wr && W % 8 == 0 && bias && (long long)Bn * H * W <= 0x7fffffffLL && ((uintptr_t)Wr & 15) == 0))
     return false;
+  if (Ci <= 2 && Co <= 32) {   // first layer: the depth is 9 Ci, two MFMA steps
+    const int BC = W < 64 ? W : 64;
+    if (256 % BC || (256 / BC + 2) * (BC + 2) > C2_TX) return false;
+    const int BR = 256 / BC;
+    const long long blocks = (long long)Bn * ((H + BR - 1) / BR) * ((W + BC - 1) / BC);
+    hipLaunchKernelGGL((k_conv3_c2<TX, TY>), dim3((unsigned)blocks), dim3(256), 0, st, Wb, X, bias, (int)relu, Y, Co,
+                       Ci, Bn, H, W, BC);
+    return true;
+  }
   const int MT = Co <= 32 ? 32 : 64, NTW = 2, NT = 4096 / MT * NTW, BC = W < 64 ? W : 64;
   const int np = (NT / BC + 2) * (BC + 2);
   if (!(NT % BC == 0 && np * HC <= HX && 2 * np <= 256 * (MT == 64 ? 1 + NTW : 2 + NTW))) return false;
@@ -959,17 +1060,17 @@ bool conv3_halo(const uint16_t* Wr, const TX* X, TY* Y, int Co, int Ci, int Bn, 
 }
 }  // namespace
 
-bool conv3_halo_h(const uint16_t* Wr, const void* X, bool x_bf16, uint16_t* Y, int Co, int Ci, int Bn, int H, int W,
-                  const float* bias, bool relu, hipStream_t st) {
-  return x_bf16 ? conv3_halo(Wr, static_cast<const uint16_t*>(X), Y, Co, Ci, Bn, H, W, bias, relu, st)
-                : conv3_halo(Wr, static_cast<const float*>(X), Y, Co, Ci, Bn, H, W, bias, relu, st);
+bool conv3_halo_h(const uint16_t* Wb, const uint16_t* Wr, const void* X, bool x_bf16, uint16_t* Y, int Co, int Ci,
+                  int Bn, int H, int W, const float* bias, bool relu, hipStream_t st) {
+  return x_bf16 ? conv3_halo(Wb, Wr, static_cast<const uint16_t*>(X), Y, Co, Ci, Bn, H, W, bias, relu, st)
+                : conv3_halo(Wb, Wr, static_cast<const float*>(X), Y, Co, Ci, Bn, H, W, bias, relu, st);
 }
 
 bool conv3_implicit(const uint16_t* Wb, const uint16_t* Wr, const float* X, float* Y, int Co, int Ci, int Bn,
                     int H, int W, const float* bias, bool relu, hipStream_t st) {
   // direct convolution over halo tiles where a block of whole 8-aligned
   // columns fits the tile
-  if (conv3_halo(Wr, X, Y, Co, Ci, Bn, H, W, bias, relu, st)) return true;
+  if (conv3_halo(Wb, Wr, X, Y, Co, Ci, Bn, H, W, bias, relu, st)) return true;
   const int K = Ci * 9;
   const long long N = (long long)Bn * H * W;
   if (W % 8 || K % 8 || ((uintptr_t)Wb & 15) || N > 0x7fffffffLL) return false;

@@ -413,8 +413,8 @@ bool forward_infer(seg_nn* n, const uint16_t* frames, const float* stin, int Bn,
   }
   auto h = [&](const Buf& b) { return at<uint16_t>(n, b); };
   auto conv = [&](int id, const void* X, bool x_bf16, uint16_t* Y, int hh, int ww) {
-    return conv3_halo_h(at<uint16_t>(n, p.wr) + p.wr_off[id], X, x_bf16, Y, n->P[id].rows, n->P[id].cols / 9, Bn, hh,
-                        ww, bias(n, id), true, st);
+    return conv3_halo_h(wbf(n, id), at<uint16_t>(n, p.wr) + p.wr_off[id], X, x_bf16, Y, n->P[id].rows,
+                        n->P[id].cols / 9, Bn, hh, ww, bias(n, id), true, st);
   };
   // activations in the FP32 buffers' memory, as BF16
   uint16_t *e1a = h(p.e1a), *cat1 = h(p.cat1), *s1 = cat1 + 32 * N, *p1 = h(p.p1);

@@ -47,8 +47,8 @@ bool conv1_out(const uint16_t* Wb, const float* X, const float* bias, float* Y, 
 // BF16 activations (inference): the halo-tile convolution with X FP32 or
 // BF16 (x_bf16) and Y BF16, the BF16 rounding of what conv3_implicit stores;
 // false (nothing launched) when the shape does not fit the halo tiles
-bool conv3_halo_h(const uint16_t* Wr, const void* X, bool x_bf16, uint16_t* Y, int Co, int Ci, int Bn, int H, int W,
-                  const float* bias, bool relu, hipStream_t st);
+bool conv3_halo_h(const uint16_t* Wb, const uint16_t* Wr, const void* X, bool x_bf16, uint16_t* Y, int Co, int Ci,
+                  int Bn, int H, int W, const float* bias, bool relu, hipStream_t st);
 // up_direct with BF16 X and Y (false under the same conditions)
 bool up_direct_h(const uint16_t* Wb, const uint16_t* X, const float* bias, uint16_t* Y, int Co, int Ci, int Bn, int h,
                  int w, hipStream_t st);
