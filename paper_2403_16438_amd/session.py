@@ -147,14 +147,19 @@ class Session:
 
 def segment_video(video: np.ndarray, block: int | None = None, net=None, **overrides) -> Session:
     """Push a host uint16 video [T, H, W] (in blocks of `block` frames) and
-    finalize. Returns the finalized session. With `net` (a Surrogate) the
-    learned detector is used (events at probability >= 0.5, c_min = 2): a
-    Surrogate reads the frames, a SummaryUNet the summary patches."""
+    finalize. Returns the finalized session. With `net` the learned detector
+    is used: a Surrogate reads the frames (events at probability >= 0.5,
+    c_min = 2), a SummaryUNet the summary patches (events at probability
+    >= 0.7, c_min = 3, the setting with the best F1 on validation recordings
+    of the training kind). Keyword overrides replace these."""
     T, H, W = video.shape
     if net is not None:
         from .unet import SummaryUNet
-        det = abi.SEG_DET_UNET if isinstance(net, SummaryUNet) else abi.SEG_DET_SURROGATE
-        overrides = dict(dict(detector=det, event_z=0.5, min_event_segs=2), **overrides)
+        if isinstance(net, SummaryUNet):
+            learned = dict(detector=abi.SEG_DET_UNET, event_z=0.7, min_event_segs=3)
+        else:
+            learned = dict(detector=abi.SEG_DET_SURROGATE, event_z=0.5, min_event_segs=2)
+        overrides = dict(learned, **overrides)
     s = Session(H, W, max(T, 50), **overrides)
     if net is not None:
         s.set_model(net)

@@ -218,7 +218,7 @@ def test_models_and_errors():
 def trained():
     from paper_2403_16438_amd.train import SummaryBank, train_unet
     bank = SummaryBank(120, device="cuda")
-    net, losses = train_unet(steps=2500, batch=32, lr=1e-3, bank=bank)
+    net, losses = train_unet(steps=5000, batch=32, lr=1e-3, bank=bank)
     return net, losses
 
 
@@ -244,15 +244,20 @@ def test_session_maps_equal_network(trained):
 
 def test_segmentation_quality(trained, record_property):
     """Held-out recordings of the training kind: planted-truth F1 of the
-    paper's detector beside the plain one."""
+    paper's detector beside the plain one. The detector's event threshold
+    (0.7) and c_min (3) were chosen on other seeds (81-84) of the same kind;
+    the paper's OR aggregation (c_min = 1) is recorded beside them."""
     net, _ = trained
-    f_unet, f_plain = [], []
+    f_unet, f_or, f_plain = [], [], []
     for seed in (91, 92, 93):
         video, truth = simulate(preset(4, height=128, width=128, frames=1000, n_neurons=8, n_overlap=2,
                                        edge_margin=10.0), seed)
         f_unet.append(oracle.match_f1(segment_video(video, net=net).footprints()["masks"], truth.masks())["f1"])
+        f_or.append(oracle.match_f1(segment_video(video, net=net, min_event_segs=1).footprints()["masks"],
+                                    truth.masks())["f1"])
         f_plain.append(oracle.match_f1(segment_video(video).footprints()["masks"], truth.masks())["f1"])
     record_property("f1_unet", float(np.mean(f_unet)))
+    record_property("f1_unet_or", float(np.mean(f_or)))
     record_property("f1_plain", float(np.mean(f_plain)))
-    print("F1 summary U-Net", f_unet, "plain", f_plain)
-    assert np.mean(f_unet) >= 0.75      # measured 0.89 (plain 0.96)
+    print("F1 summary U-Net", f_unet, "with c_min = 1", f_or, "plain", f_plain)
+    assert np.mean(f_unet) >= 0.85      # measured 0.906 (c_min = 1: 0.873, plain 0.96)
