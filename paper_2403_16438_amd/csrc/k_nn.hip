@@ -3,6 +3,7 @@
 // FP32 in a [channel][batch][row][col] layout, so a convolution is one GEMM
 // whose output is already the next activation; matrix operands are rounded to
 // BF16 (round to nearest even) and multiplied on MFMA with FP32 accumulation.
+#include <algorithm>
 #include <cstdint>
 #include <type_traits>
 
@@ -126,9 +127,7 @@ __global__ __launch_bounds__(256) void k_gemm(const TA* __restrict__ A, long lon
 //             product, plus bias[co], is stored to C at channel co, pixel
 //             (2 y + a, 2 x + e) of an image of 2 H x 2 W (X's pixels H x W),
 //             so the product lands directly in the concatenation buffer.
-//   GV_UP_H   as GV_UP, with BF16 X [K][N] (row stride sbk, passed as B) and
-//             the stored values rounded to BF16 (C then holds BF16 bits)
-enum { GV_BF16 = 0, GV_IM2COL = 1, GV_UP = 2, GV_UP_H = 3 };
+enum { GV_BF16 = 0, GV_IM2COL = 1, GV_UP = 2 };
 struct Im2col {
   const float* X;
   int Bn, H, W;
@@ -173,7 +172,7 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int gkb = k0 + bk, gn = n0 + bn + 64 * j;
-      if constexpr (MODE == GV_BF16 || MODE == GV_UP_H) {
+      if constexpr (MODE == GV_BF16) {
         rb[j] = (gkb < K && gn < N) ? *reinterpret_cast<const uint4*>(B + gkb * sbk + gn) : make_uint4(0, 0, 0, 0);
       } else if constexpr (MODE == GV_UP) {
         uint4 v = make_uint4(0, 0, 0, 0);
@@ -238,21 +237,6 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
   }
   const int col = n0 + wn * 32 + (lane & 31);
   if (col >= N) return;
-  if constexpr (MODE == GV_UP_H) {
-    const int hw = ic.H * ic.W, b = col / hw, yx = col - b * hw, y = yx / ic.W, x = yx - y * ic.W;
-    uint16_t* base = reinterpret_cast<uint16_t*>(C) + (long long)b * 4 * hw + (long long)(2 * y) * (2 * ic.W) + 2 * x;
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
-        if (row < M) {
-          const int co = row >> 2, a = (row >> 1) & 1, e = row & 1;
-          base[(long long)co * ic.Bn * 4 * hw + a * 2 * ic.W + e] = to_bf16(acc[4 * g + r] + bias[co]);
-        }
-      }
-    return;
-  }
   if constexpr (MODE == GV_UP) {
     // row 4 co + 2 a + e of pixel (b, y, x) lands on (b, 2 y + a, 2 x + e) of channel co
     const int hw = ic.H * ic.W, b = col / hw, yx = col - b * hw, y = yx / ic.W, x = yx - y * ic.W;
@@ -314,19 +298,72 @@ __global__ void k_conv3_reorder(const uint16_t* __restrict__ Wb, uint16_t* __res
   Wr[i] = c < Ci ? Wb[(long long)co * Ci * 9 + c * 9 + kyx] : (uint16_t)0;
 }
 
-// TX, TY: float (FP32) or uint16_t (BF16 bits) activations in and out. A BF16
-// output is the BF16 rounding of the FP32 value, which is what the next
-// layer's staging (or the 1 x 1 output layer) makes of an FP32 output, so
-// the two give the same network outputs.
-template <int MT, int NTW, typename TX, typename TY>
+// Activations of the BF16 inference path are kept in channel blocks of 16:
+// element (c, b, y, x) of a [C][Bn][H][W] tensor (C a multiple of 16) sits at
+// ((c / 16) Bn H W + (b H + y) W + x) 16 + c % 16, so the 16 channels of one
+// pixel are 32 contiguous bytes. A 16-byte load then brings 8 channels of one
+// position, the depth order of an MFMA operand, where the planar layout took
+// one 2-byte load per channel; a concatenation along channels is still two
+// adjacent ranges of the buffer.
+__device__ __forceinline__ long long cblk(int c, long long pix, long long npix) {
+  return ((long long)(c >> 4) * npix + pix) * 16 + (c & 15);
+}
+
+// the value of lane ^ 1 (the neighbouring column of a 32-pixel row block)
+__device__ __forceinline__ uint32_t from_pair_lane(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false);   // quad_perm 1, 0, 3, 2
+}
+
+// A 32 x 32 MFMA result gives lanes l and l + 32 (l < 32) channels
+// 4 (l >> 5) + 0..3 (BF16 pairs a0, a1) and 8 + 4 (l >> 5) + 0..3 (b0, b1)
+// of one pixel's 16-channel block. Swapping the upper half of the lanes of
+// a with the lower half of b leaves each lane 8 consecutive channels, stored
+// with one 16-byte store: channels 0..7 in lanes 0..31, 8..15 in 32..63.
+__device__ __forceinline__ uint4 gather8(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1) {
+  const auto s0 = __builtin_amdgcn_permlane32_swap(a0, b0, false, false);
+  const auto s1 = __builtin_amdgcn_permlane32_swap(a1, b1, false, false);
+  return make_uint4(s0[0], s1[0], s0[1], s1[1]);
+}
+
+// the value of lane + 32 (lanes 0..31)
+__device__ __forceinline__ uint32_t from_upper_half(uint32_t v) {
+  return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1];
+}
+
+// first maximum of a, b, c, d in that order, compared as BF16 values (the
+// order and ties of k_pool's window scan)
+__device__ __forceinline__ uint16_t max4_bf16(uint16_t a, uint16_t b, uint16_t c, uint16_t d) {
+  uint16_t m = a;
+  if (from_bf16(b) > from_bf16(m)) m = b;
+  if (from_bf16(c) > from_bf16(m)) m = c;
+  if (from_bf16(d) > from_bf16(m)) m = d;
+  return m;
+}
+
+// TX: float (FP32, planar [Ci][Bn][H][W]) or uint16_t (BF16 bits, channel
+// blocks of 16) input; TY: float (planar) or uint16_t (BF16, channel blocks)
+// output. A BF16 output is the BF16 rounding of the FP32 value, which is what
+// the next layer's staging (or the 1 x 1 output layer) makes of an FP32
+// output, so the two give the same network outputs. EP (BF16 output only):
+//   CONV_STORE  store the activations;
+//   CONV_POOL   store them and their 2 x 2 max pooling (ep.pool, channel
+//               blocks, H / 2 x W / 2), taken as k_pool takes it;
+//   CONV_OUT    store nothing but the 1 x 1 output layer on them (Co = 32):
+//               ep.z = ep.bo[0] + sum_c ep.wo[c] Y[c] in channel order (as
+//               conv1_out) and ep.prob = 1 / (1 + exp(-z)) (as bce).
+// With CONV_POOL each wave's two 32-pixel blocks are vertically adjacent
+// rows, so a 2 x 2 window lies in one lane and its neighbour.
+template <int MT, int NTW, typename TX, typename TY, int EP>
 __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__ Wr, const TX* __restrict__ X,
                                                     const float* __restrict__ bias, int relu,
                                                     TY* __restrict__ Y, int Co, int Ci, int Bn, int H, int W,
-                                                    int BC) {
-  constexpr bool XH = sizeof(TX) == 2;
+                                                    int BC, ConvEpi ep) {
+  constexpr bool XH = sizeof(TX) == 2, YH = sizeof(TY) == 2;
+  static_assert(EP == CONV_STORE || (YH && NTW == 2), "fused epilogues take BF16 outputs and row pairs");
   constexpr int NT = 4096 / MT * NTW;   // pixels: NTW 32-pixel blocks per wave
   __shared__ __attribute__((aligned(16))) uint16_t Xs[HX];
   __shared__ __attribute__((aligned(16))) uint16_t Ws[MT][9 * HC + 8];
+  __shared__ float Osh[33];   // CONV_OUT: the output layer's weights and bias
   const int BR = NT / BC, TC = BC + 2, TR = BR + 2;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = MT == 64 ? wv >> 1 : 0, wn = MT == 64 ? wv & 1 : wv;
@@ -336,13 +373,21 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   const int co0 = blockIdx.y * MT;
   const long long HW = (long long)H * W;
   // this lane's pixels (one per 32-pixel block of the wave) and their place
-  // in the halo tile
+  // in the halo tile: with whole 32-pixel blocks per tile row the wave's two
+  // blocks are rows 2 (wn / nbr) and 2 (wn / nbr) + 1 of column block
+  // wn % nbr; otherwise blocks follow the tile in raster order
+  const int nbr = BC & 31 ? 0 : BC >> 5;
   int pr[NTW], pc[NTW];
 #pragma unroll
   for (int t = 0; t < NTW; ++t) {
-    const int pl = (wn * NTW + t) * 32 + (lane & 31);
-    pr[t] = pl / BC;
-    pc[t] = pl - pr[t] * BC;
+    if (NTW == 2 && nbr) {
+      pr[t] = 2 * (wn / nbr) + t;
+      pc[t] = (wn % nbr) * 32 + (lane & 31);
+    } else {
+      const int pl = (wn * NTW + t) * 32 + (lane & 31);
+      pr[t] = pl / BC;
+      pc[t] = pl - pr[t] * BC;
+    }
   }
   const int kg = (lane >> 5) * 8;
   f32x16 acc[NTW];
@@ -350,9 +395,10 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   for (int t = 0; t < NTW; ++t)
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
-  // Staging: a thread takes 8 channels of a tile position (8 loads, each
-  // coalesced over the positions; one 16-byte LDS store) and 16-byte groups
-  // of the reordered weights. Every load is issued unconditionally (positions
+  // Staging: a thread takes items of 8 channels of a tile position (BF16
+  // input: one 16-byte load; FP32 input: 8 loads, each coalesced over the
+  // positions) and stores each as 16 bytes to LDS, plus 16-byte groups of the
+  // reordered weights. Every load is issued unconditionally (positions
   // outside the image or channels past Ci read a valid address and are then
   // replaced by zero), so a thread's loads go out together and wait once:
   // guarded loads were issued one at a time, each waiting for the previous.
@@ -361,26 +407,32 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   const int np = TR * TC;
   constexpr int XI = MT == 64 ? 1 + NTW : 2 + NTW;     // input items per thread: 2 np <= 256 XI
   constexpr int WI = (MT * 18 + 255) / 256;
-  using XV = typename std::conditional<XH, uint32_t, float>::type;   // a loaded input value
-  XV xv[XI][8];
+  float xv[XI][8];   // FP32 input
+  uint4 xq[XI];      // BF16 input
   uint4 wv4[WI];
   uint32_t okx[XI], okw = 0;   // which loaded values are real (the rest become zero)
   // per item, fixed over the chunks: its channel-0 address (position
-  // clamped into the image, so always valid), whether it is a real tile
-  // position inside the image, and its channel group g (0 or 1)
-  const long long cs = (long long)Bn * HW;   // channel stride
+  // clamped into the image, so always valid), its LDS offset, and whether it
+  // is a real tile position inside the image. BF16 input: item e is
+  // position e / 2, channels 8 (e % 2) .. + 7 of the chunk (consecutive
+  // threads read consecutive 16 bytes); FP32: position e % np, channel group
+  // e / np.
+  const long long cs = XH ? (long long)Bn * HW * 16 : (long long)Bn * HW;   // chunk (BF16) or channel stride
   const TX* ib[XI];
-  int ig[XI];
+  int ig[XI], so[XI];
   uint32_t iin = 0;
 #pragma unroll
   for (int j = 0; j < XI; ++j) {
     const int e = tid + 256 * j;
-    const int g = e >= np ? 1 : 0, pos = e - g * np, r = pos / TC, cc = pos - r * TC;
+    const int g = XH ? (e & 1) : (e >= np ? 1 : 0), pos = XH ? e >> 1 : e - g * np;
+    const int r = pos / TC, cc = pos - r * TC;
     const int y = y0 + r - 1, x = x0 + cc - 1;
     iin |= (uint32_t)(e < 2 * np && y >= 0 && y < H && x >= 0 && x < W) << j;
     const int yc = min(max(y, 0), H - 1), xc = min(max(x, 0), W - 1);
-    ib[j] = X + (long long)b * HW + (long long)yc * W + xc;
+    const long long pix = (long long)b * HW + (long long)yc * W + xc;
+    ib[j] = XH ? X + pix * 16 + 8 * g : X + pix;
     ig[j] = 8 * g;
+    so[j] = pos * HC + 8 * g;
   }
   // weights: item j's row (clamped output channel) and 16-byte group
   const int wstep = Co * 9 * HC;
@@ -391,23 +443,28 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
     okw |= (uint32_t)(e < MT * 18 && co < Co) << j;
     wo[j] = min(co0 + min(m, MT - 1), Co - 1) * 9 * HC + 8 * q;
   }
-  const bool full = Ci % HC == 0;   // no chunk runs past the last channel
+  const bool full = Ci % HC == 0;   // no chunk runs past the last channel (always so for BF16 input)
   auto load = [&](int c0) {
 #pragma unroll
     for (int j = 0; j < XI; ++j) {
-      const int cb = c0 + ig[j];
-      if (full) {
-        const TX* src = ib[j] + (long long)cb * cs;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) xv[j][q] = src[(long long)q * cs];
+      if constexpr (XH) {
+        xq[j] = *reinterpret_cast<const uint4*>(ib[j] + (long long)(c0 / HC) * cs);
         okx[j] = (iin >> j & 1u) ? 0xffu : 0u;
       } else {
-        okx[j] = 0;
+        const int cb = c0 + ig[j];
+        if (full) {
+          const TX* src = ib[j] + (long long)cb * cs;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int c = cb + q;
-          xv[j][q] = ib[j][(long long)min(c, Ci - 1) * cs];
-          okx[j] |= (uint32_t)((iin >> j & 1u) && c < Ci) << q;
+          for (int q = 0; q < 8; ++q) xv[j][q] = src[(long long)q * cs];
+          okx[j] = (iin >> j & 1u) ? 0xffu : 0u;
+        } else {
+          okx[j] = 0;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int c = cb + q;
+            xv[j][q] = ib[j][(long long)min(c, Ci - 1) * cs];
+            okx[j] |= (uint32_t)((iin >> j & 1u) && c < Ci) << q;
+          }
         }
       }
     }
@@ -416,32 +473,42 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
     for (int j = 0; j < WI; ++j) wv4[j] = *reinterpret_cast<const uint4*>(wsrc + wo[j]);
   };
   load(0);
+  // CONV_OUT: the output layer's weights go out with the first chunk and
+  // reach LDS with it, instead of costing a memory round trip after the
+  // last MFMA
+  float oload = 0.f;
+  if (EP == CONV_OUT && tid < 32) oload = from_bf16(ep.wo[tid]);
+  else if (EP == CONV_OUT && tid == 32) oload = ep.bo[0];
   for (int c0 = 0; c0 < Ci; c0 += HC) {
     __syncthreads();
+    if (EP == CONV_OUT && c0 == 0 && tid < 33) Osh[tid] = oload;
     // the loaded values are taken here whether or not they are used, so the
     // compiler keeps every load unconditional (and in flight together)
 #pragma unroll
-    for (int j = 0; j < XI; ++j)
-      asm volatile("" : "+v"(xv[j][0]), "+v"(xv[j][1]), "+v"(xv[j][2]), "+v"(xv[j][3]), "+v"(xv[j][4]),
-                        "+v"(xv[j][5]), "+v"(xv[j][6]), "+v"(xv[j][7]));
+    for (int j = 0; j < XI; ++j) {
+      if constexpr (XH)
+        asm volatile("" : "+v"(xq[j].x), "+v"(xq[j].y), "+v"(xq[j].z), "+v"(xq[j].w));
+      else
+        asm volatile("" : "+v"(xv[j][0]), "+v"(xv[j][1]), "+v"(xv[j][2]), "+v"(xv[j][3]), "+v"(xv[j][4]),
+                          "+v"(xv[j][5]), "+v"(xv[j][6]), "+v"(xv[j][7]));
+    }
 #pragma unroll
     for (int j = 0; j < WI; ++j) asm volatile("" : "+v"(wv4[j].x), "+v"(wv4[j].y), "+v"(wv4[j].z), "+v"(wv4[j].w));
 #pragma unroll
     for (int j = 0; j < XI; ++j) {
       const int e = tid + 256 * j;
       if (e < 2 * np) {
-        const int g = e >= np ? 1 : 0, pos = e - g * np;
-        uint16_t v[8];
+        uint4 s;
+        if constexpr (XH) {
+          s = okx[j] ? xq[j] : make_uint4(0, 0, 0, 0);
+        } else {
+          uint16_t v[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          uint16_t h;
-          if constexpr (XH) h = (uint16_t)xv[j][q];
-          else h = to_bf16(xv[j][q]);
-          v[q] = (okx[j] >> q & 1u) ? h : (uint16_t)0;
+          for (int q = 0; q < 8; ++q) v[q] = (okx[j] >> q & 1u) ? to_bf16(xv[j][q]) : (uint16_t)0;
+          s = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
+                         v[6] | ((uint32_t)v[7] << 16));
         }
-        *reinterpret_cast<uint4*>(&Xs[pos * HC + 8 * g]) =
-            make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
-                       v[6] | ((uint32_t)v[7] << 16));
+        *reinterpret_cast<uint4*>(&Xs[so[j]]) = s;
       }
     }
 #pragma unroll
@@ -472,23 +539,109 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   float bv[16];   // biases loaded together (clamped index), used where co < Co
 #pragma unroll
   for (int k = 0; k < 16; ++k) bv[k] = bias[min(co0 + wm * 32 + 8 * (k >> 2) + 4 * (lane >> 5) + (k & 3), Co - 1)];
+  if constexpr (!YH) {
 #pragma unroll
-  for (int t = 0; t < NTW; ++t) {
-    const int y = y0 + pr[t], x = x0 + pc[t];
-    if (y >= H || x >= W) continue;
-    TY* yp = Y + (long long)b * HW + (long long)y * W + x;
+    for (int t = 0; t < NTW; ++t) {
+      const int y = y0 + pr[t], x = x0 + pc[t];
+      if (y >= H || x >= W) continue;
+      TY* yp = Y + (long long)b * HW + (long long)y * W + x;
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+      for (int g = 0; g < 4; ++g)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int co = co0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
-        if (co < Co) {
-          float v = acc[t][4 * g + r] + bv[4 * g + r];
-          if (relu) v = fmaxf(v, 0.f);
-          if constexpr (sizeof(TY) == 2) yp[(long long)co * Bn * HW] = to_bf16(v);
-          else yp[(long long)co * Bn * HW] = v;
+        for (int r = 0; r < 4; ++r) {
+          const int co = co0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
+          if (co < Co) {
+            float v = acc[t][4 * g + r] + bv[4 * g + r];
+            if (relu) v = fmaxf(v, 0.f);
+            yp[(long long)co * Bn * HW] = v;
+          }
         }
+    }
+  } else {
+    // BF16 values, two per word: word 2 g + (r >> 1) of block t holds
+    // channels co0 + wm 32 + 8 g + 4 (lane >> 5) + r
+    uint32_t hv[NTW][8];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        float v0 = acc[t][2 * k] + bv[2 * k], v1 = acc[t][2 * k + 1] + bv[2 * k + 1];
+        if (relu) {
+          v0 = fmaxf(v0, 0.f);
+          v1 = fmaxf(v1, 0.f);
+        }
+        hv[t][k] = to_bf16(v0) | ((uint32_t)to_bf16(v1) << 16);
       }
+    const long long npix = (long long)Bn * HW;
+    const int cw = co0 + wm * 32 + 8 * (lane >> 5);   // first channel of this lane's 8 in block 0
+    if constexpr (EP != CONV_OUT) {
+      uint4 q[NTW][2];
+#pragma unroll
+      for (int t = 0; t < NTW; ++t)
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg)
+          q[t][gg] = gather8(hv[t][4 * gg], hv[t][4 * gg + 1], hv[t][4 * gg + 2], hv[t][4 * gg + 3]);
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        const int y = y0 + pr[t], x = x0 + pc[t];
+        if (y >= H || x >= W) continue;
+        const long long pix = (long long)b * HW + (long long)y * W + x;
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg)
+          if (cw + 16 * gg < Co) *reinterpret_cast<uint4*>(Y + cblk(cw + 16 * gg, pix, npix)) = q[t][gg];
+      }
+    }
+    if constexpr (EP == CONV_POOL) {
+      // window (y, x), (y, x + 1), (y + 1, x), (y + 1, x + 1) at even y, x:
+      // this lane's block 0 and 1 values and its neighbour's
+      uint32_t pw[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t a = hv[0][k], c = hv[1][k], bn = from_pair_lane(a), dn = from_pair_lane(c);
+        pw[k] = max4_bf16((uint16_t)a, (uint16_t)bn, (uint16_t)c, (uint16_t)dn) |
+                ((uint32_t)max4_bf16((uint16_t)(a >> 16), (uint16_t)(bn >> 16), (uint16_t)(c >> 16),
+                                     (uint16_t)(dn >> 16))
+                 << 16);
+      }
+      uint4 pq[2];
+#pragma unroll
+      for (int gg = 0; gg < 2; ++gg) pq[gg] = gather8(pw[4 * gg], pw[4 * gg + 1], pw[4 * gg + 2], pw[4 * gg + 3]);
+      const int y = y0 + pr[0], x = x0 + pc[0];
+      if (!(x & 1) && y < H && x < W) {
+        const int h2 = H / 2, w2 = W / 2;
+        const long long pix = ((long long)b * h2 + y / 2) * w2 + x / 2, np2 = (long long)Bn * h2 * w2;
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg)
+          if (cw + 16 * gg < Co) *reinterpret_cast<uint4*>(ep.pool + cblk(cw + 16 * gg, pix, np2)) = pq[gg];
+      }
+    }
+    if constexpr (EP == CONV_OUT) {
+      // channels 8 g + r here (lanes 0 .. 31) and 8 g + 4 + r in lane + 32
+      float wf[32];
+#pragma unroll
+      for (int c = 0; c < 32; ++c) wf[c] = Osh[c];
+      const float b0 = Osh[32];
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        uint32_t hi[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) hi[k] = from_upper_half(hv[t][k]);
+        const int y = y0 + pr[t], x = x0 + pc[t];
+        if ((lane >> 5) || y >= H || x >= W) continue;
+        float s = 0.f;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) s = fmaf(wf[8 * g + r], from_bf16((uint16_t)(hv[t][2 * g + (r >> 1)] >> (16 * (r & 1)))), s);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) s = fmaf(wf[8 * g + 4 + r], from_bf16((uint16_t)(hi[2 * g + (r >> 1)] >> (16 * (r & 1)))), s);
+        }
+        const float z = s + b0;
+        const long long pix = (long long)b * HW + (long long)y * W + x;
+        ep.z[pix] = z;
+        ep.prob[pix] = 1.f / (1.f + expf(-z));
+      }
+    }
   }
 }
 
@@ -506,24 +659,14 @@ __global__ void k_conv1_out(const uint16_t* __restrict__ Wb, const float* __rest
   Y[i] = s + bias[0];
 }
 
-// the same with BF16 input activations
-__global__ void k_conv1_out_h(const uint16_t* __restrict__ Wb, const uint16_t* __restrict__ X,
-                              const float* __restrict__ bias, float* __restrict__ Y, int C, long long N) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  float s = 0.f;
-#pragma unroll 8
-  for (int c = 0; c < C; ++c) s = fmaf(from_bf16(Wb[c]), from_bf16(X[(long long)c * N + i]), s);
-  Y[i] = s + bias[0];
-}
-
 // Direct 3 x 3 convolution of inputs with at most two channels (the summary
 // U-Net's first layer, input S and T) to at most 32 output channels: the
 // depth of the product is k = 9 c + 3 ky + kx (the weights' own order),
 // 18 values padded to two MFMA steps of 16, instead of one 16-channel chunk
 // per (ky, kx) with 14 channels of zeros. A workgroup computes 32 output
 // channels x 256 pixels (4 rows x 64 columns when W >= 64); the halo tile
-// holds both channels of a position as one BF16 pair.
+// holds both channels of a position as one BF16 pair. X is planar; a BF16 Y
+// is stored in channel blocks of 16, an FP32 Y planar.
 constexpr int C2_TX = 6 * 66;   // largest halo tile (positions)
 template <typename TX, typename TY>
 __global__ __launch_bounds__(256) void k_conv3_c2(const uint16_t* __restrict__ Wb, const TX* __restrict__ X,
@@ -538,26 +681,43 @@ __global__ __launch_bounds__(256) void k_conv3_c2(const uint16_t* __restrict__ W
   const int blk = blockIdx.x, b = blk / (bx * by), rem = blk - b * bx * by;
   const int y0 = (rem / bx) * BR, x0 = (rem % bx) * BC;
   const long long HW = (long long)H * W;
-  // halo tile: both channels of each position (zero outside the image)
-  for (int e = tid; e < np; e += 256) {
-    const int r = e / TC, cc = e - r * TC, y = y0 + r - 1, x = x0 + cc - 1;
-    uint16_t v0 = 0, v1 = 0;
-    if (y >= 0 && y < H && x >= 0 && x < W) {
-      const TX* src = X + (long long)b * HW + (long long)y * W + x;
-      if constexpr (sizeof(TX) == 2) {
-        v0 = src[0];
-        if (Ci > 1) v1 = src[(long long)Bn * HW];
-      } else {
-        v0 = to_bf16(src[0]);
-        if (Ci > 1) v1 = to_bf16(src[(long long)Bn * HW]);
-      }
-    }
-    Xs[e] = v0 | ((uint32_t)v1 << 16);
+  // halo tile: both channels of each position (zero outside the image),
+  // and the weights [co][k], k = 9 c + tap (zero past 9 Ci). Every load is
+  // issued, from a clamped address, before the first store.
+  constexpr int NI = (C2_TX + 255) / 256;
+  const long long cstr = Ci > 1 ? (long long)Bn * HW : 0;
+  TX v0[NI], v1[NI];
+  uint32_t in = 0;
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int e = tid + 256 * i, r = e / TC, cc = e - r * TC, y = y0 + r - 1, x = x0 + cc - 1;
+    in |= (uint32_t)(e < np && y >= 0 && y < H && x >= 0 && x < W) << i;
+    const TX* src = X + (long long)b * HW + (long long)min(max(y, 0), H - 1) * W + min(max(x, 0), W - 1);
+    v0[i] = src[0];
+    v1[i] = src[cstr];
   }
-  // weights [co][k], k = 9 c + tap, zero past 9 Ci
-  for (int e = tid; e < 32 * 32; e += 256) {
-    const int co = e >> 5, k = e & 31;
-    Ws[co][k] = (co < Co && k < 9 * Ci) ? Wb[(long long)co * 9 * Ci + k] : (uint16_t)0;
+  uint16_t wl[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = tid + 256 * i, co = e >> 5, k = e & 31;
+    wl[i] = Wb[(long long)min(co, Co - 1) * 9 * Ci + min(k, 9 * Ci - 1)];
+  }
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int e = tid + 256 * i;
+    if (e < np) {
+      uint16_t h0 = 0, h1 = 0;
+      if (in >> i & 1u) {
+        h0 = ld_bf16(v0, i);
+        h1 = Ci > 1 ? ld_bf16(v1, i) : (uint16_t)0;
+      }
+      Xs[e] = h0 | ((uint32_t)h1 << 16);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = tid + 256 * i, co = e >> 5, k = e & 31;
+    Ws[co][k] = (co < Co && k < 9 * Ci) ? wl[i] : (uint16_t)0;
   }
   __syncthreads();
   const int kg = (lane >> 5) * 8;
@@ -588,24 +748,138 @@ __global__ __launch_bounds__(256) void k_conv3_c2(const uint16_t* __restrict__ W
       acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[t], 0, 0, 0);
     }
   }
+  float v[2][16];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      v[t][k] = acc[t][k] + bias[min(8 * (k >> 2) + 4 * (lane >> 5) + (k & 3), Co - 1)];
+      if (relu) v[t][k] = fmaxf(v[t][k], 0.f);
+    }
+  if constexpr (sizeof(TY) == 2) {
+    // channel blocks of 16 (Co a multiple of 16), 16 bytes per lane and store
+    uint4 q[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int gg = 0; gg < 2; ++gg) {
+        uint32_t w4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          w4[k] = to_bf16(v[t][8 * gg + 2 * k]) | ((uint32_t)to_bf16(v[t][8 * gg + 2 * k + 1]) << 16);
+        q[t][gg] = gather8(w4[0], w4[1], w4[2], w4[3]);
+      }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int pl = (wv * 2 + t) * 32 + (lane & 31), pr = pl / BC, pc = pl - pr * BC;
+      const int y = y0 + pr, x = x0 + pc;
+      if (y >= H || x >= W) continue;
+      const long long pix = (long long)b * HW + (long long)y * W + x;
+#pragma unroll
+      for (int gg = 0; gg < 2; ++gg) {
+        const int c = 16 * gg + 8 * (lane >> 5);
+        if (c < Co) *reinterpret_cast<uint4*>(Y + cblk(c, pix, (long long)Bn * HW)) = q[t][gg];
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int pl = (wv * 2 + t) * 32 + (lane & 31), pr = pl / BC, pc = pl - pr * BC;
     const int y = y0 + pr, x = x0 + pc;
     if (y >= H || x >= W) continue;
-    TY* yp = Y + (long long)b * HW + (long long)y * W + x;
+    const long long pix = (long long)b * HW + (long long)y * W + x;
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < 4; ++g) {
+      const int co = 8 * g + 4 * (lane >> 5);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int co = 8 * g + 4 * (lane >> 5) + r;
-        if (co < Co) {
-          float v = acc[t][4 * g + r] + bias[co];
-          if (relu) v = fmaxf(v, 0.f);
-          if constexpr (sizeof(TY) == 2) yp[(long long)co * Bn * HW] = to_bf16(v);
-          else yp[(long long)co * Bn * HW] = v;
-        }
+      for (int r = 0; r < 4; ++r)
+        if (co + r < Co) Y[pix + (long long)(co + r) * Bn * HW] = v[t][4 * g + r];
+    }
+  }
+}
+
+// Transposed 2 x 2 convolution, stride 2, on BF16 activations in channel
+// blocks of 16: Y[co][b][2 y + a][2 x + e] = bias[co] + sum_c
+// W[4 co + 2 a + e][c] X[c][b][y][x], rounded to BF16. Two waves share a
+// block of 32 input pixels, each computing half of the 4 Co rows of the
+// product, so X is read from memory once and each output pixel written once:
+// row tile i (32 rows) is tap a 2 + e = i / (Co / 32), output channels
+// 32 (i % (Co / 32)) .. + 31, from the weights permuted into that order in
+// LDS. The MFMA B operand, 8 channels of one pixel, is one 16-byte load of
+// the blocked input. The depth steps run in channel order, as in k_gemm_v's
+// GV_UP product, so the sums are the same.
+template <int MI, int KS>   // MI = 4 Co / 32 row tiles, KS = Ci / 16 depth steps
+__global__ __launch_bounds__(256) void k_up2_h(const uint16_t* __restrict__ Wb, const uint16_t* __restrict__ X,
+                                               const float* __restrict__ bias, uint16_t* __restrict__ Y, int Bn,
+                                               int h, int w) {
+  constexpr int M = 32 * MI, K = 16 * KS, Co = M / 4, TPC = Co / 32, MH = MI / 2;   // row tiles per tap, per wave
+  static_assert(Co % 32 == 0 && MI % 2 == 0, "whole 32-channel tiles per tap, split over two waves");
+  __shared__ __attribute__((aligned(16))) uint16_t Ws[M][K + 8];
+  __shared__ float Bs[Co];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, i0 = (wv & 1) * MH;
+  // weights and biases: every load issued before the first store
+  constexpr int NWL = M * (K / 8) / 256;
+  static_assert(M * (K / 8) % 256 == 0 && Co <= 256, "whole staging rounds");
+  uint4 wl[NWL];
+#pragma unroll
+  for (int j = 0; j < NWL; ++j) {
+    const int e = tid + 256 * j, m = e / (K / 8), q = e - m * (K / 8), tap = m / Co, co = m - tap * Co;
+    wl[j] = *reinterpret_cast<const uint4*>(Wb + (long long)(4 * co + tap) * K + 8 * q);
+  }
+  const float bl = bias[min(tid, Co - 1)];
+#pragma unroll
+  for (int j = 0; j < NWL; ++j) {
+    const int e = tid + 256 * j, m = e / (K / 8), q = e - m * (K / 8);
+    *reinterpret_cast<uint4*>(&Ws[m][8 * q]) = wl[j];
+  }
+  if (tid < Co) Bs[tid] = bl;
+  __syncthreads();
+  const long long hw = (long long)h * w, npix = (long long)Bn * hw;
+  const long long nblk = (npix + 31) / 32;
+  for (long long blk = (long long)blockIdx.x * 2 + (wv >> 1); blk < nblk; blk += (long long)gridDim.x * 2) {
+    // the weight reads below are the same for every block: kept inside the
+    // loop (not hoisted into registers for all blocks)
+    asm volatile("" ::: "memory");
+    const long long p = blk * 32 + (lane & 31), pl = p < npix ? p : npix - 1;
+    uint4 bq[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      bq[s] = *reinterpret_cast<const uint4*>(X + ((long long)s * npix + pl) * 16 + 8 * (lane >> 5));
+    f32x16 acc[MH];
+#pragma unroll
+    for (int i = 0; i < MH; ++i)
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc[i][k] = 0.f;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const bf16x8 bb = __builtin_bit_cast(bf16x8, bq[s]);
+#pragma unroll
+      for (int i = 0; i < MH; ++i) {
+        const bf16x8 a = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const uint4*>(&Ws[32 * (i0 + i) + (lane & 31)][16 * s + 8 * (lane >> 5)]));
+        acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[i], 0, 0, 0);
       }
+    }
+    const long long b = pl / hw;
+    const int yx = (int)(pl - b * hw), y = yx / w, x = yx - y * w;
+#pragma unroll
+    for (int i = 0; i < MH; ++i) {
+      const int tap = (i0 + i) / TPC, a = tap >> 1, e = tap & 1;
+      const long long op = (b * 2 * h + 2 * y + a) * (2LL * w) + 2 * x + e;   // output pixel
+      const int cb = 32 * ((i0 + i) % TPC);
+#pragma unroll
+      for (int gg = 0; gg < 2; ++gg) {
+        uint32_t w4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int c = cb + 8 * (2 * gg + (k >> 1)) + 4 * (lane >> 5) + 2 * (k & 1);   // channels c, c + 1
+          w4[k] = to_bf16(acc[i][8 * gg + 2 * k] + Bs[c]) | ((uint32_t)to_bf16(acc[i][8 * gg + 2 * k + 1] + Bs[c + 1]) << 16);
+        }
+        const uint4 q = gather8(w4[0], w4[1], w4[2], w4[3]);
+        if (p < npix) *reinterpret_cast<uint4*>(Y + cblk(cb + 16 * gg + 8 * (lane >> 5), op, 4 * npix)) = q;
+      }
+    }
   }
 }
 
@@ -779,22 +1053,6 @@ __global__ void k_pool(const float* __restrict__ X, float* __restrict__ Y, uint8
   if (s[W + 1] > best) { best = s[W + 1]; a = 3; }
   Y[i] = best;
   arg[i] = (uint8_t)a;
-}
-
-// the same on BF16 activations, without the argmax (inference): the maximum
-// of BF16-rounded values is the BF16 rounding of the maximum
-__global__ void k_pool_h(const uint16_t* __restrict__ X, uint16_t* __restrict__ Y, int CB, int H, int W) {
-  const int h = H / 2, w = W / 2;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)CB * h * w) return;
-  const long long cb = i / (h * w);
-  const int yx = (int)(i % (h * w)), y = yx / w, x = yx % w;
-  const uint16_t* s = X + cb * H * W + (2 * y) * W + 2 * x;
-  uint16_t best = s[0];
-  if (from_bf16(s[1]) > from_bf16(best)) best = s[1];
-  if (from_bf16(s[W]) > from_bf16(best)) best = s[W];
-  if (from_bf16(s[W + 1]) > from_bf16(best)) best = s[W + 1];
-  Y[i] = best;
 }
 
 // dX (+)= dY routed to the argmax position
@@ -1029,48 +1287,81 @@ void conv3_reorder(const uint16_t* Wb, uint16_t* Wr, int Co, int Ci, hipStream_t
 size_t conv3_reordered_size(int Co, int Ci) { return (size_t)((Ci + HC - 1) / HC) * Co * 9 * HC; }
 
 namespace {
-// shape check and launch of the halo-tile convolution; false when the shape
-// does not fit it
+template <int MT, typename TX, typename TY>
+void launch_halo(dim3 grid, int mode, const uint16_t* Wr, const TX* X, const float* bias, bool relu, TY* Y, int Co,
+                 int Ci, int Bn, int H, int W, int BC, const ConvEpi& ep, hipStream_t st) {
+  if constexpr (sizeof(TY) == 2) {
+    if (mode == CONV_POOL) {
+      hipLaunchKernelGGL((k_conv3_halo<MT, 2, TX, TY, CONV_POOL>), grid, dim3(256), 0, st, Wr, X, bias, (int)relu, Y,
+                         Co, Ci, Bn, H, W, BC, ep);
+      return;
+    }
+    if constexpr (MT == 32) {
+      if (mode == CONV_OUT) {
+        hipLaunchKernelGGL((k_conv3_halo<MT, 2, TX, TY, CONV_OUT>), grid, dim3(256), 0, st, Wr, X, bias, (int)relu,
+                           Y, Co, Ci, Bn, H, W, BC, ep);
+        return;
+      }
+    }
+  }
+  hipLaunchKernelGGL((k_conv3_halo<MT, 2, TX, TY, CONV_STORE>), grid, dim3(256), 0, st, Wr, X, bias, (int)relu, Y, Co,
+                     Ci, Bn, H, W, BC, ep);
+}
+
+// shape check and launch of the halo-tile convolution; false (nothing
+// launched) when the shape or the epilogue does not fit it
 template <typename TX, typename TY>
 bool conv3_halo(const uint16_t* Wb, const uint16_t* Wr, const TX* X, TY* Y, int Co, int Ci, int Bn, int H, int W,
-                const float* bias, bool relu, hipStream_t st) {
+                const float* bias, bool relu, int mode, const ConvEpi& ep, hipStream_t st) {
+  constexpr bool XH = sizeof(TX) == 2, YH = sizeof(TY) == 2;
   if (!(Wr && W % 8 == 0 && bias && (long long)Bn * H * W <= 0x7fffffffLL && ((uintptr_t)Wr & 15) == 0))
     return false;
+  // channel blocks of 16 (16-byte aligned) for BF16 activations; fused
+  // epilogues only on them
+  if ((XH && (Ci % 16 || ((uintptr_t)X & 15))) || (YH && (Co % 16 || ((uintptr_t)Y & 15))) ||
+      (!YH && mode != CONV_STORE))
+    return false;
   if (Ci <= 2 && Co <= 32) {   // first layer: the depth is 9 Ci, two MFMA steps
-    const int BC = W < 64 ? W : 64;
-    if (256 % BC || (256 / BC + 2) * (BC + 2) > C2_TX) return false;
-    const int BR = 256 / BC;
-    const long long blocks = (long long)Bn * ((H + BR - 1) / BR) * ((W + BC - 1) / BC);
-    hipLaunchKernelGGL((k_conv3_c2<TX, TY>), dim3((unsigned)blocks), dim3(256), 0, st, Wb, X, bias, (int)relu, Y, Co,
-                       Ci, Bn, H, W, BC);
-    return true;
+    if constexpr (XH) {
+      return false;   // (a BF16 input has channel blocks of 16)
+    } else {
+      const int BC = W < 64 ? W : 64;
+      if (mode != CONV_STORE || 256 % BC || (256 / BC + 2) * (BC + 2) > C2_TX) return false;
+      const int BR = 256 / BC;
+      const long long blocks = (long long)Bn * ((H + BR - 1) / BR) * ((W + BC - 1) / BC);
+      hipLaunchKernelGGL((k_conv3_c2<TX, TY>), dim3((unsigned)blocks), dim3(256), 0, st, Wb, X, bias, (int)relu, Y,
+                         Co, Ci, Bn, H, W, BC);
+      return true;
+    }
   }
   const int MT = Co <= 32 ? 32 : 64, NTW = 2, NT = 4096 / MT * NTW, BC = W < 64 ? W : 64;
   const int np = (NT / BC + 2) * (BC + 2);
   if (!(NT % BC == 0 && np * HC <= HX && 2 * np <= 256 * (MT == 64 ? 1 + NTW : 2 + NTW))) return false;
   const int BR = NT / BC;
+  if (mode == CONV_POOL && (BC % 32 || BR % 2 || H % 2 || W % 2 || !ep.pool || ((uintptr_t)ep.pool & 15)))
+    return false;
+  if (mode == CONV_OUT && (Co != 32 || !ep.wo || !ep.bo || !ep.z || !ep.prob)) return false;
   const long long blocks = (long long)Bn * ((H + BR - 1) / BR) * ((W + BC - 1) / BC);
+  const dim3 grid((unsigned)blocks, (Co + MT - 1) / MT);
   if (MT == 32)
-    hipLaunchKernelGGL((k_conv3_halo<32, 2, TX, TY>), dim3((unsigned)blocks, (Co + 31) / 32), dim3(256), 0, st, Wr,
-                       X, bias, (int)relu, Y, Co, Ci, Bn, H, W, BC);
+    launch_halo<32>(grid, mode, Wr, X, bias, relu, Y, Co, Ci, Bn, H, W, BC, ep, st);
   else
-    hipLaunchKernelGGL((k_conv3_halo<64, 2, TX, TY>), dim3((unsigned)blocks, (Co + 63) / 64), dim3(256), 0, st, Wr,
-                       X, bias, (int)relu, Y, Co, Ci, Bn, H, W, BC);
+    launch_halo<64>(grid, mode, Wr, X, bias, relu, Y, Co, Ci, Bn, H, W, BC, ep, st);
   return true;
 }
 }  // namespace
 
-bool conv3_halo_h(const uint16_t* Wb, const uint16_t* Wr, const void* X, bool x_bf16, uint16_t* Y, int Co, int Ci,
-                  int Bn, int H, int W, const float* bias, bool relu, hipStream_t st) {
-  return x_bf16 ? conv3_halo(Wb, Wr, static_cast<const uint16_t*>(X), Y, Co, Ci, Bn, H, W, bias, relu, st)
-                : conv3_halo(Wb, Wr, static_cast<const float*>(X), Y, Co, Ci, Bn, H, W, bias, relu, st);
+bool conv3_h(const uint16_t* Wb, const uint16_t* Wr, const void* X, bool x_bf16, uint16_t* Y, int Co, int Ci, int Bn,
+             int H, int W, const float* bias, bool relu, int mode, const ConvEpi& ep, hipStream_t st) {
+  return x_bf16 ? conv3_halo(Wb, Wr, static_cast<const uint16_t*>(X), Y, Co, Ci, Bn, H, W, bias, relu, mode, ep, st)
+                : conv3_halo(Wb, Wr, static_cast<const float*>(X), Y, Co, Ci, Bn, H, W, bias, relu, mode, ep, st);
 }
 
 bool conv3_implicit(const uint16_t* Wb, const uint16_t* Wr, const float* X, float* Y, int Co, int Ci, int Bn,
                     int H, int W, const float* bias, bool relu, hipStream_t st) {
   // direct convolution over halo tiles where a block of whole 8-aligned
   // columns fits the tile
-  if (conv3_halo(Wb, Wr, X, Y, Co, Ci, Bn, H, W, bias, relu, st)) return true;
+  if (conv3_halo(Wb, Wr, X, Y, Co, Ci, Bn, H, W, bias, relu, CONV_STORE, ConvEpi{}, st)) return true;
   const int K = Ci * 9;
   const long long N = (long long)Bn * H * W;
   if (W % 8 || K % 8 || ((uintptr_t)Wb & 15) || N > 0x7fffffffLL) return false;
@@ -1099,21 +1390,25 @@ bool conv1_out(const uint16_t* Wb, const float* X, const float* bias, float* Y, 
   L1(k_conv1_out, N, Wb, X, bias, Y, C, N);
   return true;
 }
-void conv1_out_h(const uint16_t* Wb, const uint16_t* X, const float* bias, float* Y, int C, long long N,
-                 hipStream_t st) {
-  L1(k_conv1_out_h, N, Wb, X, bias, Y, C, N);
+bool up2_h(const uint16_t* Wb, const uint16_t* X, const float* bias, uint16_t* Y, int Co, int Ci, int Bn, int h, int w,
+           hipStream_t st) {
+  const long long npix = (long long)Bn * h * w;
+  if (npix < 1 || 4 * npix > 0x7fffffffLL || ((uintptr_t)Wb & 15) || ((uintptr_t)X & 15) || ((uintptr_t)Y & 7))
+    return false;
+  const long long nblk = (npix + 31) / 32;
+  const dim3 grid((unsigned)std::min<long long>((nblk + 1) / 2, 1024));
+#define UP2(MI, KS)                                                                                     \
+  if (4 * Co == 32 * MI && Ci == 16 * KS) {                                                              \
+    hipLaunchKernelGGL((k_up2_h<MI, KS>), grid, dim3(256), 0, st, Wb, X, bias, Y, Bn, h, w);            \
+    return true;                                                                                         \
+  }
+  UP2(4, 4)
+  UP2(4, 8)
+  UP2(8, 4)
+  UP2(8, 8)
+#undef UP2
+  return false;
 }
-bool up_direct_h(const uint16_t* Wb, const uint16_t* X, const float* bias, uint16_t* Y, int Co, int Ci, int Bn, int h,
-                 int w, hipStream_t st) {
-  const long long N = (long long)Bn * h * w;
-  if (N % 8 || Ci % 8 || N > 0x7fffffffLL || ((uintptr_t)Wb & 15) || ((uintptr_t)X & 15)) return false;
-  const Im2col ic{nullptr, Bn, h, w};
-  const int M = 4 * Co;
-  hipLaunchKernelGGL((k_gemm_v<64, GV_UP_H>), dim3((unsigned)((N + 63) / 64), (M + 63) / 64), dim3(256), 0, st, Wb,
-                     (long long)Ci, X, N, ic, reinterpret_cast<float*>(Y), 0LL, M, (int)N, Ci, 0, bias, 0);
-  return true;
-}
-
 void im2col3(const float* X, uint16_t* col, int C, int Bn, int H, int W, hipStream_t st) {
   if (W % 8 == 0 && ((uintptr_t)col & 15) == 0)
     L1(k_im2col3_v, (long long)C * 9 * Bn * H * W / 8, X, col, C, Bn, H, W);
@@ -1143,9 +1438,6 @@ void bias_grad(const float* dY, float* db, int C, long long N, hipStream_t st) {
 }
 void pool(const float* X, float* Y, uint8_t* arg, int CB, int H, int W, hipStream_t st) {
   L1(k_pool, (long long)CB * (H / 2) * (W / 2), X, Y, arg, CB, H, W);
-}
-void pool_h(const uint16_t* X, uint16_t* Y, int CB, int H, int W, hipStream_t st) {
-  L1(k_pool_h, (long long)CB * (H / 2) * (W / 2), X, Y, CB, H, W);
 }
 void pool_bwd(const float* dY, const uint8_t* arg, float* dX, int CB, int H, int W, bool acc, hipStream_t st) {
   L1(k_pool_bwd, (long long)CB * H * W, dY, arg, dX, CB, H, W, (int)acc);

@@ -373,19 +373,23 @@ hipError_t forward(seg_nn* n, const uint16_t* frames, const float* stin, int Bn,
   return e;
 }
 
-// Forward pass for inference: the U-Net's activations are kept as BF16
-// (half the bytes of every layer's reads and writes). Every consumer of an
-// activation takes it rounded to BF16 (the convolutions' staging, the
-// transposed convolutions, the output layer; a maximum commutes with the
-// rounding), so the logits are the same as forward()'s. Returns false, with
-// nothing left that forward() does not redo, when a layer's shape does not
-// fit the BF16 kernels; *err gets launch errors.
-bool forward_infer(seg_nn* n, const uint16_t* frames, const float* stin, int Bn, hipStream_t st, hipError_t* err) {
+// Forward pass for inference: the U-Net's activations are kept as BF16 in
+// channel blocks of 16 (half the bytes of every layer's reads and writes, 16
+// bytes per load). Every consumer of an activation takes it rounded to BF16
+// (the convolutions' staging, the transposed convolutions, the output layer;
+// a maximum commutes with the rounding) and every product sums in the same
+// order, so the logits are the same as forward()'s. The 2 x 2 poolings and
+// the output layer with its sigmoid run in the epilogues of the convolutions
+// before them; the probabilities go to `prob`. Returns false, with nothing
+// left that forward() does not redo, when a layer's shape does not fit the
+// BF16 kernels (H not a multiple of 4 or W of 64); *err gets launch errors.
+bool forward_infer(seg_nn* n, const uint16_t* frames, const float* stin, int Bn, float* prob, hipStream_t st,
+                   hipError_t* err) {
   const Plan& p = n->plan;
   const int H = p.H, W = p.W;
   const long long HW = (long long)H * W;
   const long long N = Bn * HW, N2 = N / 4;
-  if (H % 4 || W % 32) return false;
+  if (H % 4 || W % 64) return false;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) {
     if (x != hipSuccess && e == hipSuccess) e = x;
@@ -412,28 +416,36 @@ bool forward_infer(seg_nn* n, const uint16_t* frames, const float* stin, int Bn,
     unet_in = a3;
   }
   auto h = [&](const Buf& b) { return at<uint16_t>(n, b); };
-  auto conv = [&](int id, const void* X, bool x_bf16, uint16_t* Y, int hh, int ww) {
-    return conv3_halo_h(wbf(n, id), at<uint16_t>(n, p.wr) + p.wr_off[id], X, x_bf16, Y, n->P[id].rows,
-                        n->P[id].cols / 9, Bn, hh, ww, bias(n, id), true, st);
+  auto conv = [&](int id, const void* X, bool x_bf16, uint16_t* Y, int hh, int ww, int mode, const ConvEpi& ep) {
+    return conv3_h(wbf(n, id), at<uint16_t>(n, p.wr) + p.wr_off[id], X, x_bf16, Y, n->P[id].rows, n->P[id].cols / 9,
+                   Bn, hh, ww, bias(n, id), true, mode, ep, st);
   };
-  // activations in the FP32 buffers' memory, as BF16
+  // activations in the FP32 buffers' memory, as BF16 in channel blocks
   uint16_t *e1a = h(p.e1a), *cat1 = h(p.cat1), *s1 = cat1 + 32 * N, *p1 = h(p.p1);
   uint16_t *e2a = h(p.e2a), *cat2 = h(p.cat2), *s2 = cat2 + 64 * N2, *p2 = h(p.p2);
-  uint16_t *e3a = h(p.e3a), *b3 = h(p.b3), *d2a = h(p.d2a), *d2 = h(p.d2), *d1a = h(p.d1a), *d1 = h(p.d1);
-  bool ok = conv(E1A, unet_in, false, e1a, H, W) && conv(E1B, e1a, true, s1, H, W);
-  if (ok) {
-    pool_h(s1, p1, 32 * Bn, H, W, st);
-    ok = conv(E2A, p1, true, e2a, H / 2, W / 2) && conv(E2B, e2a, true, s2, H / 2, W / 2);
-  }
-  if (ok) {
-    pool_h(s2, p2, 64 * Bn, H / 2, W / 2, st);
-    ok = conv(E3A, p2, true, e3a, H / 4, W / 4) && conv(E3B, e3a, true, b3, H / 4, W / 4) &&
-         up_direct_h(wbf(n, U2), b3, bias(n, U2), cat2, 64, 128, Bn, H / 4, W / 4, st) &&
-         conv(D2A, cat2, true, d2a, H / 2, W / 2) && conv(D2B, d2a, true, d2, H / 2, W / 2) &&
-         up_direct_h(wbf(n, U1), d2, bias(n, U1), cat1, 32, 64, Bn, H / 2, W / 2, st) &&
-         conv(D1A, cat1, true, d1a, H, W) && conv(D1B, d1a, true, d1, H, W);
-  }
-  if (ok) conv1_out_h(wbf(n, FO), d1, bias(n, FO), at<float>(n, p.logit), n->P[FO].cols, N, st);
+  uint16_t *e3a = h(p.e3a), *b3 = h(p.b3), *d2a = h(p.d2a), *d2 = h(p.d2), *d1a = h(p.d1a);
+  const ConvEpi none;
+  ConvEpi pool1, pool2, out;
+  pool1.pool = p1;
+  pool2.pool = p2;
+  out.wo = wbf(n, FO);
+  out.bo = bias(n, FO);
+  out.z = at<float>(n, p.logit);
+  out.prob = prob;
+  // the pooling after e1b and e2b and the output layer after d1b run in
+  // those convolutions' epilogues
+  const bool ok = n->P[FO].cols == 32 && conv(E1A, unet_in, false, e1a, H, W, CONV_STORE, none) &&
+                  conv(E1B, e1a, true, s1, H, W, CONV_POOL, pool1) &&
+                  conv(E2A, p1, true, e2a, H / 2, W / 2, CONV_STORE, none) &&
+                  conv(E2B, e2a, true, s2, H / 2, W / 2, CONV_POOL, pool2) &&
+                  conv(E3A, p2, true, e3a, H / 4, W / 4, CONV_STORE, none) &&
+                  conv(E3B, e3a, true, b3, H / 4, W / 4, CONV_STORE, none) &&
+                  up2_h(wbf(n, U2), b3, bias(n, U2), cat2, 64, 128, Bn, H / 4, W / 4, st) &&
+                  conv(D2A, cat2, true, d2a, H / 2, W / 2, CONV_STORE, none) &&
+                  conv(D2B, d2a, true, d2, H / 2, W / 2, CONV_STORE, none) &&
+                  up2_h(wbf(n, U1), d2, bias(n, U1), cat1, 32, 64, Bn, H / 2, W / 2, st) &&
+                  conv(D1A, cat1, true, d1a, H, W, CONV_STORE, none) &&
+                  conv(D1B, d1a, true, nullptr, H, W, CONV_OUT, out);
   chk(hipGetLastError());
   *err = e;
   return ok;
@@ -647,11 +659,13 @@ static int run_forward(seg_nn* n, const uint16_t* frames, const float* stin, uin
     return SEG_E_INVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t fe = hipSuccess;
-  if (!forward_infer(n, frames, stin, (int)batch, st, &fe)) fe = forward(n, frames, stin, (int)batch, st);
+  float* prob = dev_prob ? dev_prob : at<float>(n, n->plan.prob);
+  if (!forward_infer(n, frames, stin, (int)batch, prob, st, &fe)) {
+    fe = forward(n, frames, stin, (int)batch, st);
+    const long long N = (long long)batch * n->plan.H * n->plan.W;
+    bce(at<float>(n, n->plan.logit), nullptr, nullptr, prob, nullptr, N, st);
+  }
   if (fe != hipSuccess) return SEG_E_DEVICE;
-  const long long N = (long long)batch * n->plan.H * n->plan.W;
-  bce(at<float>(n, n->plan.logit), nullptr, nullptr, dev_prob ? dev_prob : at<float>(n, n->plan.prob), nullptr, N,
-      st);
   n->batch = (int)batch;
   return hipGetLastError() == hipSuccess ? SEG_OK : SEG_E_DEVICE;
 }

@@ -44,19 +44,34 @@ bool up_direct(const uint16_t* Wb, const float* X, const float* bias, float* Y, 
 // Y [N] = bias[0] + W [1][C] X [C][N] (BF16 operands, FP32 accumulation);
 // always launched (returns true).
 bool conv1_out(const uint16_t* Wb, const float* X, const float* bias, float* Y, int C, long long N, hipStream_t st);
-// BF16 activations (inference): the halo-tile convolution with X FP32 or
-// BF16 (x_bf16) and Y BF16, the BF16 rounding of what conv3_implicit stores;
-// false (nothing launched) when the shape does not fit the halo tiles
-bool conv3_halo_h(const uint16_t* Wb, const uint16_t* Wr, const void* X, bool x_bf16, uint16_t* Y, int Co, int Ci,
-                  int Bn, int H, int W, const float* bias, bool relu, hipStream_t st);
-// up_direct with BF16 X and Y (false under the same conditions)
-bool up_direct_h(const uint16_t* Wb, const uint16_t* X, const float* bias, uint16_t* Y, int Co, int Ci, int Bn, int h,
-                 int w, hipStream_t st);
-// conv1_out with BF16 X
-void conv1_out_h(const uint16_t* Wb, const uint16_t* X, const float* bias, float* Y, int C, long long N,
-                 hipStream_t st);
-// 2 x 2 max pooling of BF16 activations, without the argmax
-void pool_h(const uint16_t* X, uint16_t* Y, int CB, int H, int W, hipStream_t st);
+// BF16 activations (inference) are kept in channel blocks of 16: element
+// (c, b, y, x) of [C][Bn][H][W] (C a multiple of 16) at
+// ((c / 16) Bn H W + (b H + y) W + x) 16 + c % 16.
+// Epilogues of conv3_h:
+//   CONV_STORE  Y only;
+//   CONV_POOL   Y and its 2 x 2 max pooling ep.pool [C][Bn][H / 2][W / 2]
+//               (blocked), the values k_pool would take;
+//   CONV_OUT    not Y but the 1 x 1 output layer on it (Co = 32): logits
+//               ep.z [Bn H W] = ep.bo[0] + sum_c ep.wo[c] Y[c] (as conv1_out)
+//               and ep.prob = 1 / (1 + exp(-z)) (as bce).
+enum { CONV_STORE = 0, CONV_POOL = 1, CONV_OUT = 2 };
+struct ConvEpi {
+  uint16_t* pool = nullptr;
+  const uint16_t* wo = nullptr;
+  const float* bo = nullptr;
+  float* z = nullptr;
+  float* prob = nullptr;
+};
+// The halo-tile convolution with X FP32 planar or BF16 blocked (x_bf16) and
+// Y BF16 blocked, the BF16 rounding of what conv3_implicit stores, with the
+// epilogue `mode`; false (nothing launched) when the shape or the epilogue
+// does not fit the halo tiles.
+bool conv3_h(const uint16_t* Wb, const uint16_t* Wr, const void* X, bool x_bf16, uint16_t* Y, int Co, int Ci, int Bn,
+             int H, int W, const float* bias, bool relu, int mode, const ConvEpi& ep, hipStream_t st);
+// up_direct on BF16 blocked X and Y, each input pixel read once; false
+// (nothing launched) unless Co is 32 or 64 and Ci 64 or 128.
+bool up2_h(const uint16_t* Wb, const uint16_t* X, const float* bias, uint16_t* Y, int Co, int Ci, int Bn, int h, int w,
+           hipStream_t st);
 // Wr [ceil(Ci / 16)][Co][9][16] from W [Co][Ci 9] (zero past Ci)
 void conv3_reorder(const uint16_t* Wb, uint16_t* Wr, int Co, int Ci, hipStream_t st);
 size_t conv3_reordered_size(int Co, int Ci);

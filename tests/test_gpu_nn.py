@@ -103,8 +103,9 @@ def test_forward_probabilities(case):
 
 def test_bf16_activation_forward_equals_training_forward():
     """The surrogate's forward-only call keeps the U-Net's activations as
-    BF16 (frame width a multiple of 32); its logits must equal, bit for bit,
-    those of the training forward with FP32 activations."""
+    BF16 in channel blocks (frame width a multiple of 64, height of 4); its
+    logits must equal, bit for bit, those of the training forward with FP32
+    activations."""
     rng = np.random.default_rng(12)
     frames = rng.poisson(600.0, size=(2, 50, 64, 64)).astype(np.uint16)
     frames[:, 20:30, 10:18, 40:48] += 300

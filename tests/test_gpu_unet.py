@@ -154,21 +154,25 @@ def test_convolution_paths_vs_reference(B, H, W):
     net.close()
 
 
-def test_bf16_activation_forward_equals_training_forward():
-    """The forward-only call keeps the activations as BF16 where every layer
-    fits the BF16 kernels (64 x 64 patches); every consumer rounds its input
-    to BF16 anyway, so its logits must equal, bit for bit, those of the
-    training forward (FP32 activations) that the backward call runs."""
+@pytest.mark.parametrize("B,H,W", [(4, 64, 64), (2, 68, 320)])
+def test_bf16_activation_forward_equals_training_forward(B, H, W):
+    """The forward-only call keeps the activations as BF16 in channel blocks
+    where every layer fits the BF16 kernels (H a multiple of 4, W of 64), with
+    the poolings and the output layer in convolution epilogues; every
+    consumer rounds its input to BF16 anyway and every product sums in the
+    same order, so its logits must equal, bit for bit, those of the training
+    forward (FP32 activations) that the backward call runs. 68 x 320 leaves
+    ragged tiles at every level (rows 17 at the lowest, columns 160 and 80)."""
     rng = np.random.default_rng(11)
-    S = rng.uniform(800, 1200, (4, 64, 64))
-    T = rng.uniform(0, 60, (4, 64, 64))
+    S = rng.uniform(800, 1200, (B, H, W))
+    T = rng.uniform(0, 60, (B, H, W))
     T[:, 20:28, 30:38] += 180
     st = torch.from_numpy(np.stack([S, T], axis=1).astype(np.float32)).to(DEV)
-    labels = torch.zeros((4, 64, 64), dtype=torch.float32, device=DEV)
+    labels = torch.zeros((B, H, W), dtype=torch.float32, device=DEV)
     labels[:, 20:28, 30:38] = 1
     theta = he_init(3)
     theta += (0.01 * rng.standard_normal(theta.size)).astype(np.float32)
-    net = SummaryUNet(4, 64, 64, theta)
+    net = SummaryUNet(B, H, W, theta)
     p = net.forward(st)
     li = net.logits().clone()
     net.backward(st, labels)
