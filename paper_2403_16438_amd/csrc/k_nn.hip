@@ -632,9 +632,11 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) s = fmaf(wf[8 * g + r], from_bf16((uint16_t)(hv[t][2 * g + (r >> 1)] >> (16 * (r & 1)))), s);
+          for (int r = 0; r < 4; ++r)
+            s = fmaf(wf[8 * g + r], from_bf16((uint16_t)(hv[t][2 * g + (r >> 1)] >> (16 * (r & 1)))), s);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) s = fmaf(wf[8 * g + 4 + r], from_bf16((uint16_t)(hi[2 * g + (r >> 1)] >> (16 * (r & 1)))), s);
+          for (int r = 0; r < 4; ++r)
+            s = fmaf(wf[8 * g + 4 + r], from_bf16((uint16_t)(hi[2 * g + (r >> 1)] >> (16 * (r & 1)))), s);
         }
         const float z = s + b0;
         const long long pix = (long long)b * HW + (long long)y * W + x;
@@ -874,7 +876,8 @@ __global__ __launch_bounds__(256) void k_up2_h(const uint16_t* __restrict__ Wb, 
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int c = cb + 8 * (2 * gg + (k >> 1)) + 4 * (lane >> 5) + 2 * (k & 1);   // channels c, c + 1
-          w4[k] = to_bf16(acc[i][8 * gg + 2 * k] + Bs[c]) | ((uint32_t)to_bf16(acc[i][8 * gg + 2 * k + 1] + Bs[c + 1]) << 16);
+          w4[k] = to_bf16(acc[i][8 * gg + 2 * k] + Bs[c]) |
+                  ((uint32_t)to_bf16(acc[i][8 * gg + 2 * k + 1] + Bs[c + 1]) << 16);
         }
         const uint4 q = gather8(w4[0], w4[1], w4[2], w4[3]);
         if (p < npix) *reinterpret_cast<uint4*>(Y + cblk(cb + 16 * gg + 8 * (lane >> 5), op, 4 * npix)) = q;
