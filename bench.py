@@ -292,7 +292,9 @@ def surrogate_bench(vdev, k_time, reps, dev):
     from paper_2403_16438_amd import Session, abi
     from paper_2403_16438_amd.surrogate import Surrogate, he_init
     T, H, W = vdev.shape
-    net = Surrogate(1, H, W, he_init(0), dev)
+    # a network of batch 8: the session runs up to eight whole segments of
+    # a push per call, read in place
+    net = Surrogate(8, H, W, he_init(0), dev)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     tp, tf = [], []
     for r in range(reps + 1):

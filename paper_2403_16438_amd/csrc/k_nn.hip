@@ -126,11 +126,21 @@ __global__ __launch_bounds__(256) void k_gemm(const TA* __restrict__ A, long lon
 //             for the transposed 2 x 2 convolution: row 4 co + 2 a + e of the
 //             product, plus bias[co], is stored to C at channel co, pixel
 //             (2 y + a, 2 x + e) of an image of 2 H x 2 W (X's pixels H x W),
-//             so the product lands directly in the concatenation buffer.
-enum { GV_BF16 = 0, GV_IM2COL = 1, GV_UP = 2 };
+//             so the product lands directly in the concatenation buffer;
+//   GV_TCONV  the 1-D temporal im2col of X [C][Tin][Np] (FP32, or BF16 when
+//             tbf16): row k = c KT + tap, column j Np + n holds
+//             X[c][j S + tap - P][n] (zero outside 0 .. Tin - 1), what
+//             im2col1 would write, gathered as it is loaded (Np a multiple
+//             of 8, so a group of 8 columns lies in one j); C is stored as
+//             FP32, or as BF16 bits when `out_h`.
+enum { GV_BF16 = 0, GV_IM2COL = 1, GV_UP = 2, GV_TCONV = 3 };
 struct Im2col {
   const float* X;
   int Bn, H, W;
+  // GV_TCONV
+  const void* TX;
+  int tbf16, Tin, KT, S, P, out_h;
+  long long Np;
 };
 // bias (may be null) and relu are applied to the stored values (not with
 // accumulate), as bias_act does after an unfused product.
@@ -168,7 +178,15 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
   }
   auto load = [&](int k0) {
     const int gm = m0 + am, gk = k0 + ak;
-    ra = (a_on && gm < M && gk < K) ? *reinterpret_cast<const uint4*>(A + gm * sam + gk) : make_uint4(0, 0, 0, 0);
+    if (MODE == GV_TCONV && (sam & 7)) {   // rows not 16-byte aligned (K of 5): element loads
+      uint16_t v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = (a_on && gm < M && gk + q < K) ? A[gm * sam + gk + q] : (uint16_t)0;
+      ra = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
+                      v[6] | ((uint32_t)v[7] << 16));
+    } else {
+      ra = (a_on && gm < M && gk < K) ? *reinterpret_cast<const uint4*>(A + gm * sam + gk) : make_uint4(0, 0, 0, 0);
+    }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int gkb = k0 + bk, gn = n0 + bn + 64 * j;
@@ -181,6 +199,27 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
           const float4 lo = src[0], hi = src[1];
           v = make_uint4(to_bf16(lo.x) | ((uint32_t)to_bf16(lo.y) << 16), to_bf16(lo.z) | ((uint32_t)to_bf16(lo.w) << 16),
                          to_bf16(hi.x) | ((uint32_t)to_bf16(hi.y) << 16), to_bf16(hi.z) | ((uint32_t)to_bf16(hi.w) << 16));
+        }
+        rb[j] = v;
+      } else if constexpr (MODE == GV_TCONV) {
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gkb < K && gn < N) {
+          const int c = gkb / ic.KT, tap = gkb - c * ic.KT;
+          const long long jj = gn / ic.Np, n = gn - jj * ic.Np;
+          const int t = (int)jj * ic.S + tap - ic.P;
+          if (t >= 0 && t < ic.Tin) {
+            const long long off = ((long long)c * ic.Tin + t) * ic.Np + n;
+            if (ic.tbf16) {
+              v = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(ic.TX) + off);
+            } else {
+              const float4* src = reinterpret_cast<const float4*>(static_cast<const float*>(ic.TX) + off);
+              const float4 lo = src[0], hi = src[1];
+              v = make_uint4(to_bf16(lo.x) | ((uint32_t)to_bf16(lo.y) << 16),
+                             to_bf16(lo.z) | ((uint32_t)to_bf16(lo.w) << 16),
+                             to_bf16(hi.x) | ((uint32_t)to_bf16(hi.y) << 16),
+                             to_bf16(hi.z) | ((uint32_t)to_bf16(hi.w) << 16));
+            }
+          }
         }
         rb[j] = v;
       } else {
@@ -252,6 +291,25 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
         }
       }
     return;
+  }
+  if constexpr (MODE == GV_TCONV) {
+    if (ic.out_h) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
+          if (row < M) {
+            float v = acc[4 * g + r];
+            if (bias) {
+              v += bias[row];
+              if (relu) v = fmaxf(v, 0.f);
+            }
+            reinterpret_cast<uint16_t*>(C)[(long long)row * ldc + col] = to_bf16(v);
+          }
+        }
+      return;
+    }
   }
 #pragma unroll
   for (int g = 0; g < 4; ++g)
@@ -973,6 +1031,38 @@ __global__ void k_tnorm(const uint16_t* __restrict__ frames, float* __restrict__
   for (int t = 0; t < L; ++t) out[((long long)t * Bn + b) * HW + p] = ((float)f[(long long)t * HW] - mean) * inv;
 }
 
+// k_tnorm with BF16 output (inference: the first temporal convolution rounds
+// its input to BF16 anyway). LF > 0 fixes the frame count, so a thread's
+// frames are loaded together into registers.
+template <int LF>
+__global__ void k_tnorm_h(const uint16_t* __restrict__ frames, uint16_t* __restrict__ out, int Bn, int L,
+                          long long HW) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)Bn * HW) return;
+  const int b = (int)(i / HW);
+  const long long p = i % HW;
+  const uint16_t* f = frames + (long long)b * L * HW + p;
+  if constexpr (LF > 0) {
+    float v[LF];
+#pragma unroll
+    for (int t = 0; t < LF; ++t) v[t] = (float)f[(long long)t * HW];
+    float s = 0.f;
+#pragma unroll
+    for (int t = 0; t < LF; ++t) s += v[t];
+    const float mean = s / LF;
+    const float inv = rsqrtf(mean + 25.f);
+#pragma unroll
+    for (int t = 0; t < LF; ++t) out[((long long)t * Bn + b) * HW + p] = to_bf16((v[t] - mean) * inv);
+  } else {
+    float s = 0.f;
+    for (int t = 0; t < L; ++t) s += (float)f[(long long)t * HW];
+    const float mean = s / L;
+    const float inv = rsqrtf(mean + 25.f);
+    for (int t = 0; t < L; ++t)
+      out[((long long)t * Bn + b) * HW + p] = to_bf16(((float)f[(long long)t * HW] - mean) * inv);
+  }
+}
+
 // 1-D im2col: in [C][Tin][N], kernel KT, stride S, pad P ->
 // col[(c*KT + k)][(j*N + n)] = in[c][j*S + k - P][n], j < Tout
 __global__ void k_im2col1(const float* __restrict__ in, uint16_t* __restrict__ col, int C, int Tin, int Tout,
@@ -1393,6 +1483,25 @@ bool conv1_out(const uint16_t* Wb, const float* X, const float* bias, float* Y, 
   L1(k_conv1_out, N, Wb, X, bias, Y, C, N);
   return true;
 }
+bool tconv(const uint16_t* Wb, int Co, const void* X, bool x_bf16, int C, int Tin, int Tout, int KT, int S, int P,
+           long long Np, const float* bias, bool relu, void* Y, bool y_bf16, hipStream_t st) {
+  const long long N = (long long)Tout * Np;
+  const int K = C * KT;
+  if (Co > 32 || Np % 8 || N > 0x7fffffffLL || ((uintptr_t)Wb & 15) || ((uintptr_t)X & 15)) return false;
+  Im2col ic{};
+  ic.TX = X;
+  ic.tbf16 = x_bf16;
+  ic.Tin = Tin;
+  ic.KT = KT;
+  ic.S = S;
+  ic.P = P;
+  ic.out_h = y_bf16;
+  ic.Np = Np;
+  hipLaunchKernelGGL((k_gemm_v<32, GV_TCONV>), dim3((unsigned)((N + 127) / 128), 1), dim3(256), 0, st, Wb, (long long)K,
+                     nullptr, 0LL, ic, static_cast<float*>(Y), N, Co, (int)N, K, 0, bias, (int)relu);
+  return true;
+}
+
 bool up2_h(const uint16_t* Wb, const uint16_t* X, const float* bias, uint16_t* Y, int Co, int Ci, int Bn, int h, int w,
            hipStream_t st) {
   const long long npix = (long long)Bn * h * w;
@@ -1423,6 +1532,12 @@ void col2im3(const float* dcol, float* dX, int C, int Bn, int H, int W, bool acc
 }
 void tnorm(const uint16_t* frames, float* out, int Bn, int L, long long HW, hipStream_t st) {
   L1(k_tnorm, (long long)Bn * HW, frames, out, Bn, L, HW);
+}
+void tnorm_h(const uint16_t* frames, uint16_t* out, int Bn, int L, long long HW, hipStream_t st) {
+  if (L == 50)
+    L1(k_tnorm_h<50>, (long long)Bn * HW, frames, out, Bn, L, HW);
+  else
+    L1(k_tnorm_h<0>, (long long)Bn * HW, frames, out, Bn, L, HW);
 }
 void im2col1(const float* in, uint16_t* col, int C, int Tin, int Tout, int KT, int S, int P, long long N,
              hipStream_t st) {

@@ -395,24 +395,24 @@ bool forward_infer(seg_nn* n, const uint16_t* frames, const float* stin, int Bn,
     if (x != hipSuccess && e == hipSuccess) e = x;
   };
   float* x0 = at<float>(n, p.x0);
-  uint16_t* col = at<uint16_t>(n, p.col);
   const float* unet_in = nullptr;
   if (n->st) {
     st_norm(stin, x0, Bn, HW, st);
     unet_in = x0;
   } else {
-    tnorm(frames, x0, Bn, L, HW, st);
-    float* a1 = at<float>(n, p.a1);
-    im2col1(x0, col, 1, L, 10, 5, 5, 0, N, st);
-    chk(gemm_wx(n, T1, col, true, 10 * N, a1, st));
-    bias_act(a1, bias(n, T1), 32, 10 * N, true, st);
-    float* a2 = at<float>(n, p.a2);
-    im2col1(a1, col, 32, 10, 5, 5, 2, 2, N, st);
-    chk(gemm_wx(n, T2, col, true, 5 * N, a2, st));
-    bias_act(a2, bias(n, T2), 32, 5 * N, true, st);
+    // the temporal convolutions gather their im2col as they load it, with
+    // bias and ReLU in the product's epilogue; the normalised frames, a1 and
+    // a2 are stored as BF16 (their consumers round them to BF16), a3 as FP32
+    // for the first 3 x 3 convolution's FP32 staging
+    uint16_t* x0h = at<uint16_t>(n, p.x0);
+    tnorm_h(frames, x0h, Bn, L, HW, st);
+    uint16_t* a1 = at<uint16_t>(n, p.a1);
+    uint16_t* a2 = at<uint16_t>(n, p.a2);
     float* a3 = at<float>(n, p.a3);
-    chk(gemm_wx(n, T3, a2, false, N, a3, st));
-    bias_act(a3, bias(n, T3), 32, N, true, st);
+    if (!(tconv(wbf(n, T1), 32, x0h, true, 1, L, 10, 5, 5, 0, N, bias(n, T1), true, a1, true, st) &&
+          tconv(wbf(n, T2), 32, a1, true, 32, 10, 5, 5, 2, 2, N, bias(n, T2), true, a2, true, st) &&
+          tconv(wbf(n, T3), 32, a2, true, 32, 5, 1, 5, 1, 0, N, bias(n, T3), true, a3, false, st)))
+      return false;
     unet_in = a3;
   }
   auto h = [&](const Buf& b) { return at<uint16_t>(n, b); };

@@ -130,28 +130,40 @@ T* at(seg_session* s, size_t off) {
 
 int fail(seg_session* s, hipError_t e);
 
-// Surrogate detector: for each segment completed by this push, stage its 50
-// frames contiguously (they may straddle the carried tail and the caller's
-// buffer) and write the network's probability map into p[K + j].
+// Surrogate detector: for each segment completed by this push, write the
+// network's probability map into p[K + j]. A segment that straddles the
+// carried tail and the caller's buffer is staged contiguously first; the
+// others are read where they are, as many per network call as its batch.
 int surrogate_maps(seg_session* s, const uint16_t* dev_frames, uint32_t nseg, hipStream_t st) {
   const size_t M = s->M;
   uint16_t* tail = at<uint16_t>(s, s->lay.tail);
   uint16_t* stage = at<uint16_t>(s, s->lay.stage);
   float* p = at<float>(s, s->lay.p);
-  for (uint32_t j = 0; j < nseg; ++j) {
+  uint32_t B = 1;
+  if (seg_nn_shape(s->net, &B, nullptr, nullptr) || B < 1) return fail(s, hipErrorUnknown);
+  for (uint32_t j = 0; j < nseg;) {
     const long long f0 = (long long)j * seg::kSegLen;   // first frame, counted from the tail start
     const long long in_tail = std::max(0LL, std::min<long long>(seg::kSegLen, (long long)s->tail_n - f0));
-    hipError_t he = hipSuccess;
-    if (in_tail > 0)
-      he = hipMemcpyAsync(stage, tail + (size_t)f0 * M, (size_t)in_tail * M * 2, hipMemcpyDeviceToDevice, st);
-    if (he == hipSuccess && in_tail < seg::kSegLen) {
-      const long long from = f0 + in_tail - (long long)s->tail_n;
-      he = hipMemcpyAsync(stage + (size_t)in_tail * M, dev_frames + (size_t)from * M,
-                          (size_t)(seg::kSegLen - in_tail) * M * 2, hipMemcpyDeviceToDevice, st);
+    if (in_tail > 0) {
+      // a segment that starts in the tail: staged contiguously, alone
+      hipError_t he =
+          hipMemcpyAsync(stage, tail + (size_t)f0 * M, (size_t)in_tail * M * 2, hipMemcpyDeviceToDevice, st);
+      if (he == hipSuccess && in_tail < seg::kSegLen) {
+        const long long from = f0 + in_tail - (long long)s->tail_n;
+        he = hipMemcpyAsync(stage + (size_t)in_tail * M, dev_frames + (size_t)from * M,
+                            (size_t)(seg::kSegLen - in_tail) * M * 2, hipMemcpyDeviceToDevice, st);
+      }
+      if (fail(s, he)) return SEG_E_DEVICE;
+      if (seg_nn_forward(s->net, stage, 1, p + (size_t)(s->K + j) * M, st)) return fail(s, hipErrorUnknown);
+      ++j;
+      continue;
     }
-    if (fail(s, he)) return SEG_E_DEVICE;
-    const int r = seg_nn_forward(s->net, stage, 1, p + (size_t)(s->K + j) * M, st);
-    if (r) return fail(s, hipErrorUnknown);
+    // segments wholly in this push's frames lie back to back: up to the
+    // network's batch of them in one call, read in place
+    const uint32_t b = std::min(B, nseg - j);
+    const uint16_t* src = dev_frames + (size_t)(f0 - (long long)s->tail_n) * M;
+    if (seg_nn_forward(s->net, src, b, p + (size_t)(s->K + j) * M, st)) return fail(s, hipErrorUnknown);
+    j += b;
   }
   return SEG_OK;
 }

@@ -22,14 +22,20 @@ def _video(h, w, frames, seed, **kw):
     return sc.render(0, frames).cpu().numpy().view(np.uint16), sc.truth
 
 
-def test_session_maps_equal_network_output():
-    """The session's detection maps are the network's probabilities per segment."""
-    v, _ = _video(64, 64, 250, 31, n_neurons=3, n_overlap=0, min_sep=16.0)
-    net = Surrogate(1, 64, 64, he_init(5))
-    sess = segment_video(v, block=70, net=net)
+@pytest.mark.parametrize("batch,frames,block", [(1, 250, 70), (3, 400, 170)])
+def test_session_maps_equal_network_output(batch, frames, block):
+    """The session's detection maps are the network's probabilities per
+    segment, bit for bit, whether a segment straddles the carried tail
+    (staged, run alone) or lies in a push with others (run in place, up to
+    the network's batch per call: 400 frames in pushes of 170 give calls of
+    3 whole segments, a straddling one, and 2 whole ones)."""
+    v, _ = _video(64, 64, frames, 31, n_neurons=3, n_overlap=0, min_sep=16.0)
+    net = Surrogate(batch, 64, 64, he_init(5))
+    sess = segment_video(v, block=block, net=net)
     P = sess.segment_maps(abi.SEG_MAP_P).cpu().numpy()
-    assert P.shape == (5, 64, 64)
-    for i in range(5):
+    nseg = frames // 50
+    assert P.shape == (nseg, 64, 64)
+    for i in range(nseg):
         p = net.forward(torch.from_numpy(v[i * 50:(i + 1) * 50][None].view(np.int16)).cuda())
         assert np.array_equal(P[i], p[0].cpu().numpy())
     # the events are the thresholded probabilities
