@@ -139,7 +139,7 @@ struct Im2col {
   int Bn, H, W;
   // GV_TCONV
   const void* TX;
-  int tbf16, Tin, KT, S, P, out_h;
+  int tbf16, Tin, KT, S, P, out_h, xcd;
   long long Np;
 };
 // bias (may be null) and relu are applied to the stored values (not with
@@ -155,7 +155,19 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
   __shared__ uint16_t Bs[NT][GK + 8];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = MT == 64 ? wv >> 1 : 0, wn = MT == 64 ? wv & 1 : wv;
-  const int m0 = blockIdx.y * MT, n0 = blockIdx.x * NT;
+  const int m0 = blockIdx.y * MT;
+  int n0 = blockIdx.x * NT;
+  if constexpr (MODE == GV_TCONV) {
+    if (ic.xcd) {
+      // The output samples j of one pixel range read overlapping input rows:
+      // tile t = (pixel range, j) with j fastest, and the workgroups that the
+      // dispatcher sends to one XCD (blockIdx.x mod 8) take one contiguous
+      // run of tiles, so the re-reads hit that XCD's L2.
+      const int T = gridDim.x, x = blockIdx.x, t = (x & 7) * (T >> 3) + (x >> 3);
+      const int tout = (int)(N / ic.Np), j = t % tout;
+      n0 = (int)(j * ic.Np) + (t / tout) * NT;
+    }
+  }
   // A: thread -> (row am, k group ak); B: thread -> (k row bk, n group bn + 64 j)
   const int am = tid >> 2, ak = (tid & 3) * 8;
   const bool a_on = am < MT;
@@ -165,6 +177,16 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
   // column are found once
   int py[NB], px[NB];
   long long poff[NB];
+  if constexpr (MODE == GV_TCONV) {
+    // a thread's column groups are fixed: sample j and pixel n found once
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int gn = n0 + bn + 64 * j;
+      const long long jj = gn / ic.Np;
+      py[j] = gn < N ? (int)jj * ic.S - ic.P : -(1 << 20);   // input sample of tap 0 (off-range groups load nothing)
+      poff[j] = gn - jj * ic.Np;
+    }
+  }
   if constexpr (MODE == GV_IM2COL) {
     const int HW = ic.H * ic.W;
 #pragma unroll
@@ -203,12 +225,12 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
         rb[j] = v;
       } else if constexpr (MODE == GV_TCONV) {
         uint4 v = make_uint4(0, 0, 0, 0);
-        if (gkb < K && gn < N) {
+        (void)gn;
+        if (gkb < K) {
           const int c = gkb / ic.KT, tap = gkb - c * ic.KT;
-          const long long jj = gn / ic.Np, n = gn - jj * ic.Np;
-          const int t = (int)jj * ic.S + tap - ic.P;
+          const int t = py[j] + tap;
           if (t >= 0 && t < ic.Tin) {
-            const long long off = ((long long)c * ic.Tin + t) * ic.Np + n;
+            const long long off = ((long long)c * ic.Tin + t) * ic.Np + poff[j];
             if (ic.tbf16) {
               v = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(ic.TX) + off);
             } else {
@@ -274,6 +296,34 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
     }
     __syncthreads();
   }
+  if constexpr (MODE == GV_TCONV) {
+    if (ic.out_h) {
+      // BF16 output: the tile goes through LDS so that each thread stores
+      // 16 bytes of one row (8 columns; N is a multiple of 8)
+      __shared__ __attribute__((aligned(16))) uint16_t Ts[MT][NT + 8];
+      const int cl = wn * 32 + (lane & 31);
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rl = wm * 32 + 8 * g + 4 * (lane >> 5) + r, row = m0 + rl;
+          float v = acc[4 * g + r];
+          if (bias && row < M) {
+            v += bias[row];
+            if (relu) v = fmaxf(v, 0.f);
+          }
+          Ts[rl][cl] = to_bf16(v);
+        }
+      __syncthreads();
+      for (int e = tid; e < MT * (NT / 8); e += 256) {
+        const int rl = e / (NT / 8), c8 = (e - rl * (NT / 8)) * 8, row = m0 + rl, gc = n0 + c8;
+        if (row < M && gc < N)
+          *reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(C) + (long long)row * ldc + gc) =
+              *reinterpret_cast<const uint4*>(&Ts[rl][c8]);
+      }
+      return;
+    }
+  }
   const int col = n0 + wn * 32 + (lane & 31);
   if (col >= N) return;
   if constexpr (MODE == GV_UP) {
@@ -291,25 +341,6 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
         }
       }
     return;
-  }
-  if constexpr (MODE == GV_TCONV) {
-    if (ic.out_h) {
-#pragma unroll
-      for (int g = 0; g < 4; ++g)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = m0 + wm * 32 + 8 * g + 4 * (lane >> 5) + r;
-          if (row < M) {
-            float v = acc[4 * g + r];
-            if (bias) {
-              v += bias[row];
-              if (relu) v = fmaxf(v, 0.f);
-            }
-            reinterpret_cast<uint16_t*>(C)[(long long)row * ldc + col] = to_bf16(v);
-          }
-        }
-      return;
-    }
   }
 #pragma unroll
   for (int g = 0; g < 4; ++g)
@@ -1031,35 +1062,86 @@ __global__ void k_tnorm(const uint16_t* __restrict__ frames, float* __restrict__
   for (int t = 0; t < L; ++t) out[((long long)t * Bn + b) * HW + p] = ((float)f[(long long)t * HW] - mean) * inv;
 }
 
-// k_tnorm with BF16 output (inference: the first temporal convolution rounds
-// its input to BF16 anyway). LF > 0 fixes the frame count, so a thread's
-// frames are loaded together into registers.
-template <int LF>
-__global__ void k_tnorm_h(const uint16_t* __restrict__ frames, uint16_t* __restrict__ out, int Bn, int L,
-                          long long HW) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)Bn * HW) return;
-  const int b = (int)(i / HW);
-  const long long p = i % HW;
-  const uint16_t* f = frames + (long long)b * L * HW + p;
-  if constexpr (LF > 0) {
-    float v[LF];
+// The frame normalisation and the first temporal convolution (one input
+// channel, 32 outputs, kernel 5, stride 5, no padding: 50 -> 10 samples) in
+// one pass, for inference. A wave takes 64 pixels. Each lane loads its
+// pixel's 50 frames and normalises them as k_tnorm does (sequential FP32 sum,
+// mean, 1 / sqrt(mean + 25)), rounding to BF16 as im2col1 does; for output
+// sample j the 5 values are the depth of one 32 x 32 x 16 MFMA, lanes
+// 32..63 handing their pixels to lanes 0..31 for a second one, each followed
+// by the all-zero step that the product kernels run for the rest of their
+// 32-deep chunk, so the sums are those of im2col1 + gemm. Bias, ReLU and BF16
+// rounding as bias_act and the BF16 store; a1 [32][10][Np] (row c, column
+// j Np + n) is written through a per-wave LDS tile, 16 bytes per lane.
+constexpr int T1_L = 50, T1_K = 5, T1_TO = 10;
+__global__ __launch_bounds__(256) void k_tconv1_h(const uint16_t* __restrict__ frames, const uint16_t* __restrict__ Wb,
+                                                  const float* __restrict__ bias, uint16_t* __restrict__ a1, int Bn,
+                                                  long long HW) {
+  __shared__ __attribute__((aligned(16))) uint16_t Ts[4][32][64 + 8];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane >> 5;
+  const long long Np = (long long)Bn * HW;
+  const long long p0 = ((long long)blockIdx.x * 4 + wv) * 64;   // the wave's first pixel (Np % 64 == 0)
+  if (p0 >= Np) return;   // whole waves; no workgroup barrier below
+  const long long n = p0 + lane;
+  const long long b = n / HW, p = n - b * HW;
+  const uint16_t* f = frames + b * T1_L * HW + p;
+  float v[T1_L];
 #pragma unroll
-    for (int t = 0; t < LF; ++t) v[t] = (float)f[(long long)t * HW];
-    float s = 0.f;
+  for (int t = 0; t < T1_L; ++t) v[t] = (float)f[(long long)t * HW];
+  float s = 0.f;
 #pragma unroll
-    for (int t = 0; t < LF; ++t) s += v[t];
-    const float mean = s / LF;
-    const float inv = rsqrtf(mean + 25.f);
+  for (int t = 0; t < T1_L; ++t) s += v[t];
+  const float mean = s / T1_L;
+  const float inv = rsqrtf(mean + 25.f);
+  // weights: row lane & 31, depth 0..4 in lanes 0..31, zero elsewhere
+  bf16x8 a, z;
 #pragma unroll
-    for (int t = 0; t < LF; ++t) out[((long long)t * Bn + b) * HW + p] = to_bf16((v[t] - mean) * inv);
-  } else {
-    float s = 0.f;
-    for (int t = 0; t < L; ++t) s += (float)f[(long long)t * HW];
-    const float mean = s / L;
-    const float inv = rsqrtf(mean + 25.f);
-    for (int t = 0; t < L; ++t)
-      out[((long long)t * Bn + b) * HW + p] = to_bf16(((float)f[(long long)t * HW] - mean) * inv);
+  for (int q = 0; q < 8; ++q) {
+    a[q] = __builtin_bit_cast(__bf16, (h == 0 && q < T1_K) ? Wb[(lane & 31) * T1_K + q] : (uint16_t)0);
+    z[q] = __builtin_bit_cast(__bf16, (uint16_t)0);
+  }
+  float bv[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) bv[k] = bias[8 * (k >> 2) + 4 * h + (k & 3)];
+#pragma unroll
+  for (int j = 0; j < T1_TO; ++j) {
+    uint32_t w[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const uint16_t lo = to_bf16((v[5 * j + 2 * q] - mean) * inv);
+      const uint16_t hi = 2 * q + 1 < T1_K ? to_bf16((v[5 * j + 2 * q + 1] - mean) * inv) : (uint16_t)0;
+      w[q] = lo | ((uint32_t)hi << 16);
+    }
+    uint32_t u[3];   // lanes 0..31: the words of lane + 32 (pixels 32..63)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) u[q] = from_upper_half(w[q]);
+    f32x16 acc[2];
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      const uint32_t* src = blk ? u : w;
+      const uint4 bq = h == 0 ? make_uint4(src[0], src[1], src[2], 0) : make_uint4(0, 0, 0, 0);
+      f32x16 c;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) c[i] = 0.f;
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, __builtin_bit_cast(bf16x8, bq), c, 0, 0, 0);
+      acc[blk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(z, z, c, 0, 0, 0);
+    }
+    // tile [32 channels][64 pixels] of sample j, then 16-byte row pieces
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const float y = fmaxf(acc[blk][k] + bv[k], 0.f);
+        Ts[wv][8 * (k >> 2) + 4 * h + (k & 3)][32 * blk + (lane & 31)] = to_bf16(y);
+      }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = lane + 64 * i, row = e >> 3, c8 = (e & 7) * 8;
+      *reinterpret_cast<uint4*>(a1 + (long long)row * T1_TO * Np + (long long)j * Np + p0 + c8) =
+          *reinterpret_cast<const uint4*>(&Ts[wv][row][c8]);
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   }
 }
 
@@ -1487,7 +1569,8 @@ bool tconv(const uint16_t* Wb, int Co, const void* X, bool x_bf16, int C, int Ti
            long long Np, const float* bias, bool relu, void* Y, bool y_bf16, hipStream_t st) {
   const long long N = (long long)Tout * Np;
   const int K = C * KT;
-  if (Co > 32 || Np % 8 || N > 0x7fffffffLL || ((uintptr_t)Wb & 15) || ((uintptr_t)X & 15)) return false;
+  if (Co > 32 || Np % 8 || N > 0x7fffffffLL || ((uintptr_t)Wb & 15) || ((uintptr_t)X & 15) || ((uintptr_t)Y & 15))
+    return false;
   Im2col ic{};
   ic.TX = X;
   ic.tbf16 = x_bf16;
@@ -1497,7 +1580,9 @@ bool tconv(const uint16_t* Wb, int Co, const void* X, bool x_bf16, int C, int Ti
   ic.P = P;
   ic.out_h = y_bf16;
   ic.Np = Np;
-  hipLaunchKernelGGL((k_gemm_v<32, GV_TCONV>), dim3((unsigned)((N + 127) / 128), 1), dim3(256), 0, st, Wb, (long long)K,
+  const long long tiles = (N + 127) / 128;
+  ic.xcd = Tout > 1 && Np % 128 == 0 && tiles % 8 == 0;   // tile order of the kernel's GV_TCONV remap
+  hipLaunchKernelGGL((k_gemm_v<32, GV_TCONV>), dim3((unsigned)tiles, 1), dim3(256), 0, st, Wb, (long long)K,
                      nullptr, 0LL, ic, static_cast<float*>(Y), N, Co, (int)N, K, 0, bias, (int)relu);
   return true;
 }
@@ -1533,11 +1618,13 @@ void col2im3(const float* dcol, float* dX, int C, int Bn, int H, int W, bool acc
 void tnorm(const uint16_t* frames, float* out, int Bn, int L, long long HW, hipStream_t st) {
   L1(k_tnorm, (long long)Bn * HW, frames, out, Bn, L, HW);
 }
-void tnorm_h(const uint16_t* frames, uint16_t* out, int Bn, int L, long long HW, hipStream_t st) {
-  if (L == 50)
-    L1(k_tnorm_h<50>, (long long)Bn * HW, frames, out, Bn, L, HW);
-  else
-    L1(k_tnorm_h<0>, (long long)Bn * HW, frames, out, Bn, L, HW);
+bool tconv1_h(const uint16_t* frames, int L, const uint16_t* Wb, int Co, int KT, const float* bias, uint16_t* a1, int Bn,
+              long long HW, hipStream_t st) {
+  const long long Np = (long long)Bn * HW;
+  if (L != T1_L || Co != 32 || KT != T1_K || Np % 64 || ((uintptr_t)a1 & 15)) return false;
+  const long long waves = Np / 64;
+  hipLaunchKernelGGL(k_tconv1_h, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, frames, Wb, bias, a1, Bn, HW);
+  return true;
 }
 void im2col1(const float* in, uint16_t* col, int C, int Tin, int Tout, int KT, int S, int P, long long N,
              hipStream_t st) {

@@ -400,16 +400,15 @@ bool forward_infer(seg_nn* n, const uint16_t* frames, const float* stin, int Bn,
     st_norm(stin, x0, Bn, HW, st);
     unet_in = x0;
   } else {
-    // the temporal convolutions gather their im2col as they load it, with
-    // bias and ReLU in the product's epilogue; the normalised frames, a1 and
-    // a2 are stored as BF16 (their consumers round them to BF16), a3 as FP32
-    // for the first 3 x 3 convolution's FP32 staging
-    uint16_t* x0h = at<uint16_t>(n, p.x0);
-    tnorm_h(frames, x0h, Bn, L, HW, st);
+    // the frame normalisation runs inside the first temporal convolution;
+    // the other two gather their im2col as they load it, with bias and ReLU
+    // in the product's epilogue; a1 and a2 are stored as BF16 (their
+    // consumers round them to BF16), a3 as FP32 for the first 3 x 3
+    // convolution's FP32 staging
     uint16_t* a1 = at<uint16_t>(n, p.a1);
     uint16_t* a2 = at<uint16_t>(n, p.a2);
     float* a3 = at<float>(n, p.a3);
-    if (!(tconv(wbf(n, T1), 32, x0h, true, 1, L, 10, 5, 5, 0, N, bias(n, T1), true, a1, true, st) &&
+    if (!(tconv1_h(frames, L, wbf(n, T1), n->P[T1].rows, n->P[T1].cols, bias(n, T1), a1, Bn, HW, st) &&
           tconv(wbf(n, T2), 32, a1, true, 32, 10, 5, 5, 2, 2, N, bias(n, T2), true, a2, true, st) &&
           tconv(wbf(n, T3), 32, a2, true, 32, 5, 1, 5, 1, 0, N, bias(n, T3), true, a3, false, st)))
       return false;

@@ -73,7 +73,7 @@ bool conv3_h(const uint16_t* Wb, const uint16_t* Wr, const void* X, bool x_bf16,
 // X [C][Tin][Np] (FP32, or BF16 when x_bf16) that im2col1 would write, plus
 // bias and ReLU, stored as FP32 or as BF16 (y_bf16); the same MFMA sums as
 // im2col1 + gemm + bias_act. False (nothing launched) when Co > 32, Np is
-// not a multiple of 8 or W, X are not 16-byte aligned.
+// not a multiple of 8 or W, X, Y are not 16-byte aligned.
 bool tconv(const uint16_t* Wb, int Co, const void* X, bool x_bf16, int C, int Tin, int Tout, int KT, int S, int P,
            long long Np, const float* bias, bool relu, void* Y, bool y_bf16, hipStream_t st);
 // up_direct on BF16 blocked X and Y, each input pixel read once; false
@@ -85,8 +85,13 @@ void conv3_reorder(const uint16_t* Wb, uint16_t* Wr, int Co, int Ci, hipStream_t
 size_t conv3_reordered_size(int Co, int Ci);
 void col2im3(const float* dcol, float* dX, int C, int Bn, int H, int W, bool acc, hipStream_t st);
 void tnorm(const uint16_t* frames, float* out, int Bn, int L, long long HW, hipStream_t st);
-// tnorm's values rounded to BF16
-void tnorm_h(const uint16_t* frames, uint16_t* out, int Bn, int L, long long HW, hipStream_t st);
+// tnorm and the first temporal convolution (W [32][5], stride 5, no padding,
+// bias and ReLU) in one pass for inference, a1 [32][10][Bn HW] as BF16: the
+// same values as tnorm, im2col1, gemm and bias_act rounded to BF16. False
+// (nothing launched) unless L = 50, Co = 32, KT = 5, Bn HW is a multiple of
+// 64 and a1 is 16-byte aligned.
+bool tconv1_h(const uint16_t* frames, int L, const uint16_t* Wb, int Co, int KT, const float* bias, uint16_t* a1, int Bn,
+              long long HW, hipStream_t st);
 void im2col1(const float* in, uint16_t* col, int C, int Tin, int Tout, int KT, int S, int P, long long N,
              hipStream_t st);
 void col2im1(const float* dcol, float* din, int C, int Tin, int Tout, int KT, int S, int P, long long N,
