@@ -170,6 +170,16 @@ __device__ __forceinline__ u64 get_word(u64* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The same word read through this XCD's L2 (workgroup scope: past the L1,
+// not past the L2). The planner places a component's workgroups on one XCD
+// where it can, so a slot written there (the agent-scope store passes
+// through that L2) is seen at L2 latency; a word written on another XCD may
+// sit stale in this L2, so the waits below also read with agent scope every
+// fourth poll. The tags make a stale word harmless: it is only waited on.
+__device__ __forceinline__ u64 get_word_near(u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ bool tagged(u64 w, unsigned tag) { return (unsigned)(w >> 32) == tag; }
 
 // Waits until both halves at p and p + xs carry `tag` and returns them;
@@ -184,7 +194,8 @@ __device__ __forceinline__ Halves wait_words(u64* p, int xs, unsigned tag, unsig
   const long long t0 = wall_clock64();
   for (unsigned n = 0;; ++n) {
     __builtin_amdgcn_s_sleep(2);
-    const u64 hi = get_word(p), lo = get_word(p + xs);
+    const bool far = (n & 3) == 3;
+    const u64 hi = far ? get_word(p) : get_word_near(p), lo = far ? get_word(p + xs) : get_word_near(p + xs);
     if (tagged(hi, tag) && tagged(lo, tag)) return {hi, lo, true};
     if ((n & 15) == 15 && __hip_atomic_load(abandoned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
       return {0, 0, false};
@@ -206,7 +217,7 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
   __shared__ int bad;
   const int g = blockIdx.x, t = threadIdx.x;
   const int c = s.wg_comp[g];
-  const int w0 = s.wg_base[c], nw = s.wg_n[c], r = g - w0;
+  const int w0 = s.wg_base[c], nw = s.wg_n[c], r = s.wg_rank[g];
   const int off = a.coff[c], Mc = a.coff[c + 1] - off;
   const int mw = s.mw, lo = r * mw, ml = min(mw, Mc - lo);  // own rows [lo, lo + ml)
   const int K = a.K, Kp = s.Kp, XS = s.XS;
@@ -245,8 +256,8 @@ __global__ __launch_bounds__(CT) void k_nmf_split(NmfArgs a, NmfSplit s) {
 #pragma unroll
       for (int q = 0; q < 12; ++q) {
         u64* p = slot(min(wb + q, nw - 1), e) + j;
-        hi[q] = get_word(p);
-        lw[q] = get_word(p + XS);
+        hi[q] = get_word_near(p);
+        lw[q] = get_word_near(p + XS);
       }
       asm volatile("" : "+v"(hi[0]), "+v"(hi[1]), "+v"(hi[2]), "+v"(hi[3]), "+v"(hi[4]), "+v"(hi[5]),
                         "+v"(hi[6]), "+v"(hi[7]), "+v"(hi[8]), "+v"(hi[9]), "+v"(hi[10]), "+v"(hi[11]),
@@ -671,23 +682,67 @@ bool plan_nmf_split(NmfSplit& s, const NmfArgs& a, const std::vector<int>& coff,
   s.lds_bytes = lds;
   s.limit = (long long)clock_khz * 1000LL * 2;  // two seconds of wall clock
   tab.comp.clear();
+  tab.rank.clear();
   tab.base.assign((size_t)ncomp, 0);
   tab.n.assign((size_t)ncomp, 0);
   tab.groups.clear();
+  // components in order into launches; base[k] numbers a component's slots
+  // within its launch
+  std::vector<std::vector<int>> members(1);
   int start = 0, in_group = 0;
   for (int k = 0; k < ncomp; ++k) {
     const int nwk = (coff[k + 1] - coff[k] + mw - 1) / mw;
     if (in_group + nwk > ncu) {
       tab.groups.push_back({start, in_group});
+      members.emplace_back();
       start += in_group;
       in_group = 0;
     }
-    tab.base[k] = in_group;              // first workgroup within its launch
+    tab.base[k] = in_group;
     tab.n[k] = nwk;
-    for (int j = 0; j < nwk; ++j) tab.comp.push_back(k);
+    members.back().push_back(k);
     in_group += nwk;
   }
   tab.groups.push_back({start, in_group});
+  // Workgroup g of a launch runs on XCD g mod 8 (the dispatcher deals
+  // workgroups to the XCDs in turn). Each component gets workgroups of one
+  // XCD where one has room (largest components first, into the XCD with the
+  // most room), so its exchanges stay in that XCD's L2; the rest take what
+  // is left.
+  constexpr int NX = 8;
+  tab.comp.assign((size_t)start + in_group, 0);
+  tab.rank.assign((size_t)start + in_group, 0);
+  for (size_t gi = 0; gi < tab.groups.size(); ++gi) {
+    const int first = tab.groups[gi].first, G = tab.groups[gi].second;
+    std::vector<std::vector<int>> free_g(NX);
+    for (int g = G - 1; g >= 0; --g) free_g[g % NX].push_back(g);   // popped in increasing order
+    std::vector<int> order = members[gi];
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tab.n[x] > tab.n[y]; });
+    std::vector<int> spill;
+    for (const int k : order) {
+      int best = -1;
+      for (int x = 0; x < NX; ++x)
+        if ((int)free_g[x].size() >= tab.n[k] && (best < 0 || free_g[x].size() > free_g[best].size())) best = x;
+      if (best < 0) {
+        spill.push_back(k);
+        continue;
+      }
+      for (int j = 0; j < tab.n[k]; ++j) {
+        const int g = free_g[best].back();
+        free_g[best].pop_back();
+        tab.comp[first + g] = k;
+        tab.rank[first + g] = j;
+      }
+    }
+    for (const int k : spill)
+      for (int j = 0, x = 0; j < tab.n[k]; ++j) {
+        while (free_g[x].empty()) ++x;
+        const int g = free_g[x].back();
+        free_g[x].pop_back();
+        tab.comp[first + g] = k;
+        tab.rank[first + g] = j;
+      }
+  }
   s.G = (int)tab.comp.size();
   return true;
 }

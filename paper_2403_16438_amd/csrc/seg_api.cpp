@@ -507,6 +507,8 @@ int seg_finalize(seg_session* s, void* stream) {
       if ((e = fail(s, hipMemcpyAsync(tab + G + ncomp, tabs.n.data(), (size_t)ncomp * 4, hipMemcpyHostToDevice,
                                       st))))
         return e;
+      int* rank = tab + G + 2 * (size_t)ncomp;
+      if ((e = fail(s, hipMemcpyAsync(rank, tabs.rank.data(), G * 4, hipMemcpyHostToDevice, st)))) return e;
       sp.wg_base = tab + G;
       sp.wg_n = tab + G + ncomp;
       sp.xbuf = reinterpret_cast<unsigned long long*>(na.P);
@@ -519,6 +521,7 @@ int seg_finalize(seg_session* s, void* stream) {
         seg::NmfSplit one = sp;
         one.G = tabs.groups[gi].second;
         one.wg_comp = tab + tabs.groups[gi].first;
+        one.wg_rank = rank + tabs.groups[gi].first;
         le = seg::launch_nmf_split(na, one, gi == 0, st);
         if (le != hipSuccess) break;
       }

@@ -108,7 +108,8 @@ struct NmfSplit {
   size_t lds_bytes;      // dynamic LDS per workgroup
   long long limit;       // wall-clock ticks a meeting may wait
   const int* wg_comp;    // [G] component of each workgroup of the launch
-  const int* wg_base;    // [ncomp] first workgroup of each component within its launch
+  const int* wg_rank;    // [G] its number within the component (its slice and slots)
+  const int* wg_base;    // [ncomp] first slot index of each component within its launch
   const int* wg_n;       // [ncomp] workgroups of each component
   unsigned long long* xbuf;  // [G][2][2 XS] exchange slots: tagged high, then low words
   unsigned* sync;        // [ncomp + 1] abandon flags, error flag
@@ -116,7 +117,7 @@ struct NmfSplit {
 // Host copies of the workgroup tables and the launches (first workgroup in
 // `comp`, workgroup count) of a split plan.
 struct NmfSplitTables {
-  std::vector<int> comp, base, n;
+  std::vector<int> comp, rank, base, n;
   std::vector<std::pair<int, int>> groups;
 };
 // Chooses the slice width (fewest launches of at most one workgroup per
