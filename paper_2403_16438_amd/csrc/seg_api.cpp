@@ -94,8 +94,8 @@ Layout make_layout(const seg_config& c) {
   l.comp = take(M * 4);
   l.scan = take(l.scan_cap * 4);
   l.counters = take(16 * 4);
+  l.coff = take((M + 1) * 4);   // right after the counters: both come back in one copy
   l.pix = take(M * 4);
-  l.coff = take((M + 1) * 4);
   l.cbox = take(l.Ccap * 16);
   l.nmf_P = take(M * K * 8);
   l.nmf_PT = take(M * K * 8);
@@ -449,12 +449,18 @@ int seg_finalize(seg_session* s, void* stream) {
   if ((e = fail(s, seg::launch_finalize_maps(a, st)))) return e;
   if ((e = fail(s, hipEventRecord(s->ev[1], st)))) return e;
   // component count and offsets (the pixel lists stay on the device for the
-  // NMF); the first few thousand offsets come with the count
+  // NMF): the counters and the first few thousand offsets, which follow them
+  // in the workspace, in one copy
   int ncomp = 0;
   std::vector<int> coff(std::min<size_t>(s->M + 1, 4097));
-  if ((e = fail(s, hipMemcpyAsync(&ncomp, a.counters, sizeof(int), hipMemcpyDeviceToHost, st)))) return e;
-  if ((e = fail(s, hipMemcpyAsync(coff.data(), a.coff, coff.size() * 4, hipMemcpyDeviceToHost, st)))) return e;
-  if ((e = fail(s, hipStreamSynchronize(st)))) return e;
+  {
+    const size_t gap = l.coff - l.counters, bytes = gap + coff.size() * 4;
+    std::vector<int> head((bytes + 3) / 4);
+    if ((e = fail(s, hipMemcpyAsync(head.data(), a.counters, bytes, hipMemcpyDeviceToHost, st)))) return e;
+    if ((e = fail(s, hipStreamSynchronize(st)))) return e;
+    ncomp = head[0];
+    std::memcpy(coff.data(), head.data() + gap / 4, coff.size() * 4);
+  }
   if ((size_t)ncomp + 1 > coff.size()) {
     coff.resize((size_t)ncomp + 1);
     if ((e = fail(s, hipMemcpyAsync(coff.data(), a.coff, coff.size() * 4, hipMemcpyDeviceToHost, st)))) return e;
@@ -498,17 +504,18 @@ int seg_finalize(seg_session* s, void* stream) {
     // device while waiting for the rest: one split NMF at a time per process
     static std::mutex split_mutex;
     std::unique_lock<std::mutex> hold(split_mutex, std::defer_lock);
+    std::vector<int> up;   // host tables of the split launch (kept until the stream is synchronised)
     if (split) {
       int* tab = at<int>(s, l.nmf_G);
       const size_t G = tabs.comp.size();
-      if ((e = fail(s, hipMemcpyAsync(tab, tabs.comp.data(), G * 4, hipMemcpyHostToDevice, st)))) return e;
-      if ((e = fail(s, hipMemcpyAsync(tab + G, tabs.base.data(), (size_t)ncomp * 4, hipMemcpyHostToDevice, st))))
-        return e;
-      if ((e = fail(s, hipMemcpyAsync(tab + G + ncomp, tabs.n.data(), (size_t)ncomp * 4, hipMemcpyHostToDevice,
-                                      st))))
-        return e;
+      // the four tables in one upload: comp [G], base [ncomp], n [ncomp], rank [G]
+      up.reserve(2 * G + 2 * (size_t)ncomp);
+      up.insert(up.end(), tabs.comp.begin(), tabs.comp.end());
+      up.insert(up.end(), tabs.base.begin(), tabs.base.end());
+      up.insert(up.end(), tabs.n.begin(), tabs.n.end());
+      up.insert(up.end(), tabs.rank.begin(), tabs.rank.end());
+      if ((e = fail(s, hipMemcpyAsync(tab, up.data(), up.size() * 4, hipMemcpyHostToDevice, st)))) return e;
       int* rank = tab + G + 2 * (size_t)ncomp;
-      if ((e = fail(s, hipMemcpyAsync(rank, tabs.rank.data(), G * 4, hipMemcpyHostToDevice, st)))) return e;
       sp.wg_base = tab + G;
       sp.wg_n = tab + G + ncomp;
       sp.xbuf = reinterpret_cast<unsigned long long*>(na.P);
@@ -545,13 +552,39 @@ int seg_finalize(seg_session* s, void* stream) {
     std::vector<int> N(ncomp);
     std::vector<double> F(npx * seg::kMaxRank), A((size_t)ncomp * seg::kMaxRank * s->Kmax);
     unsigned split_error = 0;
-    if ((e = fail(s, hipMemcpyAsync(N.data(), na.N, ncomp * 4, hipMemcpyDeviceToHost, st)))) return e;
-    if ((e = fail(s, hipMemcpyAsync(pix.data(), dpix, pix.size() * 4, hipMemcpyDeviceToHost, st)))) return e;
-    if ((e = fail(s, hipMemcpyAsync(F.data(), na.F, F.size() * 8, hipMemcpyDeviceToHost, st)))) return e;
-    if ((e = fail(s, hipMemcpyAsync(A.data(), na.A, A.size() * 8, hipMemcpyDeviceToHost, st)))) return e;
-    if (split && (e = fail(s, hipMemcpyAsync(&split_error, sp.sync + ncomp, 4, hipMemcpyDeviceToHost, st))))
-      return e;
-    if ((e = fail(s, hipStreamSynchronize(st)))) return e;
+    // The results (error flag, ranks, pixel lists, F, A) are packed by
+    // device-to-device copies into the P_c area, free after the NMF, and come
+    // back in one copy: each copy into pageable host memory waits for the
+    // device, so five of them cost five round trips.
+    const size_t o_err = 0, o_n = 8, o_pix = seg::align_up(o_n + (size_t)ncomp * 4),
+                 o_f = seg::align_up(o_pix + npx * 4), o_a = o_f + F.size() * 8, packed = o_a + A.size() * 8;
+    if (packed <= (size_t)s->M * s->Kmax * 8) {
+      char* dst = reinterpret_cast<char*>(na.P);
+      hipError_t he = hipSuccess;
+      if (split) he = hipMemcpyAsync(dst + o_err, sp.sync + ncomp, 4, hipMemcpyDeviceToDevice, st);
+      if (he == hipSuccess) he = hipMemcpyAsync(dst + o_n, na.N, (size_t)ncomp * 4, hipMemcpyDeviceToDevice, st);
+      if (he == hipSuccess) he = hipMemcpyAsync(dst + o_pix, dpix, npx * 4, hipMemcpyDeviceToDevice, st);
+      if (he == hipSuccess) he = hipMemcpyAsync(dst + o_f, na.F, F.size() * 8, hipMemcpyDeviceToDevice, st);
+      if (he == hipSuccess) he = hipMemcpyAsync(dst + o_a, na.A, A.size() * 8, hipMemcpyDeviceToDevice, st);
+      std::vector<double> host((packed + 7) / 8);
+      if (he == hipSuccess) he = hipMemcpyAsync(host.data(), dst, packed, hipMemcpyDeviceToHost, st);
+      if (he == hipSuccess) he = hipStreamSynchronize(st);
+      if ((e = fail(s, he))) return e;
+      const char* h = reinterpret_cast<const char*>(host.data());
+      if (split) std::memcpy(&split_error, h + o_err, 4);
+      std::memcpy(N.data(), h + o_n, (size_t)ncomp * 4);
+      std::memcpy(pix.data(), h + o_pix, npx * 4);
+      std::memcpy(F.data(), h + o_f, F.size() * 8);
+      std::memcpy(A.data(), h + o_a, A.size() * 8);
+    } else {
+      if ((e = fail(s, hipMemcpyAsync(N.data(), na.N, ncomp * 4, hipMemcpyDeviceToHost, st)))) return e;
+      if ((e = fail(s, hipMemcpyAsync(pix.data(), dpix, pix.size() * 4, hipMemcpyDeviceToHost, st)))) return e;
+      if ((e = fail(s, hipMemcpyAsync(F.data(), na.F, F.size() * 8, hipMemcpyDeviceToHost, st)))) return e;
+      if ((e = fail(s, hipMemcpyAsync(A.data(), na.A, A.size() * 8, hipMemcpyDeviceToHost, st)))) return e;
+      if (split && (e = fail(s, hipMemcpyAsync(&split_error, sp.sync + ncomp, 4, hipMemcpyDeviceToHost, st))))
+        return e;
+      if ((e = fail(s, hipStreamSynchronize(st)))) return e;
+    }
     if (hold.owns_lock()) hold.unlock();
     if (split_error) return fail(s, hipErrorLaunchTimeOut);  // a wait for a slot was abandoned
     // algorithmic work of the NMF (seg_profile)
