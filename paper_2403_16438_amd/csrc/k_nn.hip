@@ -975,6 +975,202 @@ __global__ __launch_bounds__(256) void k_up2_h(const uint16_t* __restrict__ Wb, 
   }
 }
 
+// The U-Net's first two convolutions in one kernel (inference, 64-column
+// tiles): e1a (2 -> 32 channels, k_conv3_c2's product: depth 9 c + tap in
+// two MFMA steps) is computed on the halo tile of e1b (32 -> 32, with 2 x 2
+// pooling) straight into LDS, so its activations never go to HBM. A
+// workgroup stages the FP32 input (S and T, planar) on an 8 x 68 tile as
+// BF16 pairs, computes e1a on the 6 x 66 halo positions of its 4 x 64 output
+// block (13 blocks of 32 positions over the four waves; zero outside the
+// image, e1b's padding), then runs e1b over both 16-channel halves of that
+// tile as k_conv3_halo does (same weights copy, same order of the sums),
+// with the CONV_POOL epilogue. Every value equals the two-kernel path's.
+constexpr int E1_TR = 8, E1_TC = 68;              // input tile
+constexpr int E1_HR = 6, E1_HC = 66, E1_NP = E1_HR * E1_HC;   // e1b halo positions
+// e1a on the halo tile: 32 channels (64 bytes) per position, the four
+// 16-byte groups of position p rotated by p / 4, so that 16 lanes reading the
+// same group of 16 consecutive positions hit all 64 banks once
+__device__ __forceinline__ int e1_at(int p, int grp) { return p * 32 + 8 * ((grp + (p >> 2)) & 3); }
+__global__ __launch_bounds__(256) void k_conv3_first2(const uint16_t* __restrict__ W1, const float* __restrict__ b1,
+                                                      const float* __restrict__ X, const uint16_t* __restrict__ W2r,
+                                                      const float* __restrict__ b2, uint16_t* __restrict__ Y,
+                                                      uint16_t* __restrict__ Yp, int Bn, int H, int W) {
+  __shared__ uint32_t Xs2[E1_TR * E1_TC];                                   // (S, T) BF16 pairs
+  __shared__ __attribute__((aligned(16))) uint16_t Ws1[32][32 + 8];        // e1a weights [co][k]
+  __shared__ __attribute__((aligned(16))) uint16_t XsE[E1_NP * 32];        // e1a on the halo tile (e1_at)
+  __shared__ __attribute__((aligned(16))) uint16_t Ws2[2][32][9 * HC + 8];  // e1b weights, both chunks
+  __shared__ float Bs[64];                                                  // biases of e1a, e1b
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane >> 5;
+  const int bx = W / 64, by = H / 4;
+  const int blk = blockIdx.x, b = blk / (bx * by), rem = blk - b * bx * by;
+  const int y0 = (rem / bx) * 4, x0 = (rem % bx) * 64;
+  const long long HW = (long long)H * W, cs = (long long)Bn * HW;
+  // every load first (clamped addresses, masked when stored)
+  float v0[3], v1[3];
+  uint32_t in = 0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int e = tid + 256 * j, r = e / E1_TC, cc = e - r * E1_TC, y = y0 + r - 2, x = x0 + cc - 2;
+    in |= (uint32_t)(e < E1_TR * E1_TC && y >= 0 && y < H && x >= 0 && x < W) << j;
+    const float* src = X + (long long)b * HW + (long long)min(max(y, 0), H - 1) * W + min(max(x, 0), W - 1);
+    v0[j] = src[0];
+    v1[j] = src[cs];
+  }
+  uint16_t w1[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int e = tid + 256 * j, co = min(e / 18, 31), k = e - (e / 18) * 18;
+    w1[j] = W1[co * 18 + k];
+  }
+  uint4 w2[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) w2[j] = *reinterpret_cast<const uint4*>(W2r + 8 * min(tid + 256 * j, 2 * 32 * 18 - 1));
+  const float bl = tid < 32 ? b1[tid] : tid < 64 ? b2[tid - 32] : 0.f;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int e = tid + 256 * j;
+    if (e < E1_TR * E1_TC)
+      Xs2[e] = (in >> j & 1u) ? to_bf16(v0[j]) | ((uint32_t)to_bf16(v1[j]) << 16) : 0u;
+  }
+  for (int e = tid; e < 32 * 32; e += 256) Ws1[e >> 5][e & 31] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int e = tid + 256 * j;
+    if (e < 32 * 18) Ws1[e / 18][e - (e / 18) * 18] = w1[j];
+  }
+  // 16-byte group e: chunk e / 576, co (e / 18) % 32, group e % 18
+  auto put_w2 = [&](int e, uint4 v) {
+    if (e < 2 * 32 * 18) *reinterpret_cast<uint4*>(&Ws2[e / 576][(e / 18) % 32][8 * (e % 18)]) = v;
+  };
+  put_w2(tid, w2[0]);
+  put_w2(tid + 256, w2[1]);
+  put_w2(tid + 512, w2[2]);
+  put_w2(tid + 768, w2[3]);
+  put_w2(tid + 1024, w2[4]);
+  if (tid < 64) Bs[tid] = bl;
+  __syncthreads();
+  const int kg = h * 8;
+  // e1a on the halo positions
+  bf16x8 a1[2];
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a1[st][q] = __builtin_bit_cast(__bf16, Ws1[lane & 31][16 * st + kg + q]);
+  float be[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) be[k] = Bs[8 * (k >> 2) + 4 * h + (k & 3)];
+  for (int blk32 = wv; blk32 * 32 < E1_NP; blk32 += 4) {
+    const int p = blk32 * 32 + (lane & 31), pq = min(p, E1_NP - 1), r = pq / E1_HC, cc = pq - r * E1_HC;
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      bf16x8 bb;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = 16 * st + kg + q, c = k / 9, tap = k - 9 * c, ky = tap / 3, kx = tap - 3 * ky;
+        uint16_t v = 0;
+        if (k < 18) {
+          const uint32_t pair = Xs2[(r + ky) * E1_TC + cc + kx];
+          v = (uint16_t)(c ? pair >> 16 : pair);
+        }
+        bb[q] = __builtin_bit_cast(__bf16, v);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[st], bb, acc, 0, 0, 0);
+    }
+    const int y = y0 + r - 1, x = x0 + cc - 1;
+    const bool inside = y >= 0 && y < H && x >= 0 && x < W;
+    uint4 qv[2];
+#pragma unroll
+    for (int gg = 0; gg < 2; ++gg) {
+      uint32_t w4[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i0 = 8 * gg + 2 * k;
+        const uint16_t lo = inside ? to_bf16(fmaxf(acc[i0] + be[i0], 0.f)) : (uint16_t)0;
+        const uint16_t hi = inside ? to_bf16(fmaxf(acc[i0 + 1] + be[i0 + 1], 0.f)) : (uint16_t)0;
+        w4[k] = lo | ((uint32_t)hi << 16);
+      }
+      qv[gg] = gather8(w4[0], w4[1], w4[2], w4[3]);
+    }
+    if (p < E1_NP) {
+#pragma unroll
+      for (int gg = 0; gg < 2; ++gg) *reinterpret_cast<uint4*>(&XsE[e1_at(p, 2 * gg + h)]) = qv[gg];
+    }
+  }
+  __syncthreads();
+  // e1b: wave wv owns rows 2 (wv / 2) + t of column block wv % 2
+  int pr[2], pc[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    pr[t] = 2 * (wv >> 1) + t;
+    pc[t] = (wv & 1) * 32 + (lane & 31);
+  }
+  f32x16 acc[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+#pragma unroll
+  for (int ch = 0; ch < 2; ++ch)
+#pragma unroll
+    for (int kyx = 0; kyx < 9; ++kyx) {
+      const int ky = kyx / 3, kx = kyx - 3 * ky;
+      bf16x8 a;
+      const uint16_t* ap = &Ws2[ch][lane & 31][kyx * HC + kg];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = __builtin_bit_cast(__bf16, ap[q]);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        bf16x8 bb;
+        const uint16_t* bp = &XsE[e1_at((pr[t] + ky) * E1_HC + pc[t] + kx, 2 * ch + h)];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bb[q] = __builtin_bit_cast(__bf16, bp[q]);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[t], 0, 0, 0);
+      }
+    }
+  // epilogue: e1b's bias and ReLU, BF16 activations and their 2 x 2 pooling
+  uint32_t hv[2][8];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i0 = 2 * k, i1 = 2 * k + 1;
+      const float f0 = fmaxf(acc[t][i0] + Bs[32 + 8 * (i0 >> 2) + 4 * h + (i0 & 3)], 0.f);
+      const float f1 = fmaxf(acc[t][i1] + Bs[32 + 8 * (i1 >> 2) + 4 * h + (i1 & 3)], 0.f);
+      hv[t][k] = to_bf16(f0) | ((uint32_t)to_bf16(f1) << 16);
+    }
+  const long long npix = (long long)Bn * HW;
+  const int cw = 8 * h;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const long long pix = (long long)b * HW + (long long)(y0 + pr[t]) * W + x0 + pc[t];
+#pragma unroll
+    for (int gg = 0; gg < 2; ++gg)
+      *reinterpret_cast<uint4*>(Y + cblk(cw + 16 * gg, pix, npix)) =
+          gather8(hv[t][4 * gg], hv[t][4 * gg + 1], hv[t][4 * gg + 2], hv[t][4 * gg + 3]);
+  }
+  uint32_t pw[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t a = hv[0][k], c = hv[1][k], bn = from_pair_lane(a), dn = from_pair_lane(c);
+    pw[k] = max4_bf16((uint16_t)a, (uint16_t)bn, (uint16_t)c, (uint16_t)dn) |
+            ((uint32_t)max4_bf16((uint16_t)(a >> 16), (uint16_t)(bn >> 16), (uint16_t)(c >> 16), (uint16_t)(dn >> 16))
+             << 16);
+  }
+  uint4 pq[2];
+#pragma unroll
+  for (int gg = 0; gg < 2; ++gg) pq[gg] = gather8(pw[4 * gg], pw[4 * gg + 1], pw[4 * gg + 2], pw[4 * gg + 3]);
+  if (!(pc[0] & 1)) {
+    const int h2 = H / 2, w2 = W / 2;
+    const long long pix = ((long long)b * h2 + (y0 + pr[0]) / 2) * w2 + (x0 + pc[0]) / 2, np2 = (long long)Bn * h2 * w2;
+#pragma unroll
+    for (int gg = 0; gg < 2; ++gg) *reinterpret_cast<uint4*>(Yp + cblk(cw + 16 * gg, pix, np2)) = pq[gg];
+  }
+}
+
 // sum the split-K partials in order: C[m][n] (+)= sum_z P[z][m][n]
 __global__ void k_splitk_reduce(const float* __restrict__ P, float* __restrict__ C, long long MN, int Z,
                                 int accumulate) {
@@ -1584,6 +1780,16 @@ bool tconv(const uint16_t* Wb, int Co, const void* X, bool x_bf16, int C, int Ti
   ic.xcd = Tout > 1 && Np % 128 == 0 && tiles % 8 == 0;   // tile order of the kernel's GV_TCONV remap
   hipLaunchKernelGGL((k_gemm_v<32, GV_TCONV>), dim3((unsigned)tiles, 1), dim3(256), 0, st, Wb, (long long)K,
                      nullptr, 0LL, ic, static_cast<float*>(Y), N, Co, (int)N, K, 0, bias, (int)relu);
+  return true;
+}
+
+bool conv3_first2_h(const uint16_t* W1, const float* b1, int Co1, int Ci1, const float* X, const uint16_t* W2r,
+                    const float* b2, int Co2, int Ci2, uint16_t* Y, uint16_t* Yp, int Bn, int H, int W, hipStream_t st) {
+  if (Co1 != 32 || Ci1 != 2 || Co2 != 32 || Ci2 != 32 || H % 4 || W % 64 || !W1 || !b1 || !W2r || !b2 || !X ||
+      ((uintptr_t)W2r & 15) || ((uintptr_t)Y & 15) || ((uintptr_t)Yp & 15) || (long long)Bn * H * W > 0x7fffffffLL)
+    return false;
+  const long long blocks = (long long)Bn * (H / 4) * (W / 64);
+  hipLaunchKernelGGL(k_conv3_first2, dim3((unsigned)blocks), dim3(256), 0, st, W1, b1, X, W2r, b2, Y, Yp, Bn, H, W);
   return true;
 }
 

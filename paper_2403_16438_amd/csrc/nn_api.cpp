@@ -433,8 +433,15 @@ bool forward_infer(seg_nn* n, const uint16_t* frames, const float* stin, int Bn,
   out.prob = prob;
   // the pooling after e1b and e2b and the output layer after d1b run in
   // those convolutions' epilogues
-  const bool ok = n->P[FO].cols == 32 && conv(E1A, unet_in, false, e1a, H, W, CONV_STORE, none) &&
-                  conv(E1B, e1a, true, s1, H, W, CONV_POOL, pool1) &&
+  // the first two convolutions in one kernel where they fit it (summary
+  // U-Net: 2 input channels), else one after the other
+  const bool first2 =
+      conv3_first2_h(wbf(n, E1A), bias(n, E1A), n->P[E1A].rows, n->P[E1A].cols / 9, unet_in,
+                     at<uint16_t>(n, p.wr) + p.wr_off[E1B], bias(n, E1B), n->P[E1B].rows, n->P[E1B].cols / 9, s1, p1,
+                     Bn, H, W, st);
+  const bool ok = n->P[FO].cols == 32 &&
+                  (first2 || (conv(E1A, unet_in, false, e1a, H, W, CONV_STORE, none) &&
+                              conv(E1B, e1a, true, s1, H, W, CONV_POOL, pool1))) &&
                   conv(E2A, p1, true, e2a, H / 2, W / 2, CONV_STORE, none) &&
                   conv(E2B, e2a, true, s2, H / 2, W / 2, CONV_POOL, pool2) &&
                   conv(E3A, p2, true, e3a, H / 4, W / 4, CONV_STORE, none) &&

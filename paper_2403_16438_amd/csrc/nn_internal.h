@@ -76,6 +76,14 @@ bool conv3_h(const uint16_t* Wb, const uint16_t* Wr, const void* X, bool x_bf16,
 // not a multiple of 8 or W, X, Y are not 16-byte aligned.
 bool tconv(const uint16_t* Wb, int Co, const void* X, bool x_bf16, int C, int Tin, int Tout, int KT, int S, int P,
            long long Np, const float* bias, bool relu, void* Y, bool y_bf16, hipStream_t st);
+// The first two 3 x 3 convolutions of the summary U-Net in one pass: e1a
+// (W1 [32][2 9], bias b1, ReLU) on the planar FP32 input X [2][Bn][H][W],
+// kept in LDS, then e1b (W2r: its conv3_reorder copy, bias b2, ReLU) with
+// the 2 x 2 pooling: Y and Yp as conv3_h's CONV_POOL writes them, the same
+// values as conv3_h for e1a then for e1b. False (nothing launched) unless
+// the layers are 2 -> 32 -> 32 channels, H is a multiple of 4 and W of 64.
+bool conv3_first2_h(const uint16_t* W1, const float* b1, int Co1, int Ci1, const float* X, const uint16_t* W2r,
+                    const float* b2, int Co2, int Ci2, uint16_t* Y, uint16_t* Yp, int Bn, int H, int W, hipStream_t st);
 // up_direct on BF16 blocked X and Y, each input pixel read once; false
 // (nothing launched) unless Co is 32 or 64 and Ci 64 or 128.
 bool up2_h(const uint16_t* Wb, const uint16_t* X, const float* bias, uint16_t* Y, int Co, int Ci, int Bn, int h, int w,
