@@ -398,6 +398,14 @@ __device__ __forceinline__ long long cblk(int c, long long pix, long long npix) 
   return ((long long)(c >> 4) * npix + pix) * 16 + (c & 15);
 }
 
+// Tile of this workgroup: the dispatcher deals workgroups to the eight XCDs
+// in turn, so each XCD takes a contiguous run of tiles (vertical neighbours
+// within an image), whose shared halo rows are then read through one L2.
+__device__ __forceinline__ int xcd_tile() {
+  const int T = (int)gridDim.x, x = (int)blockIdx.x;
+  return T % 8 ? x : (x & 7) * (T >> 3) + (x >> 3);
+}
+
 // the value of lane ^ 1 (the neighbouring column of a 32-pixel row block)
 __device__ __forceinline__ uint32_t from_pair_lane(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false);   // quad_perm 1, 0, 3, 2
@@ -457,7 +465,7 @@ __global__ __launch_bounds__(256) void k_conv3_halo(const uint16_t* __restrict__
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = MT == 64 ? wv >> 1 : 0, wn = MT == 64 ? wv & 1 : wv;
   const int bx = (W + BC - 1) / BC, by = (H + BR - 1) / BR;
-  const int blk = blockIdx.x, b = blk / (bx * by), rem = blk - b * bx * by;
+  const int blk = xcd_tile(), b = blk / (bx * by), rem = blk - b * bx * by;
   const int y0 = (rem / bx) * BR, x0 = (rem % bx) * BC;
   const int co0 = blockIdx.y * MT;
   const long long HW = (long long)H * W;
@@ -769,7 +777,7 @@ __global__ __launch_bounds__(256) void k_conv3_c2(const uint16_t* __restrict__ W
   const int BR = NT / BC, TC = BC + 2, TR = BR + 2, np = TR * TC;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int bx = (W + BC - 1) / BC, by = (H + BR - 1) / BR;
-  const int blk = blockIdx.x, b = blk / (bx * by), rem = blk - b * bx * by;
+  const int blk = xcd_tile(), b = blk / (bx * by), rem = blk - b * bx * by;
   const int y0 = (rem / bx) * BR, x0 = (rem % bx) * BC;
   const long long HW = (long long)H * W;
   // halo tile: both channels of each position (zero outside the image),
@@ -1002,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_conv3_first2(const uint16_t* __restrict
   __shared__ float Bs[64];                                                  // biases of e1a, e1b
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = lane >> 5;
   const int bx = W / 64, by = H / 4;
-  const int blk = blockIdx.x, b = blk / (bx * by), rem = blk - b * bx * by;
+  const int blk = xcd_tile(), b = blk / (bx * by), rem = blk - b * bx * by;
   const int y0 = (rem / bx) * 4, x0 = (rem % bx) * 64;
   const long long HW = (long long)H * W, cs = (long long)Bn * HW;
   // every load first (clamped addresses, masked when stored)
