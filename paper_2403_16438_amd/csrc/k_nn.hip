@@ -127,8 +127,8 @@ __global__ __launch_bounds__(256) void k_gemm(const TA* __restrict__ A, long lon
 //             product, plus bias[co], is stored to C at channel co, pixel
 //             (2 y + a, 2 x + e) of an image of 2 H x 2 W (X's pixels H x W),
 //             so the product lands directly in the concatenation buffer;
-//   GV_TCONV  the 1-D temporal im2col of X [C][Tin][Np] (FP32, or BF16 when
-//             tbf16): row k = c KT + tap, column j Np + n holds
+//   GV_TCONV  the 1-D temporal im2col of BF16 X [C][Tin][Np]: row
+//             k = c KT + tap, column j Np + n holds
 //             X[c][j S + tap - P][n] (zero outside 0 .. Tin - 1), what
 //             im2col1 would write, gathered as it is loaded (Np a multiple
 //             of 8, so a group of 8 columns lies in one j); C is stored as
@@ -139,7 +139,7 @@ struct Im2col {
   int Bn, H, W;
   // GV_TCONV
   const void* TX;
-  int tbf16, Tin, KT, S, P, out_h, xcd;
+  int Tin, KT, S, P, out_h, xcd;
   long long Np;
 };
 // bias (may be null) and relu are applied to the stored values (not with
@@ -231,16 +231,7 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
           const int t = py[j] + tap;
           if (t >= 0 && t < ic.Tin) {
             const long long off = ((long long)c * ic.Tin + t) * ic.Np + poff[j];
-            if (ic.tbf16) {
-              v = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(ic.TX) + off);
-            } else {
-              const float4* src = reinterpret_cast<const float4*>(static_cast<const float*>(ic.TX) + off);
-              const float4 lo = src[0], hi = src[1];
-              v = make_uint4(to_bf16(lo.x) | ((uint32_t)to_bf16(lo.y) << 16),
-                             to_bf16(lo.z) | ((uint32_t)to_bf16(lo.w) << 16),
-                             to_bf16(hi.x) | ((uint32_t)to_bf16(hi.y) << 16),
-                             to_bf16(hi.z) | ((uint32_t)to_bf16(hi.w) << 16));
-            }
+            v = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(ic.TX) + off);
           }
         }
         rb[j] = v;
@@ -1476,16 +1467,6 @@ __global__ void k_up_gather(const float* __restrict__ dY, float* __restrict__ dZ
   dZ[i] = dY[(long long)co * Bn * 4 * hw + (long long)n * 4 * hw + (2 * y + a) * (2 * w) + 2 * x + bb];
 }
 
-__global__ void k_copy(const float* __restrict__ s, float* __restrict__ d, long long n) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) d[i] = s[i];
-}
-
-__global__ void k_add(float* __restrict__ d, const float* __restrict__ s, long long n) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) d[i] += s[i];
-}
-
 // sigmoid + binary cross-entropy on logits z with targets y:
 // loss_i = max(z, 0) - z y + log(1 + exp(-|z|)); dz = (sigmoid(z) - y) / n;
 // prob = sigmoid(z); per-block loss partials (summed in order on the host)
@@ -1773,11 +1754,11 @@ bool tconv(const uint16_t* Wb, int Co, const void* X, bool x_bf16, int C, int Ti
            long long Np, const float* bias, bool relu, void* Y, bool y_bf16, hipStream_t st) {
   const long long N = (long long)Tout * Np;
   const int K = C * KT;
-  if (Co > 32 || Np % 8 || N > 0x7fffffffLL || ((uintptr_t)Wb & 15) || ((uintptr_t)X & 15) || ((uintptr_t)Y & 15))
+  if (!x_bf16 || Co > 32 || Np % 8 || N > 0x7fffffffLL || ((uintptr_t)Wb & 15) || ((uintptr_t)X & 15) ||
+      ((uintptr_t)Y & 15))
     return false;
   Im2col ic{};
   ic.TX = X;
-  ic.tbf16 = x_bf16;
   ic.Tin = Tin;
   ic.KT = KT;
   ic.S = S;
@@ -1867,8 +1848,6 @@ void up_scatter(const float* Z, const float* b, float* Y, int Co, int Bn, int h,
 void up_gather(const float* dY, float* dZ, int Co, int Bn, int h, int w, hipStream_t st) {
   L1(k_up_gather, (long long)Co * 4 * Bn * h * w, dY, dZ, Co, Bn, h, w);
 }
-void copy(const float* s, float* d, long long n, hipStream_t st) { L1(k_copy, n, s, d, n); }
-void add(float* d, const float* s, long long n, hipStream_t st) { L1(k_add, n, d, s, n); }
 void bce(const float* z, const float* y, float* dz, float* prob, float* part, long long n, hipStream_t st) {
   L1(k_bce, n, z, y, dz, prob, part, n);
 }

@@ -69,11 +69,11 @@ struct ConvEpi {
 bool conv3_h(const uint16_t* Wb, const uint16_t* Wr, const void* X, bool x_bf16, uint16_t* Y, int Co, int Ci, int Bn,
              int H, int W, const float* bias, bool relu, int mode, const ConvEpi& ep, hipStream_t st);
 // A temporal convolution as one product without an im2col matrix:
-// Y [Co][Tout Np] = W [Co][C KT] (BF16) times the 1-D im2col of
-// X [C][Tin][Np] (FP32, or BF16 when x_bf16) that im2col1 would write, plus
-// bias and ReLU, stored as FP32 or as BF16 (y_bf16); the same MFMA sums as
-// im2col1 + gemm + bias_act. False (nothing launched) when Co > 32, Np is
-// not a multiple of 8 or W, X, Y are not 16-byte aligned.
+// Y [Co][Tout Np] = W [Co][C KT] (BF16) times the 1-D im2col of BF16
+// X [C][Tin][Np] that im2col1 would write (rounded), plus bias and ReLU,
+// stored as FP32 or as BF16 (y_bf16); the same MFMA sums as im2col1 + gemm
+// + bias_act. False (nothing launched) unless x_bf16, Co <= 32, Np is a
+// multiple of 8 and W, X, Y are 16-byte aligned.
 bool tconv(const uint16_t* Wb, int Co, const void* X, bool x_bf16, int C, int Tin, int Tout, int KT, int S, int P,
            long long Np, const float* bias, bool relu, void* Y, bool y_bf16, hipStream_t st);
 // The first two 3 x 3 convolutions of the summary U-Net in one pass: e1a
@@ -111,8 +111,6 @@ void pool(const float* X, float* Y, uint8_t* arg, int CB, int H, int W, hipStrea
 void pool_bwd(const float* dY, const uint8_t* arg, float* dX, int CB, int H, int W, bool acc, hipStream_t st);
 void up_scatter(const float* Z, const float* b, float* Y, int Co, int Bn, int h, int w, hipStream_t st);
 void up_gather(const float* dY, float* dZ, int Co, int Bn, int h, int w, hipStream_t st);
-void copy(const float* s, float* d, long long n, hipStream_t st);
-void add(float* d, const float* s, long long n, hipStream_t st);
 void bce(const float* z, const float* y, float* dz, float* prob, float* part, long long n, hipStream_t st);
 void rmsprop(float* w, const float* g, float* v, uint16_t* wb, long long n, float lr, float rho, float eps,
              hipStream_t st);
