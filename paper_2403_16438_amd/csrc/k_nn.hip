@@ -25,6 +25,17 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// Activations of the BF16 inference path are kept in channel blocks of 16:
+// element (c, b, y, x) of a [C][Bn][H][W] tensor (C a multiple of 16) sits at
+// ((c / 16) Bn H W + (b H + y) W + x) 16 + c % 16, so the 16 channels of one
+// pixel are 32 contiguous bytes. A 16-byte load then brings 8 channels of one
+// position, the depth order of an MFMA operand, where the planar layout took
+// one 2-byte load per channel; a concatenation along channels is still two
+// adjacent ranges of the buffer.
+__device__ __forceinline__ long long cblk(int c, long long pix, long long npix) {
+  return ((long long)(c >> 4) * npix + pix) * 16 + (c & 15);
+}
+
 template <class T>
 __device__ __forceinline__ uint16_t ld_bf16(const T* p, long long i);
 template <>
@@ -132,7 +143,8 @@ __global__ __launch_bounds__(256) void k_gemm(const TA* __restrict__ A, long lon
 //             X[c][j S + tap - P][n] (zero outside 0 .. Tin - 1), what
 //             im2col1 would write, gathered as it is loaded (Np a multiple
 //             of 8, so a group of 8 columns lies in one j); C is stored as
-//             FP32, or as BF16 bits when `out_h`.
+//             FP32, or as BF16 bits when `out_h` (row-major when 1; when 2,
+//             with rows as channels in blocks of 16, see cblk).
 enum { GV_BF16 = 0, GV_IM2COL = 1, GV_UP = 2, GV_TCONV = 3 };
 struct Im2col {
   const float* X;
@@ -306,6 +318,23 @@ __global__ __launch_bounds__(256) void k_gemm_v(const uint16_t* __restrict__ A, 
           Ts[rl][cl] = to_bf16(v);
         }
       __syncthreads();
+      if (ic.out_h == 2) {
+        // channel blocks of 16 (M a multiple of 16, rows = channels, columns
+        // = pixels): a thread gathers the 16 channels of one pixel from the
+        // tile's column and stores them as 32 bytes
+        for (int e = tid; e < (MT / 16) * NT; e += 256) {
+          const int cb = e / NT, cl2 = e - cb * NT, gc = n0 + cl2, c0 = m0 + 16 * cb;
+          uint32_t w[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) w[k] = Ts[16 * cb + 2 * k][cl2] | ((uint32_t)Ts[16 * cb + 2 * k + 1][cl2] << 16);
+          if (c0 < M && gc < N) {
+            uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(C) + cblk(c0, gc, N));
+            dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+            dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+          }
+        }
+        return;
+      }
       for (int e = tid; e < MT * (NT / 8); e += 256) {
         const int rl = e / (NT / 8), c8 = (e - rl * (NT / 8)) * 8, row = m0 + rl, gc = n0 + c8;
         if (row < M && gc < N)
@@ -376,17 +405,6 @@ __global__ void k_conv3_reorder(const uint16_t* __restrict__ Wb, uint16_t* __res
             ch = (int)(i / ((long long)9 * HC * Co));
   const int c = ch * HC + cl;
   Wr[i] = c < Ci ? Wb[(long long)co * Ci * 9 + c * 9 + kyx] : (uint16_t)0;
-}
-
-// Activations of the BF16 inference path are kept in channel blocks of 16:
-// element (c, b, y, x) of a [C][Bn][H][W] tensor (C a multiple of 16) sits at
-// ((c / 16) Bn H W + (b H + y) W + x) 16 + c % 16, so the 16 channels of one
-// pixel are 32 contiguous bytes. A 16-byte load then brings 8 channels of one
-// position, the depth order of an MFMA operand, where the planar layout took
-// one 2-byte load per channel; a concatenation along channels is still two
-// adjacent ranges of the buffer.
-__device__ __forceinline__ long long cblk(int c, long long pix, long long npix) {
-  return ((long long)(c >> 4) * npix + pix) * 16 + (c & 15);
 }
 
 // Tile of this workgroup: the dispatcher deals workgroups to the eight XCDs
@@ -1751,11 +1769,11 @@ bool conv1_out(const uint16_t* Wb, const float* X, const float* bias, float* Y, 
   return true;
 }
 bool tconv(const uint16_t* Wb, int Co, const void* X, bool x_bf16, int C, int Tin, int Tout, int KT, int S, int P,
-           long long Np, const float* bias, bool relu, void* Y, bool y_bf16, hipStream_t st) {
+           long long Np, const float* bias, bool relu, void* Y, int y_bf16, hipStream_t st) {
   const long long N = (long long)Tout * Np;
   const int K = C * KT;
   if (!x_bf16 || Co > 32 || Np % 8 || N > 0x7fffffffLL || ((uintptr_t)Wb & 15) || ((uintptr_t)X & 15) ||
-      ((uintptr_t)Y & 15))
+      ((uintptr_t)Y & 15) || (y_bf16 == 2 && (Co % 16 || Tout != 1)))
     return false;
   Im2col ic{};
   ic.TX = X;
@@ -1773,7 +1791,8 @@ bool tconv(const uint16_t* Wb, int Co, const void* X, bool x_bf16, int C, int Ti
 }
 
 bool conv3_first2_h(const uint16_t* W1, const float* b1, int Co1, int Ci1, const float* X, const uint16_t* W2r,
-                    const float* b2, int Co2, int Ci2, uint16_t* Y, uint16_t* Yp, int Bn, int H, int W, hipStream_t st) {
+                    const float* b2, int Co2, int Ci2, uint16_t* Y, uint16_t* Yp, int Bn, int H, int W,
+                    hipStream_t st) {
   if (Co1 != 32 || Ci1 != 2 || Co2 != 32 || Ci2 != 32 || H % 4 || W % 64 || !W1 || !b1 || !W2r || !b2 || !X ||
       ((uintptr_t)W2r & 15) || ((uintptr_t)Y & 15) || ((uintptr_t)Yp & 15) || (long long)Bn * H * W > 0x7fffffffLL)
     return false;
@@ -1813,8 +1832,8 @@ void col2im3(const float* dcol, float* dX, int C, int Bn, int H, int W, bool acc
 void tnorm(const uint16_t* frames, float* out, int Bn, int L, long long HW, hipStream_t st) {
   L1(k_tnorm, (long long)Bn * HW, frames, out, Bn, L, HW);
 }
-bool tconv1_h(const uint16_t* frames, int L, const uint16_t* Wb, int Co, int KT, const float* bias, uint16_t* a1, int Bn,
-              long long HW, hipStream_t st) {
+bool tconv1_h(const uint16_t* frames, int L, const uint16_t* Wb, int Co, int KT, const float* bias, uint16_t* a1,
+              int Bn, long long HW, hipStream_t st) {
   const long long Np = (long long)Bn * HW;
   if (L != T1_L || Co != 32 || KT != T1_K || Np % 64 || ((uintptr_t)a1 & 15)) return false;
   const long long waves = Np / 64;

@@ -395,24 +395,25 @@ bool forward_infer(seg_nn* n, const uint16_t* frames, const float* stin, int Bn,
     if (x != hipSuccess && e == hipSuccess) e = x;
   };
   float* x0 = at<float>(n, p.x0);
-  const float* unet_in = nullptr;
+  const void* unet_in = nullptr;
+  bool unet_bf16 = false;   // the U-Net's input: FP32 planar, or BF16 in channel blocks
   if (n->st) {
     st_norm(stin, x0, Bn, HW, st);
     unet_in = x0;
   } else {
     // the frame normalisation runs inside the first temporal convolution;
     // the other two gather their im2col as they load it, with bias and ReLU
-    // in the product's epilogue; a1 and a2 are stored as BF16 (their
-    // consumers round them to BF16), a3 as FP32 for the first 3 x 3
-    // convolution's FP32 staging
+    // in the product's epilogue; a1, a2 and a3 are stored as BF16 (their
+    // consumers round them to BF16), a3 in channel blocks for the U-Net
     uint16_t* a1 = at<uint16_t>(n, p.a1);
     uint16_t* a2 = at<uint16_t>(n, p.a2);
-    float* a3 = at<float>(n, p.a3);
+    uint16_t* a3 = at<uint16_t>(n, p.a3);
     if (!(tconv1_h(frames, L, wbf(n, T1), n->P[T1].rows, n->P[T1].cols, bias(n, T1), a1, Bn, HW, st) &&
-          tconv(wbf(n, T2), 32, a1, true, 32, 10, 5, 5, 2, 2, N, bias(n, T2), true, a2, true, st) &&
-          tconv(wbf(n, T3), 32, a2, true, 32, 5, 1, 5, 1, 0, N, bias(n, T3), true, a3, false, st)))
+          tconv(wbf(n, T2), 32, a1, true, 32, 10, 5, 5, 2, 2, N, bias(n, T2), true, a2, 1, st) &&
+          tconv(wbf(n, T3), 32, a2, true, 32, 5, 1, 5, 1, 0, N, bias(n, T3), true, a3, 2, st)))
       return false;
     unet_in = a3;
+    unet_bf16 = true;
   }
   auto h = [&](const Buf& b) { return at<uint16_t>(n, b); };
   auto conv = [&](int id, const void* X, bool x_bf16, uint16_t* Y, int hh, int ww, int mode, const ConvEpi& ep) {
@@ -436,11 +437,12 @@ bool forward_infer(seg_nn* n, const uint16_t* frames, const float* stin, int Bn,
   // the first two convolutions in one kernel where they fit it (summary
   // U-Net: 2 input channels), else one after the other
   const bool first2 =
-      conv3_first2_h(wbf(n, E1A), bias(n, E1A), n->P[E1A].rows, n->P[E1A].cols / 9, unet_in,
+      !unet_bf16 &&
+      conv3_first2_h(wbf(n, E1A), bias(n, E1A), n->P[E1A].rows, n->P[E1A].cols / 9, static_cast<const float*>(unet_in),
                      at<uint16_t>(n, p.wr) + p.wr_off[E1B], bias(n, E1B), n->P[E1B].rows, n->P[E1B].cols / 9, s1, p1,
                      Bn, H, W, st);
   const bool ok = n->P[FO].cols == 32 &&
-                  (first2 || (conv(E1A, unet_in, false, e1a, H, W, CONV_STORE, none) &&
+                  (first2 || (conv(E1A, unet_in, unet_bf16, e1a, H, W, CONV_STORE, none) &&
                               conv(E1B, e1a, true, s1, H, W, CONV_POOL, pool1))) &&
                   conv(E2A, p1, true, e2a, H / 2, W / 2, CONV_STORE, none) &&
                   conv(E2B, e2a, true, s2, H / 2, W / 2, CONV_POOL, pool2) &&

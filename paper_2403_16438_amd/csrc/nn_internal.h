@@ -71,11 +71,12 @@ bool conv3_h(const uint16_t* Wb, const uint16_t* Wr, const void* X, bool x_bf16,
 // A temporal convolution as one product without an im2col matrix:
 // Y [Co][Tout Np] = W [Co][C KT] (BF16) times the 1-D im2col of BF16
 // X [C][Tin][Np] that im2col1 would write (rounded), plus bias and ReLU,
-// stored as FP32 or as BF16 (y_bf16); the same MFMA sums as im2col1 + gemm
-// + bias_act. False (nothing launched) unless x_bf16, Co <= 32, Np is a
-// multiple of 8 and W, X, Y are 16-byte aligned.
+// stored as FP32 (y_bf16 = 0), as BF16 row-major (1) or, with one output
+// sample, as BF16 in channel blocks of 16 (2, Co a multiple of 16); the same
+// MFMA sums as im2col1 + gemm + bias_act. False (nothing launched) unless
+// x_bf16, Co <= 32, Np is a multiple of 8 and W, X, Y are 16-byte aligned.
 bool tconv(const uint16_t* Wb, int Co, const void* X, bool x_bf16, int C, int Tin, int Tout, int KT, int S, int P,
-           long long Np, const float* bias, bool relu, void* Y, bool y_bf16, hipStream_t st);
+           long long Np, const float* bias, bool relu, void* Y, int y_bf16, hipStream_t st);
 // The first two 3 x 3 convolutions of the summary U-Net in one pass: e1a
 // (W1 [32][2 9], bias b1, ReLU) on the planar FP32 input X [2][Bn][H][W],
 // kept in LDS, then e1b (W2r: its conv3_reorder copy, bias b2, ReLU) with
@@ -83,7 +84,8 @@ bool tconv(const uint16_t* Wb, int Co, const void* X, bool x_bf16, int C, int Ti
 // values as conv3_h for e1a then for e1b. False (nothing launched) unless
 // the layers are 2 -> 32 -> 32 channels, H is a multiple of 4 and W of 64.
 bool conv3_first2_h(const uint16_t* W1, const float* b1, int Co1, int Ci1, const float* X, const uint16_t* W2r,
-                    const float* b2, int Co2, int Ci2, uint16_t* Y, uint16_t* Yp, int Bn, int H, int W, hipStream_t st);
+                    const float* b2, int Co2, int Ci2, uint16_t* Y, uint16_t* Yp, int Bn, int H, int W,
+                    hipStream_t st);
 // up_direct on BF16 blocked X and Y, each input pixel read once; false
 // (nothing launched) unless Co is 32 or 64 and Ci 64 or 128.
 bool up2_h(const uint16_t* Wb, const uint16_t* X, const float* bias, uint16_t* Y, int Co, int Ci, int Bn, int h, int w,
@@ -98,8 +100,8 @@ void tnorm(const uint16_t* frames, float* out, int Bn, int L, long long HW, hipS
 // same values as tnorm, im2col1, gemm and bias_act rounded to BF16. False
 // (nothing launched) unless L = 50, Co = 32, KT = 5, Bn HW is a multiple of
 // 64 and a1 is 16-byte aligned.
-bool tconv1_h(const uint16_t* frames, int L, const uint16_t* Wb, int Co, int KT, const float* bias, uint16_t* a1, int Bn,
-              long long HW, hipStream_t st);
+bool tconv1_h(const uint16_t* frames, int L, const uint16_t* Wb, int Co, int KT, const float* bias, uint16_t* a1,
+              int Bn, long long HW, hipStream_t st);
 void im2col1(const float* in, uint16_t* col, int C, int Tin, int Tout, int KT, int S, int P, long long N,
              hipStream_t st);
 void col2im1(const float* dcol, float* din, int C, int Tin, int Tout, int KT, int S, int P, long long N,
