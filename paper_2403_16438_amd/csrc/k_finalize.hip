@@ -357,7 +357,11 @@ __global__ void k_region_accum(FinalizeArgs a, long long n, int* __restrict__ ro
   if (l == (int)g) root[r] = l;
 }
 
-constexpr int HULL_ROWS = kMaxDim;
+// Regions whose bounding box has at most SHORT_ROWS rows (nearly all of them:
+// event regions are a few cell diameters tall) are decided by a kernel whose
+// per-row tables fit in 1.5 KB of LDS, so many blocks share a CU; the others
+// by one sized for the tallest frame (49 KB, three blocks per CU).
+constexpr int SHORT_ROWS = 64;
 
 __device__ __forceinline__ long long cross3(int ou, int ov, int au, int av, int bu, int bv) {
   return (long long)(au - ou) * (bv - ov) - (long long)(av - ov) * (bu - ou);
@@ -365,7 +369,10 @@ __device__ __forceinline__ long long cross3(int ou, int ov, int au, int av, int 
 
 // One 64-thread block per region (grid-stride). Keep decision per Sec. III-D:
 // area bounds, eccentricity of the pixel-centre covariance, solidity against
-// the convex hull of the pixel-square corners.
+// the convex hull of the pixel-square corners. TALL selects the regions of
+// more than SHORT_ROWS rows, else those of at most SHORT_ROWS; HULL_ROWS is
+// the row capacity of the tables.
+template <int HULL_ROWS, bool TALL>
 __global__ __launch_bounds__(64) void k_region_decide(FinalizeArgs a, const int* __restrict__ root) {
   __shared__ int xl[HULL_ROWS], xr[HULL_ROWS];
   __shared__ int sl[2 * HULL_ROWS + 2], sr[2 * HULL_ROWS + 2];  // packed (u << 16) | v
@@ -373,6 +380,8 @@ __global__ __launch_bounds__(64) void k_region_decide(FinalizeArgs a, const int*
   const int nreg = a.counters[1];
   const int lane = threadIdx.x;
   for (int r = blockIdx.x; r < nreg; r += gridDim.x) {
+    // the same for every lane, so the whole block skips the region
+    if ((a.reg_box[4 * r + 3] - a.reg_box[4 * r + 2] + 1 > SHORT_ROWS) != TALL) continue;
     const long long n = a.reg_area[r];
     if (lane == 0) {
       int d = 0;
@@ -614,7 +623,8 @@ hipError_t launch_finalize_maps(const FinalizeArgs& a, hipStream_t st) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_region_zero, dim3(1024), dim3(BS), 0, st, a, root);
   hipLaunchKernelGGL(k_region_accum, dim3(blocks(KM, BS)), dim3(BS), 0, st, a, KM, root);
-  hipLaunchKernelGGL(k_region_decide, dim3(4096), dim3(64), 0, st, a, (const int*)root);
+  hipLaunchKernelGGL((k_region_decide<SHORT_ROWS, false>), dim3(8192), dim3(64), 0, st, a, (const int*)root);
+  hipLaunchKernelGGL((k_region_decide<kMaxDim, true>), dim3(768), dim3(64), 0, st, a, (const int*)root);
   hipLaunchKernelGGL(k_kept, dim3(blocks(a.M, BS), KCH), dim3(BS), 0, st, a);
   hipLaunchKernelGGL(k_aggregate, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a);
   hipLaunchKernelGGL(k_ccl_merge, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a.blab, a.H, a.W, (long long)a.M);

@@ -110,6 +110,47 @@ def test_stage_isolation(c1):
     compare_footprints(s2.footprints(), r["footprints"])
 
 
+def _tall_scene(K=3, H=160, W=128):
+    """Event regions of both row classes of the shape filter: a tall ellipse
+    (69 rows, kept), a tall arch (70 rows, rejected by solidity alone), a tall
+    line (80 rows, rejected by eccentricity), a small disk (kept) and a short
+    bar (rejected by eccentricity); every segment the same."""
+    yy, xx = np.mgrid[0:H, 0:W]
+    m = np.zeros((H, W), bool)
+    m |= ((yy - 40) / 34.0) ** 2 + ((xx - 30) / 14.0) ** 2 <= 1.0
+    m[85:155, 50:56] = True
+    m[85:155, 68:74] = True
+    m[85:91, 56:68] = True
+    m |= (yy - 20) ** 2 + (xx - 100) ** 2 <= 25
+    m[40:42, 88:126] = True
+    m[60:140, 110:113] = True
+    D = np.ones((K, H, W), np.float32)            # sigma = sqrt(2 pi)
+    T = np.where(m, 10.0 * np.sqrt(2.0 * np.pi), 0.0).astype(np.float32)[None].repeat(K, 0)
+    return T, np.zeros_like(T), D
+
+
+def test_tall_regions_shape_filter():
+    """Regions taller than 64 rows take the shape filter's wide-table kernel,
+    shorter ones the compact one; both against the oracle (Sec. III-D)."""
+    T, S, D = _tall_scene()
+    s = Session(160, 128, 150)
+    s.load_summaries(T, S, D)
+    s.finalize()
+    torch.cuda.synchronize()
+    prm = params_from_config(s.cfg)
+    r = oracle_from_summaries(T, D, prm)
+    assert region_margin_ok(r["regions"])
+    reg = {st["area"]: st for st in r["regions"][0]}
+    assert reg[1485]["keep"] and reg[81]["keep"]
+    assert reg[912]["keep_area"] and reg[912]["keep_ecc"] and not reg[912]["keep_sol"]
+    assert not reg[240]["keep_ecc"] and not reg[76]["keep_ecc"]
+    assert np.array_equal(s.image(abi.SEG_IMG_EVENT_COUNT), r["count"])
+    assert np.array_equal(_maps(s, abi.SEG_MAP_B) > 0.5, r["b"])
+    assert np.array_equal(s.image(abi.SEG_IMG_MASK_COUNT), r["nb"])
+    assert np.array_equal(s.image(abi.SEG_IMG_LABELS), r["labels"])
+    assert r["labels"].max() == 2
+
+
 @pytest.mark.parametrize("block", [1, 7, 50, 333])
 def test_blocking_invariance(c1, block):
     video, truth, sess, prm, ref, g = c1
