@@ -181,11 +181,22 @@ __global__ void k_ccl_merge(int* __restrict__ lab, int H, int W, long long n) {
   }
 }
 
+// After the merge the forest no longer changes, except that this kernel
+// points pixels at their roots: any parent value a thread reads, the merged
+// one or the root written here, leads to the same root. So the parents are
+// read with ordinary loads, which the L1 serves when the lanes of a wave walk
+// the same path (neighbouring pixels of a run share it).
 __global__ void k_ccl_flatten(int* __restrict__ lab, long long n) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
-  if (lab[g] < 0) return;
-  lab[g] = uf_find(lab, (int)g);
+  int p = lab[g];
+  if (p < 0) return;
+  int x = (int)g;
+  while (p != x) {
+    x = p;
+    p = lab[x];
+  }
+  lab[g] = x;
 }
 
 // ------------------------------------------------------ compaction of roots
