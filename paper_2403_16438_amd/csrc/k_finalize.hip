@@ -155,11 +155,28 @@ __global__ void k_events(FinalizeArgs a) {
 // ------------------------------------------------- connected components
 
 // lab: [n_img][M] with -1 = background, else a parent index (global).
-__global__ void k_ccl_merge(int* __restrict__ lab, int H, int W, long long n) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  if (lab[g] < 0) return;
-  const long long M = (long long)H * W;
+// The flatten takes four consecutive elements per thread, read with one
+// 16-byte load where all four lie in the array: nearly all of them are
+// background, so most waves are done after a single memory round trip for
+// 256 elements instead of 64. The merge keeps one element per thread: with
+// four, a thread's unions run one after another and the slowest waves get
+// longer (80 -> 111 us over 200 segments of 256x256).
+constexpr int CCL_PER = 4;
+
+__device__ __forceinline__ void load_labels(const int* lab, long long g0, long long n, int v[CCL_PER]) {
+  if (g0 + CCL_PER <= n) {
+    const int4 q = *reinterpret_cast<const int4*>(lab + g0);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < CCL_PER; ++k) v[k] = g0 + k < n ? lab[g0 + k] : -1;
+  }
+}
+
+__device__ __forceinline__ void ccl_link(int* __restrict__ lab, long long g, int W, long long M) {
   const int x = (int)(g % M);
   const int yy = x / W, xx = x - yy * W;
   // neighbours earlier in raster order: W, NW, N, NE. Every foreground pixel
@@ -181,22 +198,34 @@ __global__ void k_ccl_merge(int* __restrict__ lab, int H, int W, long long n) {
   }
 }
 
+__global__ void k_ccl_merge(int* __restrict__ lab, int H, int W, long long n) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  if (lab[g] < 0) return;
+  ccl_link(lab, g, W, (long long)H * W);
+}
+
 // After the merge the forest no longer changes, except that this kernel
 // points pixels at their roots: any parent value a thread reads, the merged
 // one or the root written here, leads to the same root. So the parents are
 // read with ordinary loads, which the L1 serves when the lanes of a wave walk
 // the same path (neighbouring pixels of a run share it).
 __global__ void k_ccl_flatten(int* __restrict__ lab, long long n) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  int p = lab[g];
-  if (p < 0) return;
-  int x = (int)g;
-  while (p != x) {
-    x = p;
-    p = lab[x];
+  const long long g0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * CCL_PER;
+  if (g0 >= n) return;
+  int v[CCL_PER];
+  load_labels(lab, g0, n, v);
+#pragma unroll
+  for (int k = 0; k < CCL_PER; ++k) {
+    int p = v[k];
+    if (p < 0) continue;
+    int x = (int)(g0 + k);
+    while (p != x) {
+      x = p;
+      p = lab[x];
+    }
+    lab[g0 + k] = x;
   }
-  lab[g] = x;
 }
 
 // ------------------------------------------------------ compaction of roots
@@ -629,7 +658,7 @@ hipError_t launch_finalize_maps(const FinalizeArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_pointwise, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a, (const double*)C);
   hipLaunchKernelGGL(k_events, dim3(blocks(a.M, BS), KCH), dim3(BS), 0, st, a);
   hipLaunchKernelGGL(k_ccl_merge, dim3(blocks(KM, BS)), dim3(BS), 0, st, a.lab, a.H, a.W, KM);
-  hipLaunchKernelGGL(k_ccl_flatten, dim3(blocks(KM, BS)), dim3(BS), 0, st, a.lab, KM);
+  hipLaunchKernelGGL(k_ccl_flatten, dim3(blocks((KM + CCL_PER - 1) / CCL_PER, BS)), dim3(BS), 0, st, a.lab, KM);
   hipError_t e = compact_roots(a.lab, KM, a.scan, a.scan_cap, &a.counters[1], a.rid, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_region_zero, dim3(1024), dim3(BS), 0, st, a, root);
@@ -639,7 +668,8 @@ hipError_t launch_finalize_maps(const FinalizeArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_kept, dim3(blocks(a.M, BS), KCH), dim3(BS), 0, st, a);
   hipLaunchKernelGGL(k_aggregate, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a);
   hipLaunchKernelGGL(k_ccl_merge, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a.blab, a.H, a.W, (long long)a.M);
-  hipLaunchKernelGGL(k_ccl_flatten, dim3(blocks(a.M, BS)), dim3(BS), 0, st, a.blab, (long long)a.M);
+  hipLaunchKernelGGL(k_ccl_flatten, dim3(blocks((a.M + CCL_PER - 1) / CCL_PER, BS)), dim3(BS), 0, st, a.blab,
+                     (long long)a.M);
   // component ids reuse the rid array (the per-segment ids are no longer needed)
   e = compact_roots(a.blab, a.M, a.scan, a.scan_cap, &a.counters[0], a.rid, st);
   if (e != hipSuccess) return e;
