@@ -162,6 +162,7 @@ __global__ void k_events(FinalizeArgs a) {
 // four, a thread's unions run one after another and the slowest waves get
 // longer (80 -> 111 us over 200 segments of 256x256).
 constexpr int CCL_PER = 4;
+static_assert(CCL_PER == 4 && PER == 4, "label loads are four wide");
 
 __device__ __forceinline__ void load_labels(const int* lab, long long g0, long long n, int v[CCL_PER]) {
   if (g0 + CCL_PER <= n) {
@@ -262,11 +263,10 @@ constexpr int SCAN_NT = 1024;   // threads of the one-block scan of block sums
 __global__ void k_count_roots(const int* __restrict__ lab, long long n, int* __restrict__ sums) {
   __shared__ int sh[BS / 64];
   const long long base = (long long)blockIdx.x * CHUNK + (long long)threadIdx.x * PER;
+  int v[PER];
+  load_labels(lab, base, n, v);
   int c = 0;
-  for (int k = 0; k < PER; ++k) {
-    const long long g = base + k;
-    if (g < n && lab[g] == (int)g) ++c;
-  }
+  for (int k = 0; k < PER; ++k) c += v[k] == (int)(base + k);
   int total;
   block_exclusive_scan<BS>(c, sh, &total);
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
@@ -292,11 +292,12 @@ __global__ void k_assign_ids(const int* __restrict__ lab, long long n, const int
                              int* __restrict__ id) {
   __shared__ int sh[BS / 64];
   const long long base = (long long)blockIdx.x * CHUNK + (long long)threadIdx.x * PER;
+  int v[PER];
+  load_labels(lab, base, n, v);
   int flags[PER];
   int c = 0;
   for (int k = 0; k < PER; ++k) {
-    const long long g = base + k;
-    flags[k] = (g < n && lab[g] == (int)g);
+    flags[k] = v[k] == (int)(base + k);
     c += flags[k];
   }
   int total;
