@@ -272,23 +272,19 @@ __global__ void k_count_roots(const int* __restrict__ lab, long long n, int* __r
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-// exclusive scan of nb block sums by one block; grand total to *total. Each
-// thread takes a run of consecutive sums, so there is one block scan (two
-// barriers) whatever nb is.
+// exclusive scan of nb block sums by one block; grand total to *total
 __global__ __launch_bounds__(SCAN_NT) void k_scan_sums(int* __restrict__ sums, int nb, int* __restrict__ total) {
   __shared__ int sh[SCAN_NT / 64];
-  const int per = (nb + SCAN_NT - 1) / SCAN_NT;
-  const int i0 = min(nb, (int)threadIdx.x * per), i1 = min(nb, i0 + per);
-  int own = 0;
-  for (int i = i0; i < i1; ++i) own += sums[i];
-  int tot;
-  int run = block_exclusive_scan<SCAN_NT>(own, sh, &tot);
-  for (int i = i0; i < i1; ++i) {
-    const int v = sums[i];
-    sums[i] = run;
-    run += v;
+  int carry = 0;
+  for (int base = 0; base < nb; base += SCAN_NT) {
+    const int i = base + threadIdx.x;
+    const int v = i < nb ? sums[i] : 0;
+    int tot;
+    const int ex = block_exclusive_scan<SCAN_NT>(v, sh, &tot);
+    if (i < nb) sums[i] = carry + ex;
+    carry += tot;
   }
-  if (threadIdx.x == 0) *total = tot;
+  if (threadIdx.x == 0) *total = carry;
 }
 
 // id[g] = rank of root g among all roots (only written at roots)
